@@ -65,6 +65,7 @@ def _load():
                                            C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         lib.oracle_query_pairs.restype = C.c_int
+        lib.oracle_num_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -94,6 +95,11 @@ class _Bound:
         s.act, s.leaky_slope = obj.act, obj.leaky_slope
         s.n_mat, s.has_albedo = obj.n_mat, obj.has_albedo
         self.s = s
+
+
+def num_threads():
+    """Threads the oracle's OpenMP loops run on."""
+    return _load().oracle_num_threads()
 
 
 def query(obj, rays, debug=False, outputs=True):

@@ -38,6 +38,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_RELU 0
 #define OR_LEAKY 1
@@ -383,6 +386,16 @@ static void query_one(const oracle_object *ob, const float *ray, int64_t r, cons
     if (o->nrm) for (int b = 0; b < 3; ++b) o->nrm[r * 3 + b] = (float)n[b];
     if (o->material) o->material[r] = mat;
     if (o->albedo) for (int b = 0; b < 3; ++b) o->albedo[r * 3 + b] = (float)alb[b];
+}
+
+/* Threads the parallel loops use. */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Query n rays against one object; any NULL output array is skipped. */

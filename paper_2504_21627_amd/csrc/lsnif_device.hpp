@@ -1,0 +1,277 @@
+// Device-side steps of an LSNIF query: ray setup, AABB slab test, the voxel
+// walk, boundary points and grid-vertex slots (paper Sec. 3.1, 3.2).
+//
+// Every float32 operation here is written out in the order it is evaluated
+// and compiled without contraction into fused multiply-adds, so that the
+// voxel list, the points and the table slots are a deterministic function of
+// the ray: the same ray gives the same list in every kernel of the library.
+#pragma once
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lsnif {
+
+constexpr int kMaxLevels = 32;
+constexpr int kMaxList = 32;          // H/2 <= 32
+constexpr uint32_t kPrimeY = 2654435761u;   // spatial hash of Mueller et al. 2022, Eq. 4
+constexpr uint32_t kPrimeZ = 805459861u;
+
+// Object geometry and grid description shared by every query kernel.
+struct Geom {
+    float bmin[3];
+    float s[3];               // voxels per object-space unit, (float)V / (bmax - bmin)
+    int32_t V;
+    const uint32_t *occ;      // V^3 occupancy bits, x fastest, LSB first
+    int32_t L, F, log2_T, H;
+    uint32_t dense_mask;      // bit l: level l indexed directly ((R+1)^3 <= T)
+    uint32_t aligned_mask;    // bit l: R % V == 0, only the 4 face corners are read
+    int32_t R[kMaxLevels];
+    float lsc[kMaxLevels];    // (float)R / (float)V
+};
+
+// A ray in voxel space with its slab interval.
+struct VRay {
+    float o[3], d[3], inv[3];
+    uint32_t mov;             // bit a: axis a moves (d != 0 with a finite reciprocal)
+    float ta, tb, tmax;
+    bool valid, cand;
+};
+
+__device__ __forceinline__ float fmin2(float a, float b) { return a < b ? a : b; }
+__device__ __forceinline__ float fmax2(float a, float b) { return a > b ? a : b; }
+
+// Parameter where the line crosses the voxel-space plane x_a = k.
+__device__ __forceinline__ float plane_t(float k, float o, float inv) { return (k - o) * inv; }
+
+__device__ __forceinline__ bool bad(float x) { return !(x == x); }
+__device__ __forceinline__ bool inf_or_nan(float x) { return !(__builtin_fabsf(x) <= 3.402823466e38f); }
+
+// Validity, voxel-space transform and slab test against [0, V]^3.
+__device__ __forceinline__ void setup_ray(const Geom &g, float4 r0, float4 r1, VRay &w)
+{
+    const float in[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+    w.valid = false;
+    w.cand = false;
+    w.mov = 0;
+    w.ta = 0.0f;
+    w.tb = 0.0f;
+    w.tmax = in[7];
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ok = ok && !inf_or_nan(in[i]);
+    ok = ok && !bad(in[6]) && !bad(in[7]);
+    ok = ok && !(in[3] == 0.0f && in[4] == 0.0f && in[5] == 0.0f);
+    ok = ok && !(in[6] > in[7]);
+    if (!ok) return;
+    w.valid = true;
+    const float V = (float)g.V;
+    float t0 = -__builtin_inff(), t1 = __builtin_inff();
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        w.o[a] = (in[a] - g.bmin[a]) * g.s[a];
+        w.d[a] = in[3 + a] * g.s[a];
+        w.inv[a] = 0.0f;
+        if (w.d[a] != 0.0f) {
+            float iv = 1.0f / w.d[a];
+            if (__builtin_fabsf(iv) <= 3.402823466e38f) {
+                w.mov |= 1u << a;
+                w.inv[a] = iv;
+            }
+        }
+        if (w.mov & (1u << a)) {
+            float lo = plane_t(0.0f, w.o[a], w.inv[a]);
+            float hi = plane_t(V, w.o[a], w.inv[a]);
+            t0 = fmax2(t0, fmin2(lo, hi));
+            t1 = fmin2(t1, fmax2(lo, hi));
+        } else {
+            inside = inside && (w.o[a] >= 0.0f && w.o[a] <= V);
+        }
+    }
+    if (!inside || w.mov == 0) return;
+    w.ta = fmax2(t0, in[6]);
+    w.tb = t1;
+    w.cand = w.ta < w.tb;
+}
+
+// Entry and exit parameter of cell k along one moving axis.
+__device__ __forceinline__ void cell_span(const VRay &w, int a, int k, float &en, float &ex)
+{
+    float lo = plane_t((float)k, w.o[a], w.inv[a]);
+    float hi = plane_t((float)(k + 1), w.o[a], w.inv[a]);
+    if (w.d[a] > 0.0f) { en = lo; ex = hi; } else { en = hi; ex = lo; }
+}
+
+// Entry/exit of a cell: the latest axis entry and the earliest axis exit over
+// moving axes, each tie going to the lowest axis.
+__device__ __forceinline__ void cell_interval(const VRay &w, const int c[3], float &tin, float &tout,
+                                              int &ia, int &oa)
+{
+    tin = -__builtin_inff();
+    tout = __builtin_inff();
+    ia = -1;
+    oa = -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (w.mov & (1u << a)) {
+            float en, ex;
+            cell_span(w, a, c[a], en, ex);
+            if (ia < 0 || en > tin) { tin = en; ia = a; }
+            if (oa < 0 || ex < tout) { tout = ex; oa = a; }
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t pack_ijk(const int c[3])
+{
+    return (uint32_t)c[0] | ((uint32_t)c[1] << 10) | ((uint32_t)c[2] << 20);
+}
+__device__ __forceinline__ void unpack_ijk(uint32_t v, int c[3])
+{
+    c[0] = (int)(v & 1023u);
+    c[1] = (int)((v >> 10) & 1023u);
+    c[2] = (int)(v >> 20);
+}
+
+__device__ __forceinline__ bool occupied(const Geom &g, const int c[3])
+{
+    uint32_t V = (uint32_t)g.V;
+    uint32_t bit = (uint32_t)c[0] + V * ((uint32_t)c[1] + V * (uint32_t)c[2]);
+    return (g.occ[bit >> 5] >> (bit & 31u)) & 1u;
+}
+
+// Start cell of the walk: on a moving axis the cell whose [entry, exit)
+// holds ta (a floor guess corrected by at most a few steps), on a still axis
+// the half-open cell of the origin with V mapped to V - 1.
+__device__ __forceinline__ int start_cell(const Geom &g, const VRay &w, int a)
+{
+    const int V = g.V;
+    if (!(w.mov & (1u << a))) {
+        int k = (int)__builtin_floorf(w.o[a]);
+        return k > V - 1 ? V - 1 : k;
+    }
+    float x = w.o[a] + w.ta * w.d[a];
+    x = x < 0.0f ? 0.0f : (x > (float)(V - 1) ? (float)(V - 1) : x);
+    int k = (int)__builtin_floorf(x);
+    const int fwd = w.d[a] > 0.0f ? 1 : -1;
+    for (int it = 0; it < V; ++it) {
+        float en, ex;
+        cell_span(w, a, k, en, ex);
+        int nk;
+        if (en > w.ta) nk = k - fwd;
+        else if (ex <= w.ta) nk = k + fwd;
+        else break;
+        if (nk < 0 || nk >= V) break;
+        k = nk;
+    }
+    return k;
+}
+
+// The voxel walk.  Emits, in order along the ray, the packed coordinates of
+// the first `cap` occupied voxels whose [entry, exit] overlaps [ta, tb] with
+// positive length; list[j * stride] receives voxel j.  Steps the axis of the
+// earliest exit, the lowest axis on ties.
+__device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, uint32_t *list, int stride, int cap)
+{
+    if (!w.cand) return 0;
+    int c[3];
+    float en[3], ex[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        c[a] = start_cell(g, w, a);
+        if (w.mov & (1u << a)) {
+            cell_span(w, a, c[a], en[a], ex[a]);
+        } else {
+            en[a] = -__builtin_inff();
+            ex[a] = __builtin_inff();
+        }
+    }
+    int n = 0;
+    const int V = g.V;
+    for (int it = 0; it < 3 * V; ++it) {
+        float tin = -__builtin_inff(), tout = __builtin_inff();
+        int ia = -1, oa = -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (w.mov & (1u << a)) {
+                if (ia < 0 || en[a] > tin) { tin = en[a]; ia = a; }
+                if (oa < 0 || ex[a] < tout) { tout = ex[a]; oa = a; }
+            }
+        }
+        if (fmin2(tout, w.tb) > fmax2(tin, w.ta) && occupied(g, c)) {
+            list[n * stride] = pack_ijk(c);
+            if (++n == cap) break;
+        }
+        if (tout >= w.tb) break;
+        bool out = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a == oa) {
+                const bool up = w.d[a] > 0.0f;
+                c[a] += up ? 1 : -1;
+                out = c[a] < 0 || c[a] >= V;
+                en[a] = ex[a];
+                ex[a] = plane_t((float)(up ? c[a] + 1 : c[a]), w.o[a], w.inv[a]);
+            }
+        }
+        if (out) break;
+    }
+    return n;
+}
+
+// Boundary point h of a listed voxel: even h = where the line enters the
+// voxel, odd h = where it leaves.  The crossing axis takes the face plane
+// itself; other axes are evaluated on the line and clamped into the voxel.
+// Also returns the crossing axis.
+__device__ __forceinline__ int boundary_point(const VRay &w, uint32_t packed, bool is_exit, float p[3])
+{
+    int c[3];
+    unpack_ijk(packed, c);
+    float tin, tout;
+    int ia, oa;
+    cell_interval(w, c, tin, tout, ia, oa);
+    const float t = is_exit ? tout : tin;
+    const int face = is_exit ? oa : ia;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const float lo = (float)c[b], hi = (float)(c[b] + 1);
+        if (b == face) {
+            const bool upper = (w.d[b] > 0.0f) == is_exit;
+            p[b] = upper ? hi : lo;
+        } else {
+            float v = w.o[b] + t * w.d[b];
+            p[b] = v < lo ? lo : (v > hi ? hi : v);
+        }
+    }
+    return face;
+}
+
+// Cell of level l holding p: base vertex i and fractional weights wt.
+__device__ __forceinline__ void level_cell(const Geom &g, int l, const float p[3], uint32_t i[3], float wt[3])
+{
+    const int R = g.R[l];
+    const float Rf = (float)R;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        float x = p[b] * g.lsc[l];
+        x = x < 0.0f ? 0.0f : (x > Rf ? Rf : x);
+        int k = (int)__builtin_floorf(x);
+        k = k > R - 1 ? R - 1 : k;
+        i[b] = (uint32_t)k;
+        wt[b] = x - (float)k;
+    }
+}
+
+// Table slot of vertex v on level l.
+__device__ __forceinline__ uint32_t vertex_slot(const Geom &g, int l, uint32_t vx, uint32_t vy, uint32_t vz)
+{
+    if ((g.dense_mask >> l) & 1u) {
+        const uint32_t side = (uint32_t)g.R[l] + 1u;
+        return vx + side * (vy + side * vz);
+    }
+    return (vx ^ (vy * kPrimeY) ^ (vz * kPrimeZ)) & ((1u << g.log2_T) - 1u);
+}
+
+}  // namespace lsnif

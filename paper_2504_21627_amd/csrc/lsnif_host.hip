@@ -1,0 +1,432 @@
+// Host runtime of the LSNIF query library: contexts, the HBM-resident object
+// registry, descriptor validation, precision conversion and weight packing,
+// and the query entry points of lsnif.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lsnif_kernels.hpp"
+#include "lsnif_launch.hpp"
+#include "../../include/lsnif.h"
+
+using namespace lsnif;
+
+namespace {
+
+thread_local std::string g_err;
+
+lsnif_status fail(lsnif_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(LSNIF_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t dtype_size(int t) { return t == LSNIF_FP32 ? 4 : (t == LSNIF_FP8_E4M3 ? 1 : 2); }
+
+uint16_t f32_to_f16(float x)
+{
+    _Float16 h = (_Float16)x;   // round to nearest even
+    uint16_t u;
+    memcpy(&u, &h, 2);
+    return u;
+}
+
+uint16_t f32_to_bf16(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);   // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                                             // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+void store_elem(void *dst, size_t i, float v, int dtype)
+{
+    if (dtype == LSNIF_FP32) static_cast<float *>(dst)[i] = v;
+    else if (dtype == LSNIF_FP16) static_cast<uint16_t *>(dst)[i] = f32_to_f16(v);
+    else static_cast<uint16_t *>(dst)[i] = f32_to_bf16(v);
+}
+
+struct Object {
+    Geom geom{};
+    Mlp mlp{};
+    void *d_occ = nullptr, *d_tab = nullptr, *d_w = nullptr;
+    int feat_dtype = 0, mlp_dtype = 0, F = 0, width = 0;
+    uint64_t bytes = 0;
+};
+
+}  // namespace
+
+struct lsnif_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    uint32_t next_id = 1;
+    std::map<uint32_t, Object> objects;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int out_dim_of(const lsnif_object_desc *d) { return 5 + 3 * (d->has_albedo ? 1 : 0) + d->n_mat; }
+
+lsnif_status validate(const lsnif_object_desc *d)
+{
+    if (!d) return fail(LSNIF_E_INVALID, "descriptor is NULL");
+    if (d->V < 1 || d->V > 1024 || (d->V & (d->V - 1)))
+        return fail(LSNIF_E_INVALID, "V = %d must be a power of two in [1, 1024]", d->V);
+    for (int a = 0; a < 3; ++a)
+        if (!(d->aabb_max[a] > d->aabb_min[a]) || !std::isfinite(d->aabb_min[a]) || !std::isfinite(d->aabb_max[a]))
+            return fail(LSNIF_E_INVALID, "empty or non-finite AABB on axis %d", a);
+    if (!d->occupancy) return fail(LSNIF_E_INVALID, "occupancy is NULL");
+    if (d->L < 1 || d->L > kMaxLevels) return fail(LSNIF_E_INVALID, "L = %d not in [1, %d]", d->L, kMaxLevels);
+    if (d->F < 1 || d->F > 4) return fail(LSNIF_E_INVALID, "F = %d not in [1, 4]", d->F);
+    if (d->log2_T < 1 || d->log2_T > 30) return fail(LSNIF_E_INVALID, "log2_T = %d not in [1, 30]", d->log2_T);
+    if (!d->R || !d->tables) return fail(LSNIF_E_INVALID, "R or tables is NULL");
+    for (int l = 0; l < d->L; ++l)
+        if (d->R[l] < 1 || d->R[l] > (1 << 20)) return fail(LSNIF_E_INVALID, "R[%d] = %d out of range", l, d->R[l]);
+    if (d->H < 2 || d->H > 2 * kMaxList || (d->H & 1))
+        return fail(LSNIF_E_INVALID, "H = %d must be even in [2, %d]", d->H, 2 * kMaxList);
+    if (d->n_hidden < 1 || d->n_hidden > 6) return fail(LSNIF_E_INVALID, "n_hidden = %d not in [1, 6]", d->n_hidden);
+    if (d->width < 1) return fail(LSNIF_E_INVALID, "width = %d", d->width);
+    if (d->act != LSNIF_RELU && d->act != LSNIF_LEAKY_RELU) return fail(LSNIF_E_INVALID, "unknown activation %d", d->act);
+    if (d->n_mat < 1) return fail(LSNIF_E_INVALID, "n_mat = %d", d->n_mat);
+    if (out_dim_of(d) > kMaxOut) return fail(LSNIF_E_INVALID, "%d outputs exceed %d", out_dim_of(d), kMaxOut);
+    if (!d->W) return fail(LSNIF_E_INVALID, "W is NULL");
+    for (int k = 0; k <= d->n_hidden; ++k)
+        if (!d->W[k]) return fail(LSNIF_E_INVALID, "W[%d] is NULL", k);
+    if (d->feat_dtype < LSNIF_FP32 || d->feat_dtype > LSNIF_BF16)
+        return fail(LSNIF_E_INVALID, "feat_dtype %d unsupported", d->feat_dtype);
+    if (d->mlp_dtype < LSNIF_FP32 || d->mlp_dtype > LSNIF_FP8_E4M3)
+        return fail(LSNIF_E_INVALID, "mlp_dtype %d unknown", d->mlp_dtype);
+    return LSNIF_OK;
+}
+
+// Kernel support beyond what the ABI allows in general.
+lsnif_status supported(const lsnif_object_desc *d)
+{
+    if (d->F != 2 && d->F != 3) return fail(LSNIF_E_INVALID, "kernels support F = 2 or 3 (got %d)", d->F);
+    if (d->width != 64) return fail(LSNIF_E_INVALID, "kernels support width 64 (got %d)", d->width);
+    if (d->mlp_dtype == LSNIF_FP8_E4M3) return fail(LSNIF_E_INVALID, "FP8 MLP is not available in this build");
+    return LSNIF_OK;
+}
+
+uint64_t algorithmic_bytes(const lsnif_object_desc *d)
+{
+    const uint64_t V = (uint64_t)d->V;
+    const uint64_t vox = (V * V * V + 7) / 8;
+    const uint64_t tab = (uint64_t)d->L * ((uint64_t)1 << d->log2_T) * d->F * dtype_size(d->feat_dtype);
+    const uint64_t in = (uint64_t)d->H * d->L * d->F;
+    const uint64_t w = in * d->width + (uint64_t)(d->n_hidden - 1) * d->width * d->width +
+                       (uint64_t)d->width * out_dim_of(d);
+    return vox + tab + w * dtype_size(d->mlp_dtype);
+}
+
+// float32 path: each layer transposed to [in][out_pad].
+std::vector<float> pack_f32(const lsnif_object_desc *d, int32_t off[8])
+{
+    const int Wd = d->width, in0 = d->H * d->L * d->F, od = out_dim_of(d);
+    std::vector<float> w;
+    off[0] = 0;
+    w.resize((size_t)in0 * Wd);
+    for (int j = 0; j < Wd; ++j)
+        for (int i = 0; i < in0; ++i) w[(size_t)i * Wd + j] = d->W[0][(size_t)j * in0 + i];
+    for (int k = 1; k < d->n_hidden; ++k) {
+        off[k] = (int32_t)w.size();
+        w.resize(w.size() + (size_t)Wd * Wd);
+        float *dst = w.data() + off[k];
+        for (int j = 0; j < Wd; ++j)
+            for (int i = 0; i < Wd; ++i) dst[(size_t)i * Wd + j] = d->W[k][(size_t)j * Wd + i];
+    }
+    off[d->n_hidden] = (int32_t)w.size();
+    w.resize(w.size() + (size_t)Wd * kMaxOut, 0.0f);
+    float *dst = w.data() + off[d->n_hidden];
+    for (int j = 0; j < od; ++j)
+        for (int i = 0; i < Wd; ++i) dst[(size_t)i * kMaxOut + j] = d->W[d->n_hidden][(size_t)j * Wd + i];
+    return w;
+}
+
+// Matrix-core path: A-operand fragments of v_mfma_f32_32x32x16 (8 values per
+// lane, lane l holding row l % 32 and K slots 8 (l / 32) .. +7).
+//  layer 1: fragment ((h * KB + kb) * MB + m) for point h, 16-wide K block kb
+//           of the point's features padded to FP per level, output block m;
+//  later layers: fragment ((mo * MB + m) * 2 + s), K slot 8q + e standing for
+//           input unit 32m + 16s + (e < 4 ? 4q + e : 8 + 4q + e - 4) -- the
+//           order in which the previous layer's accumulators lie.
+std::vector<float> pack_mma(const lsnif_object_desc *d, int32_t off[8], int &KB)
+{
+    const int Wd = d->width, MB = Wd / 32, L = d->L, F = d->F, H = d->H, od = out_dim_of(d);
+    const int FP = F == 3 ? 4 : F;
+    const int in0 = H * L * F;
+    KB = (L * FP + 15) / 16;
+    std::vector<float> w;
+    off[0] = 0;
+    w.assign((size_t)H * KB * MB * 64 * 8, 0.0f);
+    for (int h = 0; h < H; ++h)
+        for (int kb = 0; kb < KB; ++kb)
+            for (int m = 0; m < MB; ++m)
+                for (int lane = 0; lane < 64; ++lane)
+                    for (int e = 0; e < 8; ++e) {
+                        const int k = 16 * kb + 8 * (lane / 32) + e;
+                        const int lvl = k / FP, f = k % FP, out = 32 * m + lane % 32;
+                        if (lvl >= L || f >= F) continue;
+                        const int in = h * L * F + lvl * F + f;
+                        w[((((size_t)h * KB + kb) * MB + m) * 64 + lane) * 8 + e] = d->W[0][(size_t)out * in0 + in];
+                    }
+    for (int k = 1; k <= d->n_hidden; ++k) {
+        const bool head = k == d->n_hidden;
+        const int MO = head ? 1 : MB, rows = head ? od : Wd;
+        off[k] = (int32_t)w.size();
+        w.resize(w.size() + (size_t)MO * MB * 2 * 64 * 8, 0.0f);
+        float *dst = w.data() + off[k];
+        for (int mo = 0; mo < MO; ++mo)
+            for (int m = 0; m < MB; ++m)
+                for (int s = 0; s < 2; ++s)
+                    for (int lane = 0; lane < 64; ++lane)
+                        for (int e = 0; e < 8; ++e) {
+                            const int q = lane / 32, out = 32 * mo + lane % 32;
+                            const int in = 32 * m + 16 * s + (e < 4 ? 4 * q + e : 8 + 4 * q + (e - 4));
+                            if (out >= rows) continue;
+                            dst[((((size_t)mo * MB + m) * 2 + s) * 64 + lane) * 8 + e] = d->W[k][(size_t)out * Wd + in];
+                        }
+    }
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lsnif_version(void) { return 100; }
+
+const char *lsnif_last_error(void) { return g_err.c_str(); }
+
+lsnif_status lsnif_create(const lsnif_ctx_desc *desc, lsnif_ctx **out)
+{
+    if (!out) return fail(LSNIF_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int dev = desc ? desc->device : 0;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (dev < 0 || dev >= n) return fail(LSNIF_E_INVALID, "device %d not in [0, %d)", dev, n);
+    lsnif_ctx *c = new (std::nothrow) lsnif_ctx();
+    if (!c) return fail(LSNIF_E_NOMEM, "host allocation failed");
+    c->device = dev;
+    c->budget = desc ? desc->hbm_budget : 0;
+    *out = c;
+    return LSNIF_OK;
+}
+
+void lsnif_destroy(lsnif_ctx *ctx)
+{
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    for (auto &kv : ctx->objects) {
+        (void)hipFree(kv.second.d_occ);
+        (void)hipFree(kv.second.d_tab);
+        (void)hipFree(kv.second.d_w);
+    }
+    delete ctx;
+}
+
+lsnif_status lsnif_desc_bytes(const lsnif_object_desc *desc, uint64_t *bytes)
+{
+    if (!bytes) return fail(LSNIF_E_INVALID, "bytes is NULL");
+    lsnif_status st = validate(desc);
+    if (st) return st;
+    *bytes = algorithmic_bytes(desc);
+    return LSNIF_OK;
+}
+
+lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *object_id)
+{
+    if (!ctx || !object_id) return fail(LSNIF_E_INVALID, "ctx or object_id is NULL");
+    lsnif_status st = validate(d);
+    if (st) return st;
+    if ((st = supported(d))) return st;
+    DeviceGuard guard(ctx->device);
+    Object ob;
+    ob.feat_dtype = d->feat_dtype;
+    ob.mlp_dtype = d->mlp_dtype;
+    ob.F = d->F;
+    ob.width = d->width;
+    Geom &g = ob.geom;
+    for (int a = 0; a < 3; ++a) {
+        g.bmin[a] = d->aabb_min[a];
+        g.s[a] = (float)d->V / (d->aabb_max[a] - d->aabb_min[a]);
+    }
+    g.V = d->V;
+    g.L = d->L;
+    g.F = d->F;
+    g.log2_T = d->log2_T;
+    g.H = d->H;
+    const uint64_t T = (uint64_t)1 << d->log2_T;
+    for (int l = 0; l < d->L; ++l) {
+        g.R[l] = d->R[l];
+        g.lsc[l] = (float)d->R[l] / (float)d->V;
+        const uint64_t side = (uint64_t)d->R[l] + 1;
+        if (side * side * side <= T) g.dense_mask |= 1u << l;
+        if (d->R[l] % d->V == 0) g.aligned_mask |= 1u << l;
+    }
+    // host-side conversions
+    const uint64_t V = (uint64_t)d->V;
+    const size_t occ_words = (size_t)((V * V * V + 31) / 32);
+    const size_t n_tab = (size_t)d->L * T * d->F;
+    std::vector<uint8_t> tab(n_tab * dtype_size(d->feat_dtype));
+    for (size_t i = 0; i < n_tab; ++i) store_elem(tab.data(), i, d->tables[i], d->feat_dtype);
+    std::vector<float> wf;
+    int KB = 0;
+    if (d->mlp_dtype == LSNIF_FP32) wf = pack_f32(d, ob.mlp.off);
+    else wf = pack_mma(d, ob.mlp.off, KB);
+    const int wdt = d->mlp_dtype == LSNIF_FP32 ? LSNIF_FP32 : d->mlp_dtype;
+    std::vector<uint8_t> wbytes(wf.size() * dtype_size(wdt));
+    for (size_t i = 0; i < wf.size(); ++i) store_elem(wbytes.data(), i, wf[i], wdt);
+    ob.bytes = occ_words * 4 + tab.size() + wbytes.size();
+    if (ctx->budget && ctx->used + ob.bytes > ctx->budget)
+        return fail(LSNIF_E_NOMEM, "object needs %llu bytes, %llu of %llu in use", (unsigned long long)ob.bytes,
+                    (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
+    auto cleanup = [&]() {
+        (void)hipFree(ob.d_occ);
+        (void)hipFree(ob.d_tab);
+        (void)hipFree(ob.d_w);
+    };
+    if (hipMalloc(&ob.d_occ, occ_words * 4) != hipSuccess || hipMalloc(&ob.d_tab, tab.size()) != hipSuccess ||
+        hipMalloc(&ob.d_w, wbytes.size()) != hipSuccess) {
+        cleanup();
+        return fail(LSNIF_E_NOMEM, "device allocation of %llu bytes failed", (unsigned long long)ob.bytes);
+    }
+    if (hipMemcpy(ob.d_occ, d->occupancy, occ_words * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ob.d_tab, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ob.d_w, wbytes.data(), wbytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        cleanup();
+        return fail(LSNIF_E_DEVICE, "copy to device failed");
+    }
+    g.occ = static_cast<const uint32_t *>(ob.d_occ);
+    Mlp &m = ob.mlp;
+    m.W = ob.d_w;
+    m.n_hidden = d->n_hidden;
+    m.out_dim = out_dim_of(d);
+    m.act = d->act;
+    m.slope = d->leaky_slope;
+    m.n_mat = d->n_mat;
+    m.has_albedo = d->has_albedo ? 1 : 0;
+    m.kb_point = KB;
+    m.fp = d->F == 3 ? 4 : d->F;
+    const uint32_t id = ctx->next_id++;
+    ctx->objects[id] = ob;
+    ctx->used += ob.bytes;
+    *object_id = id;
+    return LSNIF_OK;
+}
+
+lsnif_status lsnif_release(lsnif_ctx *ctx, uint32_t object_id)
+{
+    if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
+    auto it = ctx->objects.find(object_id);
+    if (it == ctx->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", object_id);
+    DeviceGuard guard(ctx->device);
+    (void)hipFree(it->second.d_occ);
+    (void)hipFree(it->second.d_tab);
+    (void)hipFree(it->second.d_w);
+    ctx->used -= it->second.bytes;
+    ctx->objects.erase(it);
+    return LSNIF_OK;
+}
+
+lsnif_status lsnif_object_bytes(lsnif_ctx *ctx, uint32_t object_id, uint64_t *bytes)
+{
+    if (!ctx || !bytes) return fail(LSNIF_E_INVALID, "ctx or bytes is NULL");
+    auto it = ctx->objects.find(object_id);
+    if (it == ctx->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", object_id);
+    *bytes = it->second.bytes;
+    return LSNIF_OK;
+}
+
+static lsnif_status run_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
+                              lsnif_hit *d_out, const lsnif_debug_bufs *dbg, void *stream)
+{
+    if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
+    auto it = ctx->objects.find(object_id);
+    if (it == ctx->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", object_id);
+    if (n == 0) return LSNIF_OK;
+    if (!d_rays || !d_out) return fail(LSNIF_E_INVALID, "rays or output is NULL");
+    if (reinterpret_cast<uintptr_t>(d_rays) % 16 || reinterpret_cast<uintptr_t>(d_out) % 4)
+        return fail(LSNIF_E_INVALID, "rays must be 16-byte and hits 4-byte aligned");
+    const Object &ob = it->second;
+    DeviceGuard guard(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    QueryArgs A{};
+    A.g = ob.geom;
+    A.m = ob.mlp;
+    A.tables = ob.d_tab;
+    A.rays = reinterpret_cast<const float4 *>(d_rays);
+    A.hits = d_out;
+    A.n = n;
+    if (dbg) {
+        DebugArgs D{};
+        D.g = ob.geom;
+        D.rays = A.rays;
+        D.n = n;
+        D.b = *dbg;
+        D.b.count = nullptr;
+        D.b.tatb = nullptr;
+        D.b.enc = nullptr;
+        D.b.out = nullptr;
+        HIP_TRY(launch_debug(D, s));
+        A.dbg.count = dbg->count;
+        A.dbg.tatb = dbg->tatb;
+        A.dbg.out = dbg->out;
+        A.dbg.enc = dbg->enc;
+    }
+    if (ob.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, ob.feat_dtype, ob.F, s));
+    else HIP_TRY(launch_mma(A, ob.feat_dtype, ob.mlp_dtype, ob.F, s));
+    return LSNIF_OK;
+}
+
+lsnif_status lsnif_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
+                         lsnif_hit *d_out, void *stream)
+{
+    return run_query(ctx, object_id, d_rays, n, d_out, nullptr, stream);
+}
+
+lsnif_status lsnif_query_debug(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
+                               lsnif_hit *d_out, const lsnif_debug_bufs *dbg, void *stream)
+{
+    if (!dbg) return fail(LSNIF_E_INVALID, "dbg is NULL");
+    return run_query(ctx, object_id, d_rays, n, d_out, dbg, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,266 @@
+"""Parity of the HIP query path (through the C ABI) with the CPU oracle."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.parity import gpu_query, compare_hits
+
+pytestmark = pytest.mark.gpu
+
+U = {"fp32": 2.0 ** -24, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_2504_21627_amd import lsnif
+    return lsnif
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = L.lsnif_create(0)
+    yield c
+    L.lsnif_destroy(c)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return W.configs.c1()
+
+
+@pytest.fixture(scope="module")
+def c2_small():
+    c = W.configs.c2()
+    rays = W.configs.subsample(c["rays"], 12_000, seed=5)
+    return {"objects": c["objects"], "rays": rays, "full": c["rays"]}
+
+
+def bitwise_equal(a, b):
+    return np.array_equal(np.ascontiguousarray(a).view(np.uint8), np.ascontiguousarray(b).view(np.uint8))
+
+
+def check_intermediates(g, o, obj):
+    """Voxel lists, points, slots and weights must equal the oracle's bit for bit."""
+    assert np.array_equal(g["count"], o["count"])
+    cand = o["count"] > 0
+    assert bitwise_equal(g["tatb"][cand], o["tatb"][cand])
+    assert np.array_equal(g["vox_ijk"], o["vox_ijk"])
+    assert np.array_equal(g["vox_axis"], o["vox_axis"])
+    m = o["vox_ijk"][..., 0] >= 0
+    assert bitwise_equal(g["vox_t"][m], o["vox_t"][m])
+    hm = np.arange(obj.H)[None, :] < np.maximum(o["count"], 0)[:, None]
+    assert bitwise_equal(g["points"][hm], o["points"][hm])
+    assert np.array_equal(g["slots"][hm], o["slots"][hm])
+    assert bitwise_equal(g["weights"][hm], o["weights"][hm])
+
+
+def enc_compare(g_enc, o_enc, obj, count, rel):
+    F = obj.F
+    FP = 4 if F == 3 else F
+    n, H, Lv = len(count), obj.H, obj.L
+    ge = g_enc.reshape(n, H, Lv, FP)[..., :F].reshape(n, H * Lv * F)
+    scale = np.abs(o_enc).max()
+    err = np.abs(ge - o_enc).max() / scale
+    assert err <= rel, err
+    return err
+
+
+@pytest.mark.parametrize("feat,mlp", [("fp32", "fp32")])
+def test_c1_fp32_parity(L, ctx, c1, feat, mlp):
+    obj, rays = c1["objects"][0], c1["rays"]
+    _say(f"c1 {feat}/{mlp}: {len(rays)} rays")
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
+    try:
+        g = gpu_query(L, ctx, oid, rays, debug=True, obj=obj)
+        o = oracle.query(obj, rays, debug=True)
+        check_intermediates(g, o, obj)
+        enc_compare(g["enc"], o["enc"], obj, o["count"], 1e-6)
+        cand = o["count"] > 0
+        zerr = np.abs(g["out"][cand] - o["out"][cand]).max() / np.abs(o["out"][cand]).max()
+        assert zerr < 1e-5, zerr
+        st = compare_hits(g, o, o["tatb"], o["enc"], o["out"], obj, U["fp32"], 1e-5, 1e-4, 0.9999)
+        _say(str(st))
+        assert st["ok"], st
+    finally:
+        L.lsnif_release(ctx, oid)
+
+
+@pytest.mark.parametrize("feat,mlp", [("fp16", "fp16"), ("bf16", "bf16"), ("fp32", "fp16")])
+def test_c1_mma_parity(L, ctx, c1, feat, mlp):
+    obj, rays = c1["objects"][0], c1["rays"]
+    _say(f"c1 {feat}/{mlp}: {len(rays)} rays")
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
+    try:
+        g = gpu_query(L, ctx, oid, rays, debug=True, obj=obj)
+        o = oracle.query(obj, rays, debug=True)
+        check_intermediates(g, o, obj)
+        u = max(U[feat], U[mlp])
+        enc_compare(g["enc"], o["enc"], obj, o["count"], 4 * u)
+        st = compare_hits(g, o, o["tatb"], o["enc"], o["out"], obj, u, 1e-3 if mlp == "fp16" else 1e-2,
+                          1e-2 if mlp == "fp16" else 1e-1, 0.999 if mlp == "fp16" else 0.99)
+        _say(str(st))
+        assert st["ok"], st
+    finally:
+        L.lsnif_release(ctx, oid)
+
+
+@pytest.mark.parametrize("feat,mlp", [("fp32", "fp32"), ("fp16", "fp16")])
+def test_c2_subset_parity(L, ctx, c2_small, feat, mlp):
+    obj, rays = c2_small["objects"][0], c2_small["rays"]
+    _say(f"c2 subset {feat}/{mlp}: {len(rays)} rays")
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
+    try:
+        g = gpu_query(L, ctx, oid, rays, debug=True, obj=obj)
+        o = oracle.query(obj, rays, debug=True)
+        check_intermediates(g, o, obj)
+        u = max(U[feat], U[mlp])
+        enc_compare(g["enc"], o["enc"], obj, o["count"], 1e-6 if mlp == "fp32" else 4 * u)
+        st = compare_hits(g, o, o["tatb"], o["enc"], o["out"], obj, u, 1e-5 if mlp == "fp32" else 1e-3,
+                          1e-4 if mlp == "fp32" else 1e-2, 0.9999 if mlp == "fp32" else 0.999)
+        _say(str(st))
+        assert st["ok"], st
+    finally:
+        L.lsnif_release(ctx, oid)
+
+
+@pytest.mark.parametrize("feat,mlp", [("fp32", "fp32"), ("fp16", "fp16")])
+def test_c2_full_size_sampled(L, ctx, c2_small, feat, mlp):
+    """The full 2M-ray batch in one launch; a seeded sample of rays checked against the oracle."""
+    obj, rays = c2_small["objects"][0], c2_small["full"]
+    _say(f"c2 full {feat}/{mlp}: {len(rays)} rays")
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
+    try:
+        g = gpu_query(L, ctx, oid, rays)
+        idx = np.sort(np.random.default_rng(77).choice(len(rays), 6000, replace=False))
+        idx = np.concatenate([idx, [0, len(rays) // 2 - 1, len(rays) // 2, len(rays) - 1]])
+        o = oracle.query(obj, rays[idx], debug=True)
+        gs = {k: v[idx] for k, v in g.items()}
+        u = max(U[feat], U[mlp])
+        st = compare_hits(gs, o, o["tatb"], o["enc"], o["out"], obj, u, 1e-5 if mlp == "fp32" else 1e-3,
+                          1e-4 if mlp == "fp32" else 1e-2, 0.9999 if mlp == "fp32" else 0.999)
+        _say(str(st))
+        assert st["ok"], st
+        # rays outside the sample obey the invariants: a hit has t within its AABB segment
+        h = g["hit"] == 1
+        assert np.all(np.isfinite(g["t"][h])) and np.all(np.isinf(g["t"][~h]))
+        assert np.all(g["material"][~h] == -1)
+    finally:
+        L.lsnif_release(ctx, oid)
+
+
+@pytest.mark.parametrize("mlp", ["fp32", "fp16"])
+def test_edge_cases(L, ctx, c1, mlp):
+    """Empty batch, a single ray, a ragged tail, invalid rays, an empty grid."""
+    import torch
+    obj = c1["objects"][0]
+    feat = "fp32" if mlp == "fp32" else "fp16"
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
+    try:
+        empty = torch.empty((0, 8), dtype=torch.float32, device="cuda")
+        L.lsnif_query(ctx, oid, empty, torch.empty((1, 6), device="cuda"))
+        rays = c1["rays"]
+        for n in (1, 63, 257, 1000):
+            g = gpu_query(L, ctx, oid, rays[:n])
+            full = gpu_query(L, ctx, oid, rays[:1024])
+            for k in ("hit", "t", "normal", "material"):
+                assert bitwise_equal(g[k], full[k][:n]), (n, k)
+        bad = np.array([[np.nan, 0, 0, 1, 0, 0, 0, np.inf], [0, 0, 0, 0, 0, 0, 0, np.inf],
+                        [0, 0, 0, 1, 0, 0, 2, 1], [np.inf, 0, 0, 1, 0, 0, 0, np.inf],
+                        [-3, 0, 0, 1, 0, 0, 0, 0.5]], np.float32)
+        g = gpu_query(L, ctx, oid, bad)
+        assert g["hit"].sum() == 0 and np.all(g["material"] == -1)
+    finally:
+        L.lsnif_release(ctx, oid)
+    empty_obj = W.configs.c1_object()
+    empty_obj.occ = np.zeros_like(empty_obj.occ)
+    oid = L.lsnif_build(ctx, L.ObjectDesc(empty_obj, feat, mlp))
+    try:
+        g = gpu_query(L, ctx, oid, c1["rays"])
+        assert g["hit"].sum() == 0
+    finally:
+        L.lsnif_release(ctx, oid)
+
+
+def test_batch_invariance(L, ctx, c1):
+    """A ray's result does not depend on its neighbours: shuffled batches agree bit for bit."""
+    obj, rays = c1["objects"][0], c1["rays"]
+    for feat, mlp in (("fp32", "fp32"), ("fp16", "fp16")):
+        oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
+        try:
+            a = gpu_query(L, ctx, oid, rays)
+            perm = np.random.default_rng(1).permutation(len(rays))
+            b = gpu_query(L, ctx, oid, rays[perm])
+            inv = np.argsort(perm)
+            for k in ("hit", "t", "normal", "material"):
+                assert bitwise_equal(a[k], b[k][inv]), k
+        finally:
+            L.lsnif_release(ctx, oid)
+
+
+def test_linear_exactness_on_gpu(L, ctx):
+    """A dense level holding A v + b interpolates A x + b on the GPU (float32 rounding)."""
+    from tests.test_oracle_pins import tiny_object, adversarial_rays
+    V, R, F = 8, 12, 2
+    side = R + 1
+    rng = np.random.default_rng(7)
+    A = np.round(rng.uniform(-1, 1, (F, 3)) * 64) / 64
+    b = np.round(rng.uniform(-1, 1, F) * 64) / 64
+    v = np.arange(side ** 3)
+    verts = np.stack([v % side, (v // side) % side, v // (side * side)], 1)
+    tab = np.zeros((1, 1 << 12, F), np.float32)
+    tab[0, : side ** 3] = (verts @ A.T + b).astype(np.float32)
+    occ = np.random.default_rng(8).uniform(size=V ** 3) < 0.5
+    obj = tiny_object(V, occ, L=1, F=F, log2_T=12, R=[R], tables=tab, H=18, width=64, n_hidden=3)
+    rays = adversarial_rays(np.random.default_rng(9), V, 200)
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp32", "fp32"))
+    try:
+        g = gpu_query(L, ctx, oid, rays, debug=True, obj=obj)
+        n = 0
+        for i in range(len(rays)):
+            for h in range(max(g["count"][i], 0)):
+                x = np.clip((g["points"][i, h] * (np.float32(R) / np.float32(V))).astype(np.float32), 0, R)
+                want = A @ x.astype(np.float64) + b
+                got = g["enc"][i, h * F:(h + 1) * F]
+                assert np.allclose(got, want, rtol=0, atol=2e-5 * max(1.0, np.abs(want).max())), (got, want)
+                n += 1
+        assert n > 500
+    finally:
+        L.lsnif_release(ctx, oid)
+
+
+@pytest.mark.parametrize("mlp", ["fp32", "fp16"])
+def test_debug_buffer_subsets(L, ctx, c1, mlp):
+    """Any subset of the debug buffers may be passed; a count-only call matches a full one."""
+    import torch
+    obj, rays_np = c1["objects"][0], c1["rays"]
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, mlp, mlp))
+    try:
+        full = gpu_query(L, ctx, oid, rays_np, debug=True, obj=obj)
+        rays = torch.from_numpy(rays_np).cuda()
+        out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
+        for keys in (("count",), ("tatb",), ("out",), ("count", "out")):
+            bufs = {}
+            if "count" in keys:
+                bufs["count"] = torch.full((len(rays_np),), -7, dtype=torch.int32, device="cuda")
+            if "tatb" in keys:
+                bufs["tatb"] = torch.zeros((len(rays_np), 2), dtype=torch.float32, device="cuda")
+            if "out" in keys:
+                bufs["out"] = torch.zeros((len(rays_np), obj.out_dim), dtype=torch.float32, device="cuda")
+            L.lsnif_query_debug(ctx, oid, rays, out, bufs)
+            torch.cuda.synchronize()
+            for k, v in bufs.items():
+                assert bitwise_equal(v.cpu().numpy(), full[k]), (keys, k)
+    finally:
+        L.lsnif_release(ctx, oid)
