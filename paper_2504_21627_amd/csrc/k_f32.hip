@@ -15,7 +15,7 @@ __global__ __launch_bounds__(kBlock) void k_debug(DebugArgs D)
     VRay w;
     setup_ray(g, D.rays[2 * r], D.rays[2 * r + 1], w);
     const int H = g.H, L = g.L;
-    const int nvox = walk_voxels(g, w, s_list + tid, kBlock, H >> 1);
+    const int nvox = walk_voxels(g, w, g.coarse, s_list + tid, kBlock, H >> 1);
     const int count = 2 * nvox;
     if (D.b.count) D.b.count[r] = w.valid ? count : -1;
     if (D.b.tatb) {
@@ -67,7 +67,8 @@ template <typename TF, int F>
 static void go(const QueryArgs &A, hipStream_t s)
 {
     const dim3 grid((A.n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_query_f32<TF, F, 64>), grid, dim3(kBlock), 0, s, A);
+    const size_t lds = (size_t)(A.g.H >> 1) * kBlock * sizeof(uint32_t);
+    hipLaunchKernelGGL((k_query_f32<TF, F, 64>), grid, dim3(kBlock), lds, s, A);
 }
 
 hipError_t launch_f32(const QueryArgs &A, int feat_dtype, int F, hipStream_t s)

@@ -8,7 +8,8 @@ template <typename TF, typename TM, int F>
 static void go(const QueryArgs &A, hipStream_t s)
 {
     const dim3 grid((A.n + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_query_mma<TF, TM, F, 64>), grid, dim3(kBlock), 0, s, A);
+    const size_t lds = (size_t)(A.g.H >> 1) * kBlock * sizeof(uint32_t);
+    hipLaunchKernelGGL((k_query_mma<TF, TM, F, 64>), grid, dim3(kBlock), lds, s, A);
 }
 
 template <typename TM>

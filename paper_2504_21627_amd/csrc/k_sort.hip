@@ -1,0 +1,172 @@
+// Coherence order of a ray batch: a one-pass counting sort of the rays by a
+// coarse key -- direction octant, then the Morton code of the 32^3 cell of the
+// voxel grid where the ray's segment [ta, tb] starts.  Rays that meet the
+// grid close together and head the same way then share waves, so their
+// walks and their hash-grid gathers touch the same cache lines.  Order within
+// a key is whatever the atomics give; every ray's result is independent of
+// the order the rays are processed in.
+#include "lsnif_kernels.hpp"
+#include "lsnif_launch.hpp"
+
+namespace lsnif {
+
+__device__ __forceinline__ uint32_t spread5(uint32_t x)
+{
+    x &= 31u;
+    x = (x | (x << 8)) & 0x0000f00fu;
+    x = (x | (x << 4)) & 0x000c30c3u;
+    x = (x | (x << 2)) & 0x00249249u;
+    return x;
+}
+
+__device__ __forceinline__ uint32_t coherence_key(const Geom &g, float4 r0, float4 r1)
+{
+    VRay w;
+    setup_ray(g, r0, r1, w);
+    if (!w.cand) return kSortBins - 1;
+    uint32_t cell[3];
+    const float sc = 32.0f / (float)g.V;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float x = (w.o[a] + w.ta * w.d[a]) * sc;
+        x = x < 0.0f ? 0.0f : (x > 31.0f ? 31.0f : x);
+        cell[a] = (uint32_t)x;
+    }
+    const uint32_t oct = (w.d[0] < 0.0f ? 1u : 0u) | (w.d[1] < 0.0f ? 2u : 0u) | (w.d[2] < 0.0f ? 4u : 0u);
+    return (oct << 15) | spread5(cell[0]) | (spread5(cell[1]) << 1) | (spread5(cell[2]) << 2);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(uint32_t *p, uint32_t n, uint32_t v)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Lanes of a wave that share a key are served by one atomic on that key's
+// counter (issued by the lowest such lane); returns the counter's old value
+// plus this lane's rank among the lanes with its key, so equal keys of one
+// wave never contend for the same address.
+__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t *ctr, uint32_t key, bool active)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    uint64_t todo = __ballot(active);
+    uint32_t old = 0, leader = lane;
+    uint64_t mine = 0;
+    while (todo) {
+        const uint32_t l = (uint32_t)__builtin_ctzll(todo);
+        const uint32_t k = __shfl(key, l, 64);
+        const uint64_t same = __ballot(active && key == k);
+        if (active && key == k) {
+            leader = l;
+            mine = same;
+        }
+        if (lane == l) old = atomicAdd(&ctr[k], (uint32_t)__builtin_popcountll(same));
+        todo &= ~same;
+    }
+    const uint32_t base = __shfl(old, leader, 64);
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    return base + (uint32_t)__builtin_popcountll(mine & below);
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_keys(Geom g, const float4 *rays, uint32_t n, uint32_t *keys,
+                                                      uint32_t *hist)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const bool live = i < n;
+    uint32_t k = 0;
+    if (live) {
+        k = coherence_key(g, rays[2 * i], rays[2 * i + 1]);
+        keys[i] = k;
+    }
+    (void)wave_aggregated_add(hist, k, live);
+}
+
+// Exclusive scan of the kSortBins counters in two passes: block b first sums
+// counters [1024 b, 1024 b + 1024), then rescans them with the sum of the
+// blocks before it as the carry-in.
+constexpr uint32_t kScanChunk = 1024;
+constexpr uint32_t kScanBlocks = (kSortBins + kScanChunk - 1) / kScanChunk;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp, uint32_t &total)
+{
+    // 256 threads: inclusive scan in LDS (Hillis-Steele), then exclusive value
+    const uint32_t t = threadIdx.x;
+    tmp[t] = v;
+    __syncthreads();
+    for (uint32_t off = 1; off < kBlock; off <<= 1) {
+        const uint32_t u = t >= off ? tmp[t - off] : 0u;
+        __syncthreads();
+        tmp[t] += u;
+        __syncthreads();
+    }
+    total = tmp[kBlock - 1];
+    const uint32_t incl = tmp[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_partial(const uint32_t *hist, uint32_t *part)
+{
+    __shared__ uint32_t tmp[kBlock];
+    const uint32_t b0 = blockIdx.x * kScanChunk;
+    uint32_t v = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kScanChunk / kBlock; ++q) {
+        const uint32_t i = b0 + q * kBlock + threadIdx.x;
+        if (i < kSortBins) v += hist[i];
+    }
+    uint32_t total;
+    (void)block_exclusive_scan(v, tmp, total);
+    if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t *hist, const uint32_t *part)
+{
+    __shared__ uint32_t tmp[kBlock];
+    const uint32_t t = threadIdx.x;
+    // carry-in: sum of the partial sums of the blocks before this one
+    uint32_t c = 0;
+    for (uint32_t j = t; j < blockIdx.x; j += kBlock) c += part[j];
+    uint32_t carry;
+    (void)block_exclusive_scan(c, tmp, carry);
+    // each thread scans 4 consecutive counters
+    const uint32_t i0 = blockIdx.x * kScanChunk + 4 * t;
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        v[q] = i0 + q < kSortBins ? hist[i0 + q] : 0u;
+        sum += v[q];
+    }
+    uint32_t total;
+    uint32_t run = carry + block_exclusive_scan(sum, tmp, total);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (i0 + q < kSortBins) hist[i0 + q] = run;
+        run += v[q];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint32_t *keys, uint32_t n, uint32_t *cursor,
+                                                         uint32_t *order)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const bool live = i < n;
+    const uint32_t k = live ? keys[i] : 0u;
+    const uint32_t pos = wave_aggregated_add(cursor, k, live);
+    if (live) order[pos] = i;
+}
+
+hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *keys, uint32_t *hist,
+                                 uint32_t *order, hipStream_t s)
+{
+    const dim3 gb((kSortBins + kBlock - 1) / kBlock), gr((n + kBlock - 1) / kBlock);
+    uint32_t *part = hist + kSortBins;
+    hipLaunchKernelGGL(k_fill, gb, dim3(kBlock), 0, s, hist, (uint32_t)kSortBins, 0u);
+    hipLaunchKernelGGL(k_sort_keys, gr, dim3(kBlock), 0, s, g, rays, n, keys, hist);
+    hipLaunchKernelGGL(k_scan_partial, dim3(kScanBlocks), dim3(kBlock), 0, s, hist, part);
+    hipLaunchKernelGGL(k_scan_final, dim3(kScanBlocks), dim3(kBlock), 0, s, hist, part);
+    hipLaunchKernelGGL(k_sort_scatter, gr, dim3(kBlock), 0, s, keys, n, hist, order);
+    return hipGetLastError();
+}
+
+}  // namespace lsnif

@@ -15,20 +15,34 @@ namespace lsnif {
 
 constexpr int kMaxLevels = 32;
 constexpr int kMaxList = 32;          // H/2 <= 32
+constexpr int kCoarseLdsWords = 2048; // brick bits staged in LDS when the grid has <= 65536 bricks
 constexpr uint32_t kPrimeY = 2654435761u;   // spatial hash of Mueller et al. 2022, Eq. 4
 constexpr uint32_t kPrimeZ = 805459861u;
 
 // Object geometry and grid description shared by every query kernel.
+//
+// Occupancy is held as 4x4x4 bricks: `fine` has one 64-bit mask per brick
+// (bit (x&3) + 4 (y&3) + 16 (z&3)), brick (x>>2) + NB ((y>>2) + NB (z>>2)),
+// and `coarse` one bit per brick telling whether its mask is non-zero.
+//
+// A level's table slot of vertex v is (vx + my vy + mz vz) & dmask when the
+// level is indexed directly (my = R+1, mz = (R+1)^2, dmask = ~0, hmask = 0)
+// and (vx ^ my vy ^ mz vz) & hmask when it is hashed (my, mz = the primes,
+// dmask = 0, hmask = T-1); the kernels combine both forms without branching.
 struct Geom {
     float bmin[3];
     float s[3];               // voxels per object-space unit, (float)V / (bmax - bmin)
     int32_t V;
-    const uint32_t *occ;      // V^3 occupancy bits, x fastest, LSB first
+    int32_t NB;               // bricks per axis, ceil(V / 4)
+    const uint64_t *fine;
+    const uint32_t *coarse;
+    int32_t coarse_words;     // uint32 words of `coarse`
     int32_t L, F, log2_T, H;
     uint32_t dense_mask;      // bit l: level l indexed directly ((R+1)^3 <= T)
-    uint32_t aligned_mask;    // bit l: R % V == 0, only the 4 face corners are read
+    uint32_t aligned_mask;    // bit l: R % V == 0, the crossing-axis weight is 0 or 1
     int32_t R[kMaxLevels];
     float lsc[kMaxLevels];    // (float)R / (float)V
+    uint32_t my[kMaxLevels], mz[kMaxLevels], dmask[kMaxLevels], hmask[kMaxLevels];
 };
 
 // A ray in voxel space with its slab interval.
@@ -135,11 +149,15 @@ __device__ __forceinline__ void unpack_ijk(uint32_t v, int c[3])
     c[2] = (int)(v >> 20);
 }
 
-__device__ __forceinline__ bool occupied(const Geom &g, const int c[3])
+__device__ __forceinline__ uint32_t brick_of(const Geom &g, const int c[3])
 {
-    uint32_t V = (uint32_t)g.V;
-    uint32_t bit = (uint32_t)c[0] + V * ((uint32_t)c[1] + V * (uint32_t)c[2]);
-    return (g.occ[bit >> 5] >> (bit & 31u)) & 1u;
+    const uint32_t NB = (uint32_t)g.NB;
+    return ((uint32_t)c[0] >> 2) + NB * (((uint32_t)c[1] >> 2) + NB * ((uint32_t)c[2] >> 2));
+}
+
+__device__ __forceinline__ uint32_t bit_in_brick(const int c[3])
+{
+    return ((uint32_t)c[0] & 3u) + 4u * ((uint32_t)c[1] & 3u) + 16u * ((uint32_t)c[2] & 3u);
 }
 
 // Start cell of the walk: on a moving axis the cell whose [entry, exit)
@@ -172,8 +190,11 @@ __device__ __forceinline__ int start_cell(const Geom &g, const VRay &w, int a)
 // The voxel walk.  Emits, in order along the ray, the packed coordinates of
 // the first `cap` occupied voxels whose [entry, exit] overlaps [ta, tb] with
 // positive length; list[j * stride] receives voxel j.  Steps the axis of the
-// earliest exit, the lowest axis on ties.
-__device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, uint32_t *list, int stride, int cap)
+// earliest exit, the lowest axis on ties.  Occupancy is read a brick at a
+// time: the coarse bit (from `coarse`, LDS or global) and, for a non-empty
+// brick, its 64-bit mask, loaded once on entering the brick.
+__device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, const uint32_t *coarse,
+                                           uint32_t *list, int stride, int cap)
 {
     if (!w.cand) return 0;
     int c[3];
@@ -190,6 +211,8 @@ __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, uint32_
     }
     int n = 0;
     const int V = g.V;
+    uint32_t cur = 0xffffffffu;
+    uint64_t mask = 0;
     for (int it = 0; it < 3 * V; ++it) {
         float tin = -__builtin_inff(), tout = __builtin_inff();
         int ia = -1, oa = -1;
@@ -200,9 +223,16 @@ __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, uint32_
                 if (oa < 0 || ex[a] < tout) { tout = ex[a]; oa = a; }
             }
         }
-        if (fmin2(tout, w.tb) > fmax2(tin, w.ta) && occupied(g, c)) {
-            list[n * stride] = pack_ijk(c);
-            if (++n == cap) break;
+        if (fmin2(tout, w.tb) > fmax2(tin, w.ta)) {
+            const uint32_t b = brick_of(g, c);
+            if (b != cur) {
+                cur = b;
+                mask = ((coarse[b >> 5] >> (b & 31u)) & 1u) ? g.fine[b] : 0ull;
+            }
+            if ((mask >> bit_in_brick(c)) & 1ull) {
+                list[n * stride] = pack_ijk(c);
+                if (++n == cap) break;
+            }
         }
         if (tout >= w.tb) break;
         bool out = false;
@@ -267,11 +297,8 @@ __device__ __forceinline__ void level_cell(const Geom &g, int l, const float p[3
 // Table slot of vertex v on level l.
 __device__ __forceinline__ uint32_t vertex_slot(const Geom &g, int l, uint32_t vx, uint32_t vy, uint32_t vz)
 {
-    if ((g.dense_mask >> l) & 1u) {
-        const uint32_t side = (uint32_t)g.R[l] + 1u;
-        return vx + side * (vy + side * vz);
-    }
-    return (vx ^ (vy * kPrimeY) ^ (vz * kPrimeZ)) & ((1u << g.log2_T) - 1u);
+    const uint32_t y = vy * g.my[l], z = vz * g.mz[l];
+    return ((vx + y + z) & g.dmask[l]) | ((vx ^ y ^ z) & g.hmask[l]);
 }
 
 }  // namespace lsnif

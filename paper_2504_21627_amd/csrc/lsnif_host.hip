@@ -70,7 +70,7 @@ void store_elem(void *dst, size_t i, float v, int dtype)
 struct Object {
     Geom geom{};
     Mlp mlp{};
-    void *d_occ = nullptr, *d_tab = nullptr, *d_w = nullptr;
+    void *d_occ = nullptr, *d_tab = nullptr, *d_w = nullptr;   // d_occ: brick masks, then brick bits
     int feat_dtype = 0, mlp_dtype = 0, F = 0, width = 0;
     uint64_t bytes = 0;
 };
@@ -83,6 +83,9 @@ struct lsnif_ctx {
     uint64_t used = 0;
     uint32_t next_id = 1;
     std::map<uint32_t, Object> objects;
+    // query workspace (coherence-sort keys, order and bin counters); grown on demand
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
 };
 
 namespace {
@@ -259,6 +262,7 @@ void lsnif_destroy(lsnif_ctx *ctx)
         (void)hipFree(kv.second.d_tab);
         (void)hipFree(kv.second.d_w);
     }
+    (void)hipFree(ctx->ws);
     delete ctx;
 }
 
@@ -298,12 +302,39 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
         g.R[l] = d->R[l];
         g.lsc[l] = (float)d->R[l] / (float)d->V;
         const uint64_t side = (uint64_t)d->R[l] + 1;
-        if (side * side * side <= T) g.dense_mask |= 1u << l;
+        if (side * side * side <= T) {
+            g.dense_mask |= 1u << l;
+            g.my[l] = (uint32_t)side;
+            g.mz[l] = (uint32_t)(side * side);
+            g.dmask[l] = 0xffffffffu;
+            g.hmask[l] = 0u;
+        } else {
+            g.my[l] = kPrimeY;
+            g.mz[l] = kPrimeZ;
+            g.dmask[l] = 0u;
+            g.hmask[l] = (uint32_t)(T - 1);
+        }
         if (d->R[l] % d->V == 0) g.aligned_mask |= 1u << l;
     }
+    // occupancy as 4x4x4 bricks: one 64-bit mask per brick, then one bit per brick
+    const int V = d->V, NB = (V + 3) / 4;
+    const size_t nbricks = (size_t)NB * NB * NB;
+    const size_t coarse_words = (nbricks + 31) / 32;
+    std::vector<uint64_t> occ_dev(nbricks + (coarse_words + 1) / 2, 0ull);
+    uint32_t *coarse = reinterpret_cast<uint32_t *>(occ_dev.data() + nbricks);
+    for (int z = 0; z < V; ++z)
+        for (int y = 0; y < V; ++y)
+            for (int x = 0; x < V; ++x) {
+                const uint64_t bit = (uint64_t)x + (uint64_t)V * ((uint64_t)y + (uint64_t)V * (uint64_t)z);
+                if (!((d->occupancy[bit >> 5] >> (bit & 31)) & 1u)) continue;
+                const size_t b = (size_t)(x >> 2) + (size_t)NB * ((size_t)(y >> 2) + (size_t)NB * (size_t)(z >> 2));
+                occ_dev[b] |= 1ull << ((x & 3) + 4 * (y & 3) + 16 * (z & 3));
+                coarse[b >> 5] |= 1u << (b & 31);
+            }
+    g.NB = NB;
+    g.coarse_words = (int32_t)coarse_words;
+    const size_t occ_bytes = occ_dev.size() * sizeof(uint64_t);
     // host-side conversions
-    const uint64_t V = (uint64_t)d->V;
-    const size_t occ_words = (size_t)((V * V * V + 31) / 32);
     const size_t n_tab = (size_t)d->L * T * d->F;
     std::vector<uint8_t> tab(n_tab * dtype_size(d->feat_dtype));
     for (size_t i = 0; i < n_tab; ++i) store_elem(tab.data(), i, d->tables[i], d->feat_dtype);
@@ -314,7 +345,7 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
     const int wdt = d->mlp_dtype == LSNIF_FP32 ? LSNIF_FP32 : d->mlp_dtype;
     std::vector<uint8_t> wbytes(wf.size() * dtype_size(wdt));
     for (size_t i = 0; i < wf.size(); ++i) store_elem(wbytes.data(), i, wf[i], wdt);
-    ob.bytes = occ_words * 4 + tab.size() + wbytes.size();
+    ob.bytes = occ_bytes + tab.size() + wbytes.size();
     if (ctx->budget && ctx->used + ob.bytes > ctx->budget)
         return fail(LSNIF_E_NOMEM, "object needs %llu bytes, %llu of %llu in use", (unsigned long long)ob.bytes,
                     (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
@@ -323,18 +354,19 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
         (void)hipFree(ob.d_tab);
         (void)hipFree(ob.d_w);
     };
-    if (hipMalloc(&ob.d_occ, occ_words * 4) != hipSuccess || hipMalloc(&ob.d_tab, tab.size()) != hipSuccess ||
+    if (hipMalloc(&ob.d_occ, occ_bytes) != hipSuccess || hipMalloc(&ob.d_tab, tab.size()) != hipSuccess ||
         hipMalloc(&ob.d_w, wbytes.size()) != hipSuccess) {
         cleanup();
         return fail(LSNIF_E_NOMEM, "device allocation of %llu bytes failed", (unsigned long long)ob.bytes);
     }
-    if (hipMemcpy(ob.d_occ, d->occupancy, occ_words * 4, hipMemcpyHostToDevice) != hipSuccess ||
+    if (hipMemcpy(ob.d_occ, occ_dev.data(), occ_bytes, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(ob.d_tab, tab.data(), tab.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(ob.d_w, wbytes.data(), wbytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
         cleanup();
         return fail(LSNIF_E_DEVICE, "copy to device failed");
     }
-    g.occ = static_cast<const uint32_t *>(ob.d_occ);
+    g.fine = static_cast<const uint64_t *>(ob.d_occ);
+    g.coarse = reinterpret_cast<const uint32_t *>(g.fine + nbricks);
     Mlp &m = ob.mlp;
     m.W = ob.d_w;
     m.n_hidden = d->n_hidden;
@@ -375,6 +407,22 @@ lsnif_status lsnif_object_bytes(lsnif_ctx *ctx, uint32_t object_id, uint64_t *by
     return LSNIF_OK;
 }
 
+// Batches below this size are processed in the order given.
+constexpr uint32_t kSortMin = 8192;
+
+static lsnif_status ensure_workspace(lsnif_ctx *ctx, uint32_t n)
+{
+    const size_t need = ((size_t)2 * n + kSortBins + kSortScanBlocks) * sizeof(uint32_t);
+    if (need <= ctx->ws_bytes) return LSNIF_OK;
+    (void)hipFree(ctx->ws);   // waits for work that may still use the old buffer
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    if (hipMalloc(&ctx->ws, need) != hipSuccess)
+        return fail(LSNIF_E_NOMEM, "workspace of %llu bytes", (unsigned long long)need);
+    ctx->ws_bytes = need;
+    return LSNIF_OK;
+}
+
 static lsnif_status run_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
                               lsnif_hit *d_out, const lsnif_debug_bufs *dbg, void *stream)
 {
@@ -410,6 +458,15 @@ static lsnif_status run_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ra
         A.dbg.tatb = dbg->tatb;
         A.dbg.out = dbg->out;
         A.dbg.enc = dbg->enc;
+    }
+    if (n >= kSortMin) {
+        lsnif_status st = ensure_workspace(ctx, n);
+        if (st) return st;
+        uint32_t *keys = static_cast<uint32_t *>(ctx->ws);
+        uint32_t *order = keys + n;
+        uint32_t *hist = order + n;
+        HIP_TRY(launch_coherence_sort(ob.geom, A.rays, n, keys, hist, order, s));
+        A.order = order;
     }
     if (ob.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, ob.feat_dtype, ob.F, s));
     else HIP_TRY(launch_mma(A, ob.feat_dtype, ob.mlp_dtype, ob.F, s));

@@ -16,6 +16,7 @@
 #include <stdint.h>
 
 #include "lsnif_device.hpp"
+#include "lsnif_launch.hpp"
 #include "../../include/lsnif.h"
 
 namespace lsnif {
@@ -50,6 +51,7 @@ struct QueryArgs {
     const float4 *rays;
     lsnif_hit *hits;
     uint32_t n;
+    const uint32_t *order;    // processing order of the rays (coherence sort), or NULL
     Dbg dbg;
 };
 
@@ -58,98 +60,131 @@ template <> __device__ __forceinline__ float to_f32<float>(float v) { return v; 
 template <> __device__ __forceinline__ float to_f32<_Float16>(_Float16 v) { return (float)v; }
 template <> __device__ __forceinline__ float to_f32<__bf16>(__bf16 v) { return (float)v; }
 
-// F features of table slot `slot`.
-template <typename TF, int F>
-__device__ __forceinline__ void load_entry(const TF *__restrict__ base, uint32_t slot, float v[F])
+template <typename TF> __device__ __forceinline__ float lo16(uint32_t x)
 {
-    const TF *p = base + (size_t)slot * F;
-    if constexpr (F == 2 && sizeof(TF) == 4) {
-        float2 x = *reinterpret_cast<const float2 *>(p);
-        v[0] = x.x;
-        v[1] = x.y;
-    } else if constexpr (F == 2 && sizeof(TF) == 2) {
-        uint32_t x = *reinterpret_cast<const uint32_t *>(p);
-        TF lo, hi;
-        uint16_t l16 = (uint16_t)(x & 0xffffu), h16 = (uint16_t)(x >> 16);
-        __builtin_memcpy(&lo, &l16, 2);
-        __builtin_memcpy(&hi, &h16, 2);
-        v[0] = to_f32<TF>(lo);
-        v[1] = to_f32<TF>(hi);
-    } else if constexpr (F == 4 && sizeof(TF) == 4) {
-        float4 x = *reinterpret_cast<const float4 *>(p);
-        v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-    } else {
-#pragma unroll
-        for (int f = 0; f < F; ++f) v[f] = to_f32<TF>(p[f]);
-    }
+    uint16_t u = (uint16_t)(x & 0xffffu);
+    TF v;
+    __builtin_memcpy(&v, &u, 2);
+    return to_f32<TF>(v);
+}
+template <typename TF> __device__ __forceinline__ float hi16(uint32_t x)
+{
+    uint16_t u = (uint16_t)(x >> 16);
+    TF v;
+    __builtin_memcpy(&v, &u, 2);
+    return to_f32<TF>(v);
 }
 
-// Interpolated F features of level l at boundary point p (voxel units)
-// whose crossing axis is `face`.  Levels aligned with the voxel faces read
-// only the 4 corners of the face (the other 4 carry weight exactly 0).
-template <typename TF, int F>
-__device__ __forceinline__ void encode_level(const Geom &g, const TF *__restrict__ tab, int l,
-                                             const float p[3], int face, float out[F])
-{
-    uint32_t i[3];
-    float wt[3];
-    level_cell(g, l, p, i, wt);
-    const TF *base = tab + ((size_t)l << g.log2_T) * F;
-    const bool dense = (g.dense_mask >> l) & 1u;
-    const uint32_t side = (uint32_t)g.R[l] + 1u;
-    // per-axis vertex terms of the slot: slot = combine(tx, ty, tz)
-    uint32_t tx0 = i[0], tx1 = i[0] + 1u;
-    uint32_t ty0, ty1, tz0, tz1;
-    if (dense) {
-        ty0 = side * i[1]; ty1 = ty0 + side;
-        tz0 = side * side * i[2]; tz1 = tz0 + side * side;
-    } else {
-        ty0 = i[1] * kPrimeY; ty1 = ty0 + kPrimeY;
-        tz0 = i[2] * kPrimeZ; tz1 = tz0 + kPrimeZ;
-    }
-    const uint32_t mask = (1u << g.log2_T) - 1u;
-#pragma unroll
-    for (int f = 0; f < F; ++f) out[f] = 0.0f;
-    if ((g.aligned_mask >> l) & 1u) {
-        // put the crossing axis last: u, v = the two other axes in order
-        const uint32_t tf[3][2] = {{tx0, tx1}, {ty0, ty1}, {tz0, tz1}};
-        const int ua = face == 0 ? 1 : 0, va = face == 2 ? 1 : 2;
-        const uint32_t u0 = ua == 0 ? tf[0][0] : tf[1][0], u1 = ua == 0 ? tf[0][1] : tf[1][1];
-        const uint32_t v0 = va == 1 ? tf[1][0] : tf[2][0], v1 = va == 1 ? tf[1][1] : tf[2][1];
-        const float wu = ua == 0 ? wt[0] : wt[1];
-        const float wv = va == 1 ? wt[1] : wt[2];
-        const float wf = face == 0 ? wt[0] : (face == 1 ? wt[1] : wt[2]);
-        const uint32_t fsel = wf != 0.0f ? 1u : 0u;
-        const uint32_t ff = face == 0 ? (fsel ? tx1 : tx0) : (face == 1 ? (fsel ? ty1 : ty0) : (fsel ? tz1 : tz0));
-        uint32_t s[4];
-        s[0] = dense ? u0 + v0 + ff : ((u0 ^ v0 ^ ff) & mask);
-        s[1] = dense ? u1 + v0 + ff : ((u1 ^ v0 ^ ff) & mask);
-        s[2] = dense ? u0 + v1 + ff : ((u0 ^ v1 ^ ff) & mask);
-        s[3] = dense ? u1 + v1 + ff : ((u1 ^ v1 ^ ff) & mask);
-        float e[4][F];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) load_entry<TF, F>(base, s[c], e[c]);
-        const float w[4] = {(1.0f - wu) * (1.0f - wv), wu * (1.0f - wv), (1.0f - wu) * wv, wu * wv};
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int f = 0; f < F; ++f) out[f] = __builtin_fmaf(w[c], e[c][f], out[f]);
-    } else {
-        uint32_t s[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const uint32_t a = (c & 1) ? tx1 : tx0, b = (c & 2) ? ty1 : ty0, d = (c & 4) ? tz1 : tz0;
-            s[c] = dense ? a + b + d : ((a ^ b ^ d) & mask);
+// Raw bytes of one table entry (F features of type TF) at byte offset `off`.
+template <typename TF, int F> struct Entry {
+    static constexpr int W = (F * (int)sizeof(TF) + 3) / 4;   // dwords
+    uint32_t d[W];
+    __device__ __forceinline__ void load(const char *base, uint32_t off)
+    {
+        if constexpr (F * sizeof(TF) == 4) {
+            d[0] = *reinterpret_cast<const uint32_t *>(base + off);
+        } else if constexpr (F * sizeof(TF) == 8) {
+            uint2 x = *reinterpret_cast<const uint2 *>(base + off);
+            d[0] = x.x;
+            d[1] = x.y;
+        } else if constexpr (F * sizeof(TF) == 16) {
+            uint4 x = *reinterpret_cast<const uint4 *>(base + off);
+            d[0] = x.x; d[1] = x.y; d[2] = x.z; d[3] = x.w;
+        } else {
+            const TF *p = reinterpret_cast<const TF *>(base + off);
+            uint16_t u[2 * W] = {};
+            float f32[W] = {};
+            for (int f = 0; f < F; ++f) {
+                if constexpr (sizeof(TF) == 2) __builtin_memcpy(&u[f], &p[f], 2);
+                else f32[f] = to_f32<TF>(p[f]);
+            }
+            for (int k = 0; k < W; ++k) {
+                if constexpr (sizeof(TF) == 2) d[k] = (uint32_t)u[2 * k] | ((uint32_t)u[2 * k + 1] << 16);
+                else d[k] = __float_as_uint(f32[k]);
+            }
         }
-        float e[8][F];
+    }
+    // An opaque use of the loaded dwords: nothing that reads them can be
+    // moved above this point, so a batch of gathers is issued in full first.
+    __device__ __forceinline__ void pin()
+    {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) load_entry<TF, F>(base, s[c], e[c]);
-        const float wx[2] = {1.0f - wt[0], wt[0]}, wy[2] = {1.0f - wt[1], wt[1]}, wz[2] = {1.0f - wt[2], wt[2]};
+        for (int k = 0; k < W; ++k) asm volatile("" : "+v"(d[k]));
+    }
+    __device__ __forceinline__ float get(int f) const
+    {
+        if constexpr (sizeof(TF) == 4) return __uint_as_float(d[f]);
+        else return (f & 1) ? hi16<TF>(d[f >> 1]) : lo16<TF>(d[f >> 1]);
+    }
+};
+
+// Interpolated features of NL consecutive levels l0 .. l0 + NL - 1 at the
+// boundary point p (voxel units) whose crossing axis is `face`; levels at or
+// beyond L give zeros.  All slots are formed first and all gathers issued
+// before any is consumed.  On a level aligned with the voxel faces the
+// crossing-axis weight is exactly 0 or 1; both of that axis' vertex terms are
+// set to the selected one, so the 4 zero-weight corners re-read the 4 face
+// corners instead of touching other table entries.
+template <typename TF, int F, int NL>
+__device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restrict__ tab, int l0,
+                                              const float p[3], int face, float out[NL][F])
+{
+    const char *base[NL];
+    uint32_t off[NL][8];
+    float wx[NL][2], wy[NL][2], wz[NL][2];
+    constexpr uint32_t esz = F * sizeof(TF);
+#pragma unroll
+    for (int lv = 0; lv < NL; ++lv) {
+        const int l = l0 + lv < g.L ? l0 + lv : g.L - 1;
+        uint32_t i[3];
+        float wt[3];
+        level_cell(g, l, p, i, wt);
+        const uint32_t my = g.my[l], mz = g.mz[l];
+        uint32_t t[3][2] = {{i[0], i[0] + 1u}, {i[1] * my, i[1] * my + my}, {i[2] * mz, i[2] * mz + mz}};
+        const bool al = (g.aligned_mask >> l) & 1u;
+        const float wf = face == 0 ? wt[0] : (face == 1 ? wt[1] : wt[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool col = al && a == face;
+            const uint32_t sel = wf != 0.0f ? t[a][1] : t[a][0];
+            t[a][0] = col ? sel : t[a][0];
+            t[a][1] = col ? sel : t[a][1];
+        }
+        const uint32_t dm = g.dmask[l], hm = g.hmask[l];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const float w = (wx[c & 1] * wy[(c >> 1) & 1]) * wz[(c >> 2) & 1];
+            const uint32_t x = t[0][c & 1], y = t[1][(c >> 1) & 1], z = t[2][c >> 2];
+            off[lv][c] = (((x + y + z) & dm) | ((x ^ y ^ z) & hm)) * esz;
+        }
+        wx[lv][0] = 1.0f - wt[0]; wx[lv][1] = wt[0];
+        wy[lv][0] = 1.0f - wt[1]; wy[lv][1] = wt[1];
+        wz[lv][0] = 1.0f - wt[2]; wz[lv][1] = wt[2];
+        base[lv] = reinterpret_cast<const char *>(tab + ((size_t)l << g.log2_T) * F);
+    }
+    Entry<TF, F> e[NL][8];
 #pragma unroll
-            for (int f = 0; f < F; ++f) out[f] = __builtin_fmaf(w, e[c][f], out[f]);
+    for (int lv = 0; lv < NL; ++lv)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) e[lv][c].load(base[lv], off[lv][c]);
+    // keep every gather of the batch in flight before the first is consumed
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int lv = 0; lv < NL; ++lv)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) e[lv][c].pin();
+#pragma unroll
+    for (int lv = 0; lv < NL; ++lv) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) out[lv][f] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const float w = (wx[lv][c & 1] * wy[lv][(c >> 1) & 1]) * wz[lv][c >> 2];
+#pragma unroll
+            for (int f = 0; f < F; ++f) out[lv][f] = __builtin_fmaf(w, e[lv][c].get(f), out[lv][f]);
+        }
+        if (l0 + lv >= g.L) {
+#pragma unroll
+            for (int f = 0; f < F; ++f) out[lv][f] = 0.0f;
         }
     }
 }
@@ -204,6 +239,99 @@ __device__ __forceinline__ void decode_store(const QueryArgs &A, uint32_t r, con
     A.hits[r] = h;
 }
 
+// ------------------------------------------------------------- shared prologue
+//
+// Each lane walks the voxels of ray blockIdx.x * kBlock + threadIdx.x, then
+// the block's rays are ordered by voxel count (most first) so that each wave
+// encodes rays with similar numbers of boundary points.  After the prologue,
+// lane `tid` works on ray `src` of the block; its voxel list is at
+// s_list[j * kBlock + src] and its walk state has been reloaded from LDS.
+constexpr int kState = 14;          // words of walk state per ray kept in LDS
+
+struct Shared {
+    uint32_t coarse[kCoarseLdsWords];
+    float state[kState * kBlock];
+    uint32_t hist[kMaxList + 2];
+    uint16_t perm[kBlock];
+};
+
+struct Lane {
+    VRay w;
+    int nvox;
+    uint32_t src;     // ray index within the block
+    uint32_t r;       // global ray index
+    bool live;
+};
+
+__device__ __forceinline__ void walk_and_sort(const QueryArgs &A, Shared &S, uint32_t *s_list, Lane &L)
+{
+    const uint32_t tid = threadIdx.x;
+    const Geom &g = A.g;
+    const int cap = g.H >> 1;
+    const bool lds_coarse = g.coarse_words <= kCoarseLdsWords;
+    if (lds_coarse)
+        for (int i = tid; i < g.coarse_words; i += kBlock) S.coarse[i] = g.coarse[i];
+    if (tid <= (uint32_t)cap) S.hist[tid] = 0;
+    __syncthreads();
+    const uint32_t slot0 = blockIdx.x * kBlock + tid;
+    const uint32_t r0 = slot0 < A.n ? (A.order ? A.order[slot0] : slot0) : 0u;
+    VRay w;
+    w.valid = w.cand = false;
+    w.ta = w.tb = w.tmax = 0.0f;
+    w.mov = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w.o[a] = w.d[a] = w.inv[a] = 0.0f;
+    int nvox = 0;
+    if (slot0 < A.n) {
+        setup_ray(g, A.rays[2 * r0], A.rays[2 * r0 + 1], w);
+        nvox = lds_coarse ? walk_voxels(g, w, S.coarse, s_list + tid, kBlock, cap)
+                          : walk_voxels(g, w, g.coarse, s_list + tid, kBlock, cap);
+    }
+    float *st = S.state;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        st[(0 + a) * kBlock + tid] = w.o[a];
+        st[(3 + a) * kBlock + tid] = w.d[a];
+        st[(6 + a) * kBlock + tid] = w.inv[a];
+    }
+    st[9 * kBlock + tid] = w.ta;
+    st[10 * kBlock + tid] = w.tb;
+    st[11 * kBlock + tid] = w.tmax;
+    st[12 * kBlock + tid] = __uint_as_float(w.mov | (w.valid ? 8u : 0u) | (w.cand ? 16u : 0u) | ((uint32_t)nvox << 8));
+    st[13 * kBlock + tid] = __uint_as_float(r0);
+    const uint32_t pos = atomicAdd(&S.hist[cap - nvox], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b <= cap; ++b) {
+            const uint32_t c = S.hist[b];
+            S.hist[b] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    S.perm[S.hist[cap - nvox] + pos] = (uint16_t)tid;
+    __syncthreads();
+    const uint32_t src = S.perm[tid];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        L.w.o[a] = st[(0 + a) * kBlock + src];
+        L.w.d[a] = st[(3 + a) * kBlock + src];
+        L.w.inv[a] = st[(6 + a) * kBlock + src];
+    }
+    L.w.ta = st[9 * kBlock + src];
+    L.w.tb = st[10 * kBlock + src];
+    L.w.tmax = st[11 * kBlock + src];
+    const uint32_t pk = __float_as_uint(st[12 * kBlock + src]);
+    L.w.mov = pk & 7u;
+    L.w.valid = (pk & 8u) != 0;
+    L.w.cand = (pk & 16u) != 0;
+    L.nvox = (int)(pk >> 8);
+    L.src = src;
+    L.live = blockIdx.x * kBlock + src < A.n;
+    L.r = __float_as_uint(st[13 * kBlock + src]);
+}
+
 // ---------------------------------------------------------------- float32 path
 //
 // Weights: layer k transposed to [in][out_pad] float32 (out_pad = WIDTH for
@@ -212,19 +340,16 @@ __device__ __forceinline__ void decode_store(const QueryArgs &A, uint32_t r, con
 template <typename TF, int F, int WIDTH>
 __global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
 {
-    __shared__ uint32_t s_list[kMaxList * kBlock];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t r = blockIdx.x * kBlock + tid;
-    const bool live = r < A.n;
+    constexpr int NL = 4;
+    extern __shared__ uint32_t s_list[];
+    __shared__ Shared S;
+    Lane ln;
+    walk_and_sort(A, S, s_list, ln);
+    const uint32_t src = ln.src, r = ln.r;
+    const bool live = ln.live;
+    const VRay &w = ln.w;
     const Geom &g = A.g;
-    VRay w;
-    w.valid = w.cand = false;
-    w.ta = w.tb = 0.0f;
-    w.tmax = 0.0f;
-    w.mov = 0;
-    if (live) setup_ray(g, A.rays[2 * r], A.rays[2 * r + 1], w);
-    const int nvox = live ? walk_voxels(g, w, s_list + tid, kBlock, g.H >> 1) : 0;
-    const int count = 2 * nvox;
+    const int count = 2 * ln.nvox;
     const int wmax = __builtin_amdgcn_readfirstlane(wave_max(count));
     const float *__restrict__ Wf = reinterpret_cast<const float *>(A.m.W);
     const TF *__restrict__ tab = reinterpret_cast<const TF *>(A.tables);
@@ -236,19 +361,26 @@ __global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
     for (int h = 0; h < wmax; ++h) {
         if (h < count) {
             float p[3];
-            const int face = boundary_point(w, s_list[(h >> 1) * kBlock + tid], h & 1, p);
-            for (int l = 0; l < g.L; ++l) {
-                float e[F];
-                encode_level<TF, F>(g, tab, l, p, face, e);
-                if (A.dbg.enc) {
+            const int face = boundary_point(w, s_list[(h >> 1) * kBlock + src], h & 1, p);
+            for (int l0 = 0; l0 < g.L; l0 += NL) {
+                float e[NL][F];
+                encode_levels<TF, F, NL>(g, tab, l0, p, face, e);
 #pragma unroll
-                    for (int f = 0; f < F; ++f) A.dbg.enc[(size_t)r * g.H * LF + h * LF + l * F + f] = e[f];
+                for (int lv = 0; lv < NL; ++lv) {
+                    const int l = l0 + lv;
+                    if (l < g.L) {
+                        if (A.dbg.enc) {
+#pragma unroll
+                            for (int f = 0; f < F; ++f)
+                                A.dbg.enc[(size_t)r * g.H * LF + h * LF + l * F + f] = e[lv][f];
+                        }
+                        const float *Wk = Wf + A.m.off[0] + (size_t)(h * LF + l * F) * WIDTH;
+#pragma unroll
+                        for (int f = 0; f < F; ++f)
+#pragma unroll
+                            for (int j = 0; j < WIDTH; ++j) acc[j] = __builtin_fmaf(Wk[f * WIDTH + j], e[lv][f], acc[j]);
+                    }
                 }
-                const float *Wk = Wf + A.m.off[0] + (size_t)(h * LF + l * F) * WIDTH;
-#pragma unroll
-                for (int f = 0; f < F; ++f)
-#pragma unroll
-                    for (int j = 0; j < WIDTH; ++j) acc[j] = __builtin_fmaf(Wk[f * WIDTH + j], e[f], acc[j]);
             }
         }
     }
@@ -370,20 +502,17 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
     constexpr int FP = F == 3 ? 4 : F;        // features per level, padded to divide 16
     constexpr int MB = WIDTH / 32;            // output blocks of a hidden layer
     constexpr int LPB = 16 / FP;              // levels per K block
-    __shared__ uint32_t s_list[kMaxList * kBlock];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63u;
-    const uint32_t r = blockIdx.x * kBlock + tid;
-    const bool live = r < A.n;
+    constexpr int NL = (F * sizeof(TF) <= 4 && LPB >= 8) ? 8 : (LPB < 4 ? LPB : 4);   // levels per gather batch
+    extern __shared__ uint32_t s_list[];
+    __shared__ Shared S;
+    Lane ln;
+    walk_and_sort(A, S, s_list, ln);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t src = ln.src, r = ln.r;
+    const bool live = ln.live;
+    const VRay &w = ln.w;
     const Geom &g = A.g;
-    VRay w;
-    w.valid = w.cand = false;
-    w.ta = w.tb = 0.0f;
-    w.tmax = 0.0f;
-    w.mov = 0;
-    if (live) setup_ray(g, A.rays[2 * r], A.rays[2 * r + 1], w);
-    const int nvox = live ? walk_voxels(g, w, s_list + tid, kBlock, g.H >> 1) : 0;
-    const int count = 2 * nvox;
+    const int count = 2 * ln.nvox;
     const int wmax = __builtin_amdgcn_readfirstlane(wave_max(count));
     const TF *__restrict__ tab = reinterpret_cast<const TF *>(A.tables);
     const uint4 *__restrict__ Wv = reinterpret_cast<const uint4 *>(A.m.W);
@@ -401,21 +530,20 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
         float p[3] = {0.0f, 0.0f, 0.0f};
         int face = 0;
         const bool has = h < count;
-        if (has) face = boundary_point(w, s_list[(h >> 1) * kBlock + tid], h & 1, p);
+        if (has) face = boundary_point(w, s_list[(h >> 1) * kBlock + src], h & 1, p);
         for (int kb = 0; kb < KB; ++kb) {
             float e[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) e[q] = 0.0f;
             if (has) {
 #pragma unroll
-                for (int lv = 0; lv < LPB; ++lv) {
-                    const int l = kb * LPB + lv;
-                    if (l < g.L) {
-                        float v[F];
-                        encode_level<TF, F>(g, tab, l, p, face, v);
+                for (int c0 = 0; c0 < LPB; c0 += NL) {
+                    float v[NL][F];
+                    encode_levels<TF, F, NL>(g, tab, kb * LPB + c0, p, face, v);
 #pragma unroll
-                        for (int f = 0; f < F; ++f) e[lv * FP + f] = v[f];
-                    }
+                    for (int lv = 0; lv < NL; ++lv)
+#pragma unroll
+                        for (int f = 0; f < F; ++f) e[(c0 + lv) * FP + f] = v[lv][f];
                 }
             }
             uint32_t lo[4], hi[4];

@@ -3,9 +3,14 @@
 #include <hip/hip_runtime.h>
 
 namespace lsnif {
+constexpr uint32_t kSortBins = (1u << 18) + 1;   // 8 octants x 32^3 cells, plus one bin for rays that miss
+constexpr uint32_t kSortScanBlocks = (kSortBins + 1023) / 1024;   // partial sums of the two-pass scan
+struct Geom;
 struct QueryArgs;
 struct DebugArgs;
 hipError_t launch_f32(const QueryArgs &A, int feat_dtype, int F, hipStream_t s);
 hipError_t launch_mma(const QueryArgs &A, int feat_dtype, int mlp_dtype, int F, hipStream_t s);
 hipError_t launch_debug(const DebugArgs &D, hipStream_t s);
+hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *keys, uint32_t *hist,
+                                 uint32_t *order, hipStream_t s);
 }  // namespace lsnif
