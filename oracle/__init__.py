@@ -37,7 +37,7 @@ class _Object(C.Structure):
                 ("R", C.c_void_p), ("tables", C.c_void_p), ("H", C.c_int32),
                 ("n_layers", C.c_int32), ("dims", C.c_void_p), ("W", C.c_void_p),
                 ("act", C.c_int32), ("leaky_slope", C.c_float), ("n_mat", C.c_int32),
-                ("has_albedo", C.c_int32)]
+                ("has_albedo", C.c_int32), ("grazing_recheck", C.c_int32)]
 
 
 class _Outputs(C.Structure):
@@ -94,6 +94,7 @@ class _Bound:
         s.W = C.cast(self.Wp, C.c_void_p)
         s.act, s.leaky_slope = obj.act, obj.leaky_slope
         s.n_mat, s.has_albedo = obj.n_mat, obj.has_albedo
+        s.grazing_recheck = int(getattr(obj, "grazing_recheck", 0))
         self.s = s
 
 

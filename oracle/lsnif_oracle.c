@@ -59,6 +59,7 @@ typedef struct {
     int32_t act;
     float leaky_slope;
     int32_t n_mat, has_albedo;
+    int32_t grazing_recheck;   /* 1: grazing voxels of the walk are re-decided in float64 */
 } oracle_object;
 
 /* Per-ray walk result. */
@@ -108,6 +109,39 @@ static float cell_entry(int k, float o, float inv, float d)
 static float cell_exit(int k, float o, float inv, float d)
 {
     return d > 0.0f ? plane_t((float)(k + 1), o, inv) : plane_t((float)k, o, inv);
+}
+
+/*
+ * Optional float64 re-decision of a voxel the float32 walk finds grazing: its
+ * overlap with [ta, tb] is no longer than 2^-16 max(1, |entry|), or the whole
+ * segment [ta, tb] is that short.  The slab intervals of the voxel and of the
+ * grid are recomputed in float64 from the same float32 voxel-space origin and
+ * direction, over the axes the float32 walk treats as moving, and the voxel is
+ * kept iff the float64 overlap has positive length.  Only the decision to list
+ * a voxel the walk visits changes; its t values stay the float32 ones.
+ */
+static int grazing(float tin, float tout, float ta, float tb)
+{
+    const float lo = fmax2(tin, ta), hi = fmin2(tout, tb);
+    const float q = 0x1p-16f;
+    return hi - lo <= q * fmax2(1.0f, fabsf(tin)) || tb - ta <= q * fmax2(1.0f, fabsf(ta));
+}
+
+static int keep_f64(const walk_t *w, const int moving[3], const int c[3], int V, float tmin)
+{
+    double t0 = -INFINITY, t1 = INFINITY, tin = -INFINITY, tout = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (!moving[a]) continue;
+        const double o = w->o[a], d = w->d[a];
+        const double g0 = (0.0 - o) / d, g1 = ((double)V - o) / d;
+        const double e0 = ((double)c[a] - o) / d, e1 = ((double)(c[a] + 1) - o) / d;
+        t0 = fmax(t0, fmin(g0, g1));
+        t1 = fmin(t1, fmax(g0, g1));
+        tin = fmax(tin, fmin(e0, e1));
+        tout = fmin(tout, fmax(e0, e1));
+    }
+    const double ta = fmax(t0, (double)tmin), tb = t1;
+    return fmin(tout, tb) > fmax(tin, ta);
 }
 
 /*
@@ -184,7 +218,9 @@ static void walk(const oracle_object *ob, const float *ray, walk_t *w)
             if (ia < 0 || en > tin) { tin = en; ia = a; }
             if (oa < 0 || ex < tout) { tout = ex; oa = a; }
         }
-        if (occupied(ob, c[0], c[1], c[2]) && fmin2(tout, tb) > fmax2(tin, ta)) {
+        int keep = fmin2(tout, tb) > fmax2(tin, ta);
+        if (ob->grazing_recheck && grazing(tin, tout, ta, tb)) keep = keep_f64(w, moving, c, V, ray[6]);
+        if (occupied(ob, c[0], c[1], c[2]) && keep) {
             int j = w->nvox++;
             for (int a = 0; a < 3; ++a) w->ijk[j][a] = c[a];
             w->tin[j] = tin;

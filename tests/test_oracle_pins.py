@@ -12,7 +12,7 @@ import pytest
 import oracle
 import workloads as W
 from workloads.objects import LsnifObject, make_weights
-from tests.bruteforce import voxel_list
+from tests.bruteforce import voxel_list, recheck_sets
 
 f32 = np.float32
 HASH_PRIMES = (1, 2654435761, 805459861)   # Mueller et al. 2022, Eq. 4
@@ -463,3 +463,47 @@ def test_pairs_nearest_hit_matches_bruteforce():
     assert np.array_equal(r["winner"], best_i)
     assert np.array_equal(r["t"][best_i >= 0], best_t[best_i >= 0])
     assert np.all(r["hit"] == (best_i >= 0))
+
+
+def edge_grazing_rays(rng, V, n):
+    """Rays aimed within 1e-7.5 .. 1e-5 voxels of a lattice edge inside the grid (object space is
+    voxel space here), so float32 and float64 can disagree on the cells at the edge."""
+    rays = []
+    for _ in range(n):
+        p = rng.integers(1, V, 3).astype(np.float64)
+        p[rng.integers(3)] = rng.uniform(0.5, V - 0.5)
+        p += rng.choice([-1, 1], 3) * 10 ** rng.uniform(-7.5, -5, 3)
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        o = p - rng.uniform(1.5, 3) * V * d
+        rays.append([*o, *d, 0.0, np.inf])
+    return np.asarray(rays, f32)
+
+
+def test_grazing_recheck_against_bruteforce():
+    """Optional float64 recheck of grazing voxels (off by default): against the all-voxel test
+    in float32 and float64, every listed voxel is allowed and every required one is listed,
+    in walk order; the recheck changes some lists, a walk that ignored it would fail, and so
+    would one that dropped every grazing voxel."""
+    V = 8
+    rng = np.random.default_rng(7)
+    occ = rng.uniform(size=V ** 3) < 0.8
+    obj = tiny_object(V, occ, H=48, L=1, F=1, width=2, n_hidden=1, bmin=(0, 0, 0), bmax=(V, V, V))
+    rays = edge_grazing_rays(rng, V, 3000)
+    off = oracle.query(obj, rays, debug=True)
+    obj.grazing_recheck = 1
+    on = oracle.query(obj, rays, debug=True)
+    changed = fp32_fails = grazing_required = 0
+    for i, ray in enumerate(rays):
+        s = recheck_sets(ray, occ, V, obj.bmin, obj.bmax)
+        n = on["count"][i] // 2
+        listed = [tuple(int(x) for x in v) for v in on["vox_ijk"][i, :n]]
+        assert len(set(listed)) == len(listed), i
+        assert set(listed) >= s["must"] and set(listed) <= s["may"], i
+        assert np.all(np.diff(on["vox_t"][i, :n, 0]) >= 0), i
+        n0 = off["count"][i] // 2
+        l32 = {tuple(int(x) for x in v) for v in off["vox_ijk"][i, :n0]}
+        fp32_fails += not (l32 >= s["must"] and l32 <= s["may"])
+        changed += l32 != set(listed)
+        grazing_required += len(s["must_grazing"])
+    assert changed >= 50 and fp32_fails >= 10 and grazing_required >= 50

@@ -47,6 +47,7 @@ class LsnifObject:
     n_mat: int = 4
     has_albedo: int = 0
     name: str = ""
+    grazing_recheck: int = 0         # 1: re-decide grazing voxels of the walk in float64
 
     @property
     def T(self):
