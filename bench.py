@@ -29,13 +29,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_FP16_PEAK_TFLOPS = 2500.0
-KERNEL = "k_query_mma<_Float16, _Float16, 2, 64>"
+KERNEL = "k_query_mma<_Float16, _Float16, 2, 64, 2>"
+
+
+KERNEL_SOURCES = ("lsnif_device.hpp", "lsnif_kernels.hpp", "lsnif_launch.hpp", "k_mma_f16.hip",
+                  "lsnif_host.hip")
 
 
 def kernel_source_hash():
+    """Hash of the sources that fix the timed kernel's code and its data layout in HBM."""
     h = hashlib.sha1()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2504_21627_amd", "csrc", "*"))):
-        with open(p, "rb") as f:
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2504_21627_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
@@ -52,23 +57,33 @@ def stored_traffic(workload):
     return rec.get("bytes_per_launch")
 
 
-def time_path(L, ctx, oid, rays, out, steps, warmup):
+def time_calls(L, ctx, call, steps, warmup):
+    """Time `call(stream)` on torch's current stream: wall clock over `steps` calls, per-call
+    HIP event latency, and the library's own per-query sort and kernel time."""
     import torch
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
-        L.lsnif_query(ctx, oid, rays, out, stream)
+        call(stream)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    L.lsnif_profile_read(ctx)
+    L.lsnif_profile_enable(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for a, b in ev:
         a.record(stream)
-        L.lsnif_query(ctx, oid, rays, out, stream)
+        call(stream)
         b.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    L.lsnif_profile_enable(ctx, False)
+    sort_ms, kern_ms, k = L.lsnif_profile_read(ctx)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
-    return wall, lat
+    return wall, lat, (sort_ms / k if k else None), (kern_ms / k if k else None)
+
+
+def time_path(L, ctx, oid, rays, out, steps, warmup):
+    return time_calls(L, ctx, lambda s: L.lsnif_query(ctx, oid, rays, out, s), steps, warmup)
 
 
 def points_per_launch(L, ctx, oid, rays, out):
@@ -95,26 +110,148 @@ def cpu_baseline(obj, rays_np, sample):
                       f"float32 walk + float64 encoding/MLP, OpenMP, {dt:.2f} s wall"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--only", choices=["fp16", "fp32"], default=None,
-                    help="time one path only (for profiling)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); every box here has one GPU "
-              "and this build runs no multi-GPU path.", file=sys.stderr)
-        sys.exit(2)
+def bytes_per_point(obj, feat_bytes=2):
+    """Algorithmic gather bytes of one boundary point: 4 corners on levels aligned with the
+    voxel faces, 8 elsewhere, F features each."""
+    return sum(4 if int(R) % obj.V == 0 else 8 for R in obj.R) * obj.F * feat_bytes
 
+
+def bench_c4(L, steps, warmup):
+    """64 objects, 16,777,216 (ray, object) pairs with power-law counts, one pair query per step
+    (identity instances), timed as direct calls and as replays of a captured graph."""
     import torch
     import workloads as W
-    from paper_2504_21627_amd import lsnif as L
+    print("[bench] generating the c4 workload (64 objects, 16M pairs)", file=sys.stderr, flush=True)
+    d = W.configs.c4()
+    objs, rays_np, owner, counts = d["objects"], d["rays"], d["owner"], d["counts"]
+    n = len(rays_np)
+    ctx = L.lsnif_create(0)
+    try:
+        ids = [L.lsnif_build(ctx, L.ObjectDesc(o, "fp16", "fp16")) for o in objs]
+        eye = np.concatenate([np.eye(3), np.zeros((3, 1))], 1).astype(np.float32)
+        inst = torch.from_numpy(L.instances_array([(i, eye) for i in ids])).cuda()
+        rays = torch.from_numpy(rays_np).cuda()
+        pr = torch.arange(n, dtype=torch.int32, device="cuda")
+        pi = torch.from_numpy(owner.astype(np.int32)).cuda()
+        out = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+        print(f"[bench] timing c4 direct: {warmup} warmup + {steps} steps", file=sys.stderr, flush=True)
+        wall_d, lat_d, prep_ms, kern_ms = time_calls(
+            L, ctx, lambda st: L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out, st), steps, warmup)
+        g = L.lsnif_graph_pairs(ctx, rays, pr, pi, inst, out)
+        try:
+            print(f"[bench] timing c4 graph replays", file=sys.stderr, flush=True)
+            wall_g, lat_g, _, _ = time_calls(L, ctx, lambda st: L.lsnif_graph_launch(g, st), steps, warmup)
+        finally:
+            L.lsnif_graph_destroy(g)
+        # algorithmic gather bytes: boundary points per object from the per-ray voxel counts
+        m = int(counts.max())
+        cnt = torch.empty(m, dtype=torch.int32, device="cuda")
+        tmp = torch.empty((m, 6), dtype=torch.float32, device="cuda")
+        alg, pts, cand, off = 0, 0, 0, 0
+        for k, o in enumerate(objs):
+            c = int(counts[k])
+            L.lsnif_query_debug(ctx, ids[k], rays[off:off + c], tmp[:c], {"count": cnt[:c]})
+            cc = cnt[:c]
+            p = int(cc.clamp(min=0).sum().item())
+            alg += p * bytes_per_point(o)
+            pts += p
+            cand += int((cc > 0).sum().item())
+            off += c
+    finally:
+        L.lsnif_destroy(ctx)
+    macs = sum(w.shape[0] * w.shape[1] for w in objs[0].weights)   # every c4 MLP: 576/k -> 64x3 -> 9
+    val = lambda wall: n / (wall / steps) / 1e6
+    return {
+        "workload": "c4: 64 objects (tori, displaced spheres, box soups; 1k-500k triangles; V 32-256; "
+                    "8-16 levels x 2^14-2^19 entries x 2 fp16 features; MLP 3x64 fp16), 16,777,216 "
+                    "(ray, object) pairs, power-law counts 1,189-977,190 per object, one pair query",
+        "pairs": n, "objects": len(objs),
+        "direct": {"value": val(wall_d), "unit": "Mpairs/s", "ms_per_step": wall_d * 1e3 / steps,
+                   "p50_ms": float(np.percentile(lat_d, 50)), "p99_ms": float(np.percentile(lat_d, 99)),
+                   "prepare_ms": prep_ms, "kernel_ms": kern_ms},
+        "graph": {"value": val(wall_g), "unit": "Mpairs/s", "ms_per_step": wall_g * 1e3 / steps,
+                  "p50_ms": float(np.percentile(lat_g, 50)), "p99_ms": float(np.percentile(lat_g, 99))},
+        "roofline": {"bound": "hbm", "alg_bytes_per_launch": alg, "points_per_launch": pts,
+                     "achieved": alg / (kern_ms * 1e-3) / 1e9 if kern_ms else None, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": alg / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if kern_ms else None,
+                     "candidate_pairs": cand, "mlp_macs_per_pair": macs},
+    }
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+def bench_c5(L, n_requests, seed=7):
+    """Serving: requests from a path tracer over c4's 64 objects as 8 x 8 instances (primary
+    tiles, diffuse bounces, shadow rays), sizes log-uniform in [256, 2M] rays.  First every
+    request is submitted at once (closed loop: the sustained rate); then requests arrive as a
+    Poisson process at 0.7x that rate, and p50/p99 are taken from submit to completion."""
+    import torch
+    import workloads as W
+    from paper_2504_21627_amd.serving import RequestSet
+    print("[bench] generating the c5 scene, ray pool and broad phase", file=sys.stderr, flush=True)
+    objs = [W.configs.c4_object(i) for i in range(64)]
+    pool = W.configs.c5_pool(objs)
+    rays = pool["rays"]
+    pr, pi = W.configs.ray_box_pairs(rays, pool["boxes"])
+    windows = W.configs.c5_requests(pool["n_primary"], len(rays), n_requests=n_requests)
+    total = sum(n for _, n, _ in windows)
+    ctx = L.lsnif_create(0)
+    try:
+        ids = [L.lsnif_build(ctx, L.ObjectDesc(o, "fp16", "fp16")) for o in objs]
+        rs = RequestSet(L, rays, pr, pi, [(ids[k], m) for k, m in pool["insts"]], windows)
+        torch.cuda.synchronize()
+        cfg = dict(max_inflight=8, hbm_budget=4 << 30, n_streams=4)
+
+        def run(arrivals):
+            L.lsnif_serve_start(ctx, **cfg)
+            try:
+                t0 = time.perf_counter()
+                tickets = []
+                for j in range(len(windows)):
+                    if arrivals is not None:
+                        dt = t0 + arrivals[j] - time.perf_counter()
+                        if dt > 0:
+                            time.sleep(dt)
+                    tickets.append(L.lsnif_serve_submit(ctx, rs.request(j)))
+                for t in tickets:
+                    if L.lsnif_serve_wait(ctx, t) != L.LSNIF_OK:
+                        raise RuntimeError("a serving request failed")
+                wall = time.perf_counter() - t0
+                st = L.lsnif_serve_stats_get(ctx)
+            finally:
+                L.lsnif_serve_stop(ctx)
+            return wall, st
+
+        print("[bench] c5 warm-up", file=sys.stderr, flush=True)
+        for j in range(min(16, len(windows))):
+            L.lsnif_query_pairs(ctx, rs.rays_of(j), rs.pr[j], rs.pi[j], rs.inst, rs.outs[j])
+        torch.cuda.synchronize()
+        print(f"[bench] c5 closed loop: {len(windows)} requests, {total} rays", file=sys.stderr, flush=True)
+        wall_c, st_c = run(None)
+        sustained = total / wall_c
+        lam = 0.7 * sustained / (total / len(windows))          # requests per second
+        arrivals = np.cumsum(np.random.Generator(np.random.PCG64(seed)).exponential(1.0 / lam, len(windows)))
+        arrivals -= arrivals[0]
+        print(f"[bench] c5 Poisson arrivals at {lam:.1f} requests/s", file=sys.stderr, flush=True)
+        wall_p, st_p = run(arrivals)
+    finally:
+        L.lsnif_destroy(ctx)
+    return {
+        "workload": "c5: c4's 64 objects as 8x8 instances, 1024x1024 primary pool + 3M secondary "
+                    f"(diffuse, shadow) rays, {len(windows)} requests of 256-2M rays, depth 1-4, "
+                    "fp16, 4 GiB in-flight budget, 8 slots, 4 streams",
+        "requests": len(windows), "rays": total, "pairs_per_ray": len(pr) / len(rays),
+        "closed_loop": {"value": sustained / 1e6, "unit": "Mrays/s", "wall_s": wall_c,
+                        "p50_ms": st_c["p50_ms"], "p99_ms": st_c["p99_ms"],
+                        "ws_bytes_peak": st_c["ws_bytes_peak"]},
+        "poisson": {"rate_req_s": lam, "offered_mrays_s": 0.7 * sustained / 1e6,
+                    "value": total / wall_p / 1e6, "unit": "Mrays/s", "wall_s": wall_p,
+                    "p50_ms": st_p["p50_ms"], "p99_ms": st_p["p99_ms"], "max_ms": st_p["max_ms"]},
+    }
+
+
+def bench_c2(L, args):
+    """The headline: the c2 batch through the FP16 matrix-core path and the plain FP32 path."""
+    import torch
+    import workloads as W
     print("[bench] generating the c2 workload", file=sys.stderr, flush=True)
     obj = W.configs.c2_object()
     rays_np = W.configs.c2_rays()
@@ -129,21 +266,18 @@ def main():
         oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
         print(f"[bench] timing the {name} path: {args.warmup} warmup + {args.steps} steps",
               file=sys.stderr, flush=True)
-        wall, lat = time_path(L, ctx, oid, rays, out, args.steps, args.warmup)
+        wall, lat, sort_ms, kern_ms = time_path(L, ctx, oid, rays, out, args.steps, args.warmup)
         pts, cand = points_per_launch(L, ctx, oid, rays, out)
-        paths[name] = {"wall": wall, "lat": lat, "points": pts, "cand": cand,
-                       "feat_bytes": 2 if feat == "fp16" else 4}
+        paths[name] = {"wall": wall, "lat": lat, "points": pts, "cand": cand, "sort_ms": sort_ms,
+                       "kern_ms": kern_ms, "feat_bytes": 2 if feat == "fp16" else 4}
         L.lsnif_release(ctx, oid)
     L.lsnif_destroy(ctx)
 
     head = paths.get("fp16") or paths["fp32"]
     ms_per_step = head["wall"] * 1e3 / args.steps
-    mean_ms = float(head["lat"].mean())
-    # algorithmic gather bytes per boundary point: 4 corners on levels aligned with the
-    # voxel faces, 8 elsewhere, F features each
-    corners = sum(4 if int(R) % obj.V == 0 else 8 for R in obj.R)
-    bytes_per_point = corners * obj.F * head["feat_bytes"]
-    alg_bytes = head["points"] * bytes_per_point
+    mean_ms = float(head["kern_ms"])      # query kernel alone, HIP events on its stream
+    bpp = bytes_per_point(obj, head["feat_bytes"])
+    alg_bytes = head["points"] * bpp
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
     macs = sum(w.shape[0] * w.shape[1] for w in obj.weights)
     flops = 2.0 * macs * head["cand"]
@@ -167,7 +301,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("c2-fp16"),
                      "kernel": KERNEL if "fp16" in paths else "k_query_f32",
                      "alg_bytes_per_launch": alg_bytes, "points_per_launch": head["points"],
-                     "bytes_per_point": bytes_per_point, "mean_kernel_ms": mean_ms,
+                     "bytes_per_point": bpp, "mean_kernel_ms": mean_ms,
+                     "mean_sort_ms": float(head["sort_ms"]),
                      "mfma_tflops": flops / (mean_ms * 1e-3) / 1e12,
                      "mfma_frac": flops / (mean_ms * 1e-3) / 1e12 / MFMA_FP16_PEAK_TFLOPS},
     }
@@ -178,7 +313,51 @@ def main():
                              "p99_ms": float(np.percentile(p["lat"], 99))}
         if "fp16" in paths:
             rec["fp16_over_fp32"] = rec["value"] / rec["fp32_plain"]["value"]
-    if not args.no_cpu:
+    return rec, obj, rays_np
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--only", choices=["fp16", "fp32"], default=None,
+                    help="time one path only (for profiling)")
+    ap.add_argument("--legs", default="c2,c4,c5",
+                    help="comma list: c2 (headline), c4 (batched objects), c5 (serving)")
+    ap.add_argument("--c5-requests", type=int, default=2000)
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="first copy a device buffer of this size (MiB): the copy of known size "
+                         "against which rocprofv3's FETCH_SIZE/WRITE_SIZE counters are scaled")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); every box here has one GPU "
+              "and this build runs no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2504_21627_amd import lsnif as L
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_ref_mib:
+        src = torch.ones(args.copy_ref_mib << 18, dtype=torch.float32, device="cuda")
+        dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
+    legs = set(args.legs.split(","))
+    if "c2" in legs:
+        rec, obj, rays_np = bench_c2(L, args)
+    else:
+        rec = {"metric": "Mrays/s LSNIF queries (FP16 MFMA vs FP32 plain) + p50/p99 batch latency",
+               "legs": sorted(legs), "note": "headline (c2) leg not run"}
+    if "c4" in legs:
+        rec["batched_c4"] = bench_c4(L, max(args.steps // 10, 5), min(args.warmup, 3))
+    if "c5" in legs:
+        rec["serving_c5"] = bench_c5(L, args.c5_requests)
+    if not args.no_cpu and "c2" in legs:
         print("[bench] timing the oracle on a CPU sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(obj, rays_np, args.cpu_sample)
     print(json.dumps(rec), flush=True)

@@ -68,10 +68,19 @@ typedef struct {
     int32_t material; /* argmax of the material logits, lowest index on ties */
 } lsnif_hit;
 
+/* One instance of a built object, 52 bytes: the object's id and the row-major
+ * 3x4 world-to-object matrix [A | b], x_obj = A x_world + b.  Rays are mapped
+ * with d_obj = A d_world and not renormalised, so t is shared by both spaces;
+ * normals return to world space as normalize(A^T n). */
+typedef struct {
+    uint32_t object_id;
+    float world_to_object[12];
+} lsnif_instance;
+
 typedef struct lsnif_ctx lsnif_ctx;
 
 typedef struct {
-    int32_t device;          /* HIP device ordinal */
+    int32_t device;          /* HIP device ordinal; -1 = a host-only context (serving dry runs) */
     uint64_t hbm_budget;     /* bytes the context may hold for objects; 0 = no limit */
     const char *autotune_cache; /* path of the tile-size cache, or NULL */
 } lsnif_ctx_desc;
@@ -101,7 +110,18 @@ typedef struct {
  *  feat_dtype     type the tables are stored in on the device (FP32/FP16/BF16).
  *  mlp_dtype      MLP arithmetic: FP32 (vector ALU) or FP16/BF16/FP8_E4M3
  *                 (matrix cores, FP32 accumulation).
- *  fp8_act_scale  n_hidden + 1 activation scales for FP8 (else NULL).
+ *  fp8_act_scale  n_hidden + 1 activation scales for FP8 (else NULL): layer k's
+ *                 input x is stored as e4m3(x / fp8_act_scale[k]); weights get a
+ *                 per-layer scale amax|W_k| / 448 at build.  All e4m3 values
+ *                 round to nearest even and saturate at +-448.
+ *  grazing_recheck 0 (default) or 1: the walk lists a visited voxel when its
+ *                 float32 slab interval overlaps [ta, tb] with positive length
+ *                 (Sec. 3.1); with 1, a voxel whose float32 overlap is at most
+ *                 2^-16 max(1, |entry|) long, or any voxel of a ray whose whole
+ *                 segment [ta, tb] is that short, is instead listed iff its
+ *                 float64 slab interval (computed from the same float32
+ *                 voxel-space origin and direction) overlaps the float64
+ *                 [ta, tb] with positive length.  t values stay float32.
  */
 typedef struct {
     float aabb_min[3];
@@ -118,6 +138,7 @@ typedef struct {
     const float *const *W;
     int32_t feat_dtype, mlp_dtype;
     const float *fp8_act_scale;
+    int32_t grazing_recheck;
 } lsnif_object_desc;
 
 /* Optional device buffers filled by lsnif_query_debug; any may be NULL. */
@@ -132,6 +153,10 @@ typedef struct {
     float *weights;      /* [n][H][L][3] interpolation weights */
     float *enc;          /* [n][H*L*F] encoding as fed to the MLP (widened to fp32) */
     float *out;          /* [n][outputs] raw network outputs */
+    float *act_amax;     /* [n_hidden + 1] largest |input| of each MLP layer over the batch,
+                            folded in with a maximum (FP32-MLP objects only); start it at 0.
+                            act_amax / 448 are the FP8 activation scales of a calibration
+                            batch. */
 } lsnif_debug_bufs;
 
 /* Context. */
@@ -164,6 +189,130 @@ lsnif_status lsnif_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_
 lsnif_status lsnif_query_debug(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays,
                                uint32_t n, lsnif_hit *d_out, const lsnif_debug_bufs *dbg,
                                void *stream);
+
+/* Nearest hit over (ray, instance) pairs (Sec. 4: the broad phase lists the
+ * pairs, the narrow phase queries each LSNIF object, and a ray's hit
+ * information is updated with the nearest hit).
+ *
+ *  d_rays       [n_rays] world-space rays.
+ *  d_pair_ray   [n_pairs] ray index of each pair; d_pair_inst the instance index.
+ *  d_inst       [n_inst] instances (object ids must name built objects).
+ *  d_out        [n_rays] per-ray result: the pair with the smallest t wins, ties
+ *               going to the lowest instance index; normal in world space.
+ *
+ * All device pointers; asynchronous on `stream`.  Pairs are grouped by object
+ * and ordered for coherence on the device; every object that the pairs name
+ * must share one kernel class (feature type, MLP type, F, width) with the
+ * other objects of the context, else LSNIF_E_INVALID.  A pair whose ray or
+ * instance index is out of range, or whose instance names no built object,
+ * contributes nothing.  Rays with no hit get the miss record. */
+lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t n_rays,
+                               const uint32_t *d_pair_ray, const uint32_t *d_pair_inst, uint32_t n_pairs,
+                               const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out,
+                               void *stream);
+
+/* ------------------------------------------------------------------ graphs
+ *
+ * A query captured once into a HIP graph and replayed with one launch.  A
+ * replay reruns the whole query (coherence sort or pair grouping, the query
+ * kernel, the nearest-hit payload) on the buffers named at capture, so the
+ * caller refills those buffers between replays; results equal the direct
+ * call's on the same inputs.  A graph owns its workspace (allocated at
+ * capture, freed by lsnif_graph_destroy) and reads the context's objects
+ * through pointers taken at capture: after any lsnif_build or lsnif_release
+ * on the context, lsnif_graph_launch returns LSNIF_E_INVALID.  Destroy every
+ * graph before its context.  The capture runs on a private stream; the
+ * context's kernel timing is not recorded inside graphs.
+ *
+ *  lsnif_graph_query  captures lsnif_query(ctx, object_id, d_rays, n, d_out).
+ *  lsnif_graph_pairs  captures lsnif_query_pairs with the same arguments.
+ *  lsnif_graph_launch enqueues one replay on `stream` (asynchronous).
+ */
+typedef struct lsnif_graph lsnif_graph;
+lsnif_status lsnif_graph_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
+                               lsnif_hit *d_out, lsnif_graph **out);
+lsnif_status lsnif_graph_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t n_rays,
+                               const uint32_t *d_pair_ray, const uint32_t *d_pair_inst, uint32_t n_pairs,
+                               const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out,
+                               lsnif_graph **out);
+lsnif_status lsnif_graph_launch(lsnif_graph *graph, void *stream);
+void lsnif_graph_destroy(lsnif_graph *graph);
+
+/* ------------------------------------------------------------------ serving
+ *
+ * Continuous batching of queries that arrive over time (requests of many
+ * sizes, single-object or instanced pairs).  A host thread admits waiting
+ * requests in arrival order as soon as a slot and workspace within the HBM
+ * budget are free, spreads admitted requests over several HIP streams so
+ * their kernels overlap on the device, and frees each request's slot and
+ * workspace when its work completes.  Results are those of the direct calls:
+ * a request's answer does not depend on what else is in flight.
+ *
+ * The serve calls are thread-safe.  The caller owns every buffer a request
+ * names and keeps it alive until the request is done; buffers are device
+ * pointers.  Objects must not be built or released while requests are
+ * admitted. */
+typedef struct {
+    uint32_t max_inflight;  /* requests admitted at once; 0 = 8 */
+    uint64_t hbm_budget;    /* bytes of query workspace admitted requests may hold; 0 = 4 GiB */
+    uint32_t n_streams;     /* HIP streams (default priority) requests are spread over; 0 = 4 */
+    uint32_t max_queue;     /* waiting requests beyond which submit returns LSNIF_E_BUSY; 0 = 65536 */
+    uint64_t dry_run_ns_per_ray; /* > 0: touch no device; a request "completes" this many ns per
+                                    ray after admission and writes nothing (tests of the
+                                    admission logic on hosts without a GPU) */
+} lsnif_serve_cfg;
+
+enum { LSNIF_REQ_SINGLE = 0, LSNIF_REQ_PAIRS = 1 };
+
+typedef struct {
+    int32_t kind;                    /* LSNIF_REQ_SINGLE (object_id, rays) or LSNIF_REQ_PAIRS */
+    uint32_t object_id;              /* single-object request: the object */
+    const lsnif_ray *d_rays;         /* [n_rays] */
+    uint32_t n_rays;
+    const uint32_t *d_pair_ray;      /* pair request: [n_pairs] ray and instance indices (may be
+                                        NULL when n_pairs is 0) */
+    const uint32_t *d_pair_inst;
+    uint32_t n_pairs;
+    const lsnif_instance *d_inst;    /* [n_inst] */
+    uint32_t n_inst;
+    lsnif_hit *d_out;                /* [n_rays] */
+    int64_t timeout_ns;              /* > 0: dropped with LSNIF_E_TIMEOUT if not admitted in time */
+} lsnif_request;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected, cancelled, timed_out, failed;
+    uint64_t queued, inflight;       /* at the time of the call */
+    uint64_t rays_completed;
+    uint64_t ws_bytes_peak;          /* most workspace held at once */
+    double p50_ms, p99_ms, mean_ms, max_ms;   /* submit -> completion, completed requests */
+    double elapsed_s;                /* since lsnif_serve_start */
+} lsnif_serve_stats;
+
+/* Request states reported by lsnif_serve_poll (negative values are the final
+ * lsnif_status of a request that did not complete). */
+enum { LSNIF_REQ_QUEUED = 0, LSNIF_REQ_RUNNING = 1, LSNIF_REQ_DONE = 2 };
+
+lsnif_status lsnif_serve_start(lsnif_ctx *ctx, const lsnif_serve_cfg *cfg);
+/* LSNIF_E_NOMEM: the request's workspace can never fit the budget;
+ * LSNIF_E_BUSY: the queue is full; LSNIF_E_INVALID / E_NOTFOUND: bad request. */
+lsnif_status lsnif_serve_submit(lsnif_ctx *ctx, const lsnif_request *req, uint64_t *ticket);
+lsnif_status lsnif_serve_poll(lsnif_ctx *ctx, uint64_t ticket, int32_t *state);
+/* Waits until the request is finished: returns its final status (LSNIF_OK when
+ * it completed), or LSNIF_E_TIMEOUT if timeout_ns (>= 0) passes first. */
+lsnif_status lsnif_serve_wait(lsnif_ctx *ctx, uint64_t ticket, int64_t timeout_ns);
+/* Cancels a waiting request (LSNIF_E_BUSY once admitted). */
+lsnif_status lsnif_serve_cancel(lsnif_ctx *ctx, uint64_t ticket);
+lsnif_status lsnif_serve_stats_get(lsnif_ctx *ctx, lsnif_serve_stats *stats);
+/* Waits for admitted requests, cancels waiting ones, stops the loop. */
+lsnif_status lsnif_serve_stop(lsnif_ctx *ctx);
+
+/* Kernel timing.  While enabled, every query on the context records HIP
+ * events on its stream before the coherence sort, between the sort and the
+ * query kernel, and after the query kernel.  lsnif_profile_read waits for the
+ * recorded queries, returns the summed sort and query-kernel milliseconds and
+ * the number of queries since the last read, and forgets them. */
+lsnif_status lsnif_profile_enable(lsnif_ctx *ctx, int32_t on);
+lsnif_status lsnif_profile_read(lsnif_ctx *ctx, double *sort_ms, double *kernel_ms, uint64_t *launches);
 
 #ifdef __cplusplus
 }

@@ -64,21 +64,22 @@ __global__ __launch_bounds__(kBlock) void k_debug(DebugArgs D)
 
 
 template <typename TF, int F>
-static void go(const QueryArgs &A, hipStream_t s)
+static void go(const QueryArgs &A, bool pairs, uint32_t grid, hipStream_t s)
 {
-    const dim3 grid((A.n + kBlock - 1) / kBlock);
+    // voxel lists of H/2 entries per lane (for pairs, H is the largest over the objects)
     const size_t lds = (size_t)(A.g.H >> 1) * kBlock * sizeof(uint32_t);
-    hipLaunchKernelGGL((k_query_f32<TF, F, 64>), grid, dim3(kBlock), lds, s, A);
+    if (pairs) hipLaunchKernelGGL((k_query_f32<TF, F, 64, true>), dim3(grid), dim3(kBlock), lds, s, A);
+    else hipLaunchKernelGGL((k_query_f32<TF, F, 64, false>), dim3(grid), dim3(kBlock), lds, s, A);
 }
 
-hipError_t launch_f32(const QueryArgs &A, int feat_dtype, int F, hipStream_t s)
+hipError_t launch_f32(const QueryArgs &A, int feat_dtype, int F, bool pairs, uint32_t grid, hipStream_t s)
 {
     if (feat_dtype == LSNIF_FP32) {
-        if (F == 2) go<float, 2>(A, s); else go<float, 3>(A, s);
+        if (F == 2) go<float, 2>(A, pairs, grid, s); else go<float, 3>(A, pairs, grid, s);
     } else if (feat_dtype == LSNIF_FP16) {
-        if (F == 2) go<_Float16, 2>(A, s); else go<_Float16, 3>(A, s);
+        if (F == 2) go<_Float16, 2>(A, pairs, grid, s); else go<_Float16, 3>(A, pairs, grid, s);
     } else {
-        if (F == 2) go<__bf16, 2>(A, s); else go<__bf16, 3>(A, s);
+        if (F == 2) go<__bf16, 2>(A, pairs, grid, s); else go<__bf16, 3>(A, pairs, grid, s);
     }
     return hipGetLastError();
 }

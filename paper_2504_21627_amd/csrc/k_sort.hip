@@ -42,32 +42,6 @@ __global__ __launch_bounds__(kBlock) void k_fill(uint32_t *p, uint32_t n, uint32
     if (i < n) p[i] = v;
 }
 
-// Lanes of a wave that share a key are served by one atomic on that key's
-// counter (issued by the lowest such lane); returns the counter's old value
-// plus this lane's rank among the lanes with its key, so equal keys of one
-// wave never contend for the same address.
-__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t *ctr, uint32_t key, bool active)
-{
-    const uint32_t lane = threadIdx.x & 63u;
-    uint64_t todo = __ballot(active);
-    uint32_t old = 0, leader = lane;
-    uint64_t mine = 0;
-    while (todo) {
-        const uint32_t l = (uint32_t)__builtin_ctzll(todo);
-        const uint32_t k = __shfl(key, l, 64);
-        const uint64_t same = __ballot(active && key == k);
-        if (active && key == k) {
-            leader = l;
-            mine = same;
-        }
-        if (lane == l) old = atomicAdd(&ctr[k], (uint32_t)__builtin_popcountll(same));
-        todo &= ~same;
-    }
-    const uint32_t base = __shfl(old, leader, 64);
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    return base + (uint32_t)__builtin_popcountll(mine & below);
-}
-
 __global__ __launch_bounds__(kBlock) void k_sort_keys(Geom g, const float4 *rays, uint32_t n, uint32_t *keys,
                                                       uint32_t *hist)
 {

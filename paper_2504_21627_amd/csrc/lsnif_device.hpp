@@ -16,6 +16,7 @@ namespace lsnif {
 constexpr int kMaxLevels = 32;
 constexpr int kMaxList = 32;          // H/2 <= 32
 constexpr int kCoarseLdsWords = 2048; // brick bits staged in LDS when the grid has <= 65536 bricks
+constexpr uint32_t kTablePad = 16;     // spare bytes after an object's tables (a paired gather may read one entry past the slot it needs)
 constexpr uint32_t kPrimeY = 2654435761u;   // spatial hash of Mueller et al. 2022, Eq. 4
 constexpr uint32_t kPrimeZ = 805459861u;
 
@@ -40,6 +41,7 @@ struct Geom {
     int32_t L, F, log2_T, H;
     uint32_t dense_mask;      // bit l: level l indexed directly ((R+1)^3 <= T)
     uint32_t aligned_mask;    // bit l: R % V == 0, the crossing-axis weight is 0 or 1
+    uint32_t recheck;         // 1: grazing voxels of the walk are re-decided in float64
     int32_t R[kMaxLevels];
     float lsc[kMaxLevels];    // (float)R / (float)V
     uint32_t my[kMaxLevels], mz[kMaxLevels], dmask[kMaxLevels], hmask[kMaxLevels];
@@ -49,7 +51,7 @@ struct Geom {
 struct VRay {
     float o[3], d[3], inv[3];
     uint32_t mov;             // bit a: axis a moves (d != 0 with a finite reciprocal)
-    float ta, tb, tmax;
+    float ta, tb, tmax, tmin;
     bool valid, cand;
 };
 
@@ -72,6 +74,7 @@ __device__ __forceinline__ void setup_ray(const Geom &g, float4 r0, float4 r1, V
     w.ta = 0.0f;
     w.tb = 0.0f;
     w.tmax = in[7];
+    w.tmin = in[6];
     bool ok = true;
 #pragma unroll
     for (int i = 0; i < 6; ++i) ok = ok && !inf_or_nan(in[i]);
@@ -193,6 +196,38 @@ __device__ __forceinline__ int start_cell(const Geom &g, const VRay &w, int a)
 // earliest exit, the lowest axis on ties.  Occupancy is read a brick at a
 // time: the coarse bit (from `coarse`, LDS or global) and, for a non-empty
 // brick, its 64-bit mask, loaded once on entering the brick.
+// Optional float64 re-decision of a voxel the float32 walk finds grazing: its
+// overlap with [ta, tb] is no longer than 2^-16 max(1, |entry|), or all of
+// [ta, tb] is that short.  The slab intervals of the voxel and of the grid are
+// recomputed in float64 (IEEE division) from the same float32 voxel-space
+// origin and direction, over the axes the float32 walk moves along, and the
+// voxel is kept iff the float64 overlap has positive length.  Only whether a
+// visited voxel is listed changes; its t values stay float32.
+__device__ __forceinline__ bool grazing(float tin, float tout, float ta, float tb)
+{
+    const float lo = fmax2(tin, ta), hi = fmin2(tout, tb);
+    const float q = 0x1p-16f;
+    return hi - lo <= q * fmax2(1.0f, __builtin_fabsf(tin)) || tb - ta <= q * fmax2(1.0f, __builtin_fabsf(ta));
+}
+
+__device__ __forceinline__ bool keep_f64(const VRay &w, const int c[3], int V)
+{
+    double t0 = -__builtin_inf(), t1 = __builtin_inf(), tin = -__builtin_inf(), tout = __builtin_inf();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!(w.mov & (1u << a))) continue;
+        const double o = w.o[a], d = w.d[a];
+        const double g0 = (0.0 - o) / d, g1 = ((double)V - o) / d;
+        const double e0 = ((double)c[a] - o) / d, e1 = ((double)(c[a] + 1) - o) / d;
+        t0 = __builtin_fmax(t0, __builtin_fmin(g0, g1));
+        t1 = __builtin_fmin(t1, __builtin_fmax(g0, g1));
+        tin = __builtin_fmax(tin, __builtin_fmin(e0, e1));
+        tout = __builtin_fmin(tout, __builtin_fmax(e0, e1));
+    }
+    const double ta = __builtin_fmax(t0, (double)w.tmin), tb = t1;
+    return __builtin_fmin(tout, tb) > __builtin_fmax(tin, ta);
+}
+
 __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, const uint32_t *coarse,
                                            uint32_t *list, int stride, int cap)
 {
@@ -223,7 +258,9 @@ __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, const u
                 if (oa < 0 || ex[a] < tout) { tout = ex[a]; oa = a; }
             }
         }
-        if (fmin2(tout, w.tb) > fmax2(tin, w.ta)) {
+        bool keep = fmin2(tout, w.tb) > fmax2(tin, w.ta);
+        if (g.recheck && grazing(tin, tout, w.ta, w.tb)) keep = keep_f64(w, c, V);
+        if (keep) {
             const uint32_t b = brick_of(g, c);
             if (b != cur) {
                 cur = b;

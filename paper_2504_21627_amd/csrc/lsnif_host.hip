@@ -7,19 +7,18 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
-#include "lsnif_kernels.hpp"
-#include "lsnif_launch.hpp"
-#include "../../include/lsnif.h"
+#include "lsnif_internal.hpp"
 
 using namespace lsnif;
 
-namespace {
+namespace lsnif {
 
 thread_local std::string g_err;
 
@@ -34,12 +33,9 @@ lsnif_status fail(lsnif_status st, const char *fmt, ...)
     return st;
 }
 
-#define HIP_TRY(expr)                                                                  \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(LSNIF_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
+}  // namespace lsnif
+
+namespace {
 
 size_t dtype_size(int t) { return t == LSNIF_FP32 ? 4 : (t == LSNIF_FP8_E4M3 ? 1 : 2); }
 
@@ -60,49 +56,34 @@ uint16_t f32_to_bf16(float x)
     return (uint16_t)(u >> 16);
 }
 
+// OCP FP8 E4M3 (bias 7, no infinities, largest finite 448), round to nearest
+// even, saturating at +-448.
+uint8_t f32_to_e4m3(float x)
+{
+    if (x != x) return 0x7f;
+    const uint8_t sign = std::signbit(x) ? 0x80 : 0x00;
+    double a = std::fabs((double)x);
+    if (a >= 448.0) return sign | 0x7e;
+    if (a < std::ldexp(1.0, -6)) {                       // subnormal: multiples of 2^-9
+        const double q = std::nearbyint(a * 512.0);      // ties to even (default rounding mode)
+        return sign | (uint8_t)q;                        // q == 8 is the smallest normal, 0x08
+    }
+    int e;
+    const double m = std::frexp(a, &e);                  // a = m 2^e, m in [0.5, 1)
+    double q = std::nearbyint((m * 2.0 - 1.0) * 8.0);    // 3 mantissa bits
+    int E = e - 1;
+    if (q == 8.0) { q = 0.0; ++E; }
+    if (E > 8 || (E == 8 && q > 6.0)) return sign | 0x7e;
+    return sign | (uint8_t)(((E + 7) << 3) | (int)q);
+}
+
 void store_elem(void *dst, size_t i, float v, int dtype)
 {
     if (dtype == LSNIF_FP32) static_cast<float *>(dst)[i] = v;
     else if (dtype == LSNIF_FP16) static_cast<uint16_t *>(dst)[i] = f32_to_f16(v);
-    else static_cast<uint16_t *>(dst)[i] = f32_to_bf16(v);
+    else if (dtype == LSNIF_BF16) static_cast<uint16_t *>(dst)[i] = f32_to_bf16(v);
+    else static_cast<uint8_t *>(dst)[i] = f32_to_e4m3(v);
 }
-
-struct Object {
-    Geom geom{};
-    Mlp mlp{};
-    void *d_occ = nullptr, *d_tab = nullptr, *d_w = nullptr;   // d_occ: brick masks, then brick bits
-    int feat_dtype = 0, mlp_dtype = 0, F = 0, width = 0;
-    uint64_t bytes = 0;
-};
-
-}  // namespace
-
-struct lsnif_ctx {
-    int device = 0;
-    uint64_t budget = 0;
-    uint64_t used = 0;
-    uint32_t next_id = 1;
-    std::map<uint32_t, Object> objects;
-    // query workspace (coherence-sort keys, order and bin counters); grown on demand
-    void *ws = nullptr;
-    size_t ws_bytes = 0;
-};
-
-namespace {
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
 
 int out_dim_of(const lsnif_object_desc *d) { return 5 + 3 * (d->has_albedo ? 1 : 0) + d->n_mat; }
 
@@ -143,7 +124,12 @@ lsnif_status supported(const lsnif_object_desc *d)
 {
     if (d->F != 2 && d->F != 3) return fail(LSNIF_E_INVALID, "kernels support F = 2 or 3 (got %d)", d->F);
     if (d->width != 64) return fail(LSNIF_E_INVALID, "kernels support width 64 (got %d)", d->width);
-    if (d->mlp_dtype == LSNIF_FP8_E4M3) return fail(LSNIF_E_INVALID, "FP8 MLP is not available in this build");
+    if (d->mlp_dtype == LSNIF_FP8_E4M3) {
+        if (!d->fp8_act_scale) return fail(LSNIF_E_INVALID, "an FP8 MLP needs fp8_act_scale");
+        for (int k = 0; k <= d->n_hidden; ++k)
+            if (!(d->fp8_act_scale[k] > 0.0f) || !std::isfinite(d->fp8_act_scale[k]))
+                return fail(LSNIF_E_INVALID, "fp8_act_scale[%d] must be positive and finite", k);
+    }
     return LSNIF_OK;
 }
 
@@ -241,10 +227,12 @@ lsnif_status lsnif_create(const lsnif_ctx_desc *desc, lsnif_ctx **out)
 {
     if (!out) return fail(LSNIF_E_INVALID, "out is NULL");
     *out = nullptr;
-    int dev = desc ? desc->device : 0;
-    int n = 0;
-    HIP_TRY(hipGetDeviceCount(&n));
-    if (dev < 0 || dev >= n) return fail(LSNIF_E_INVALID, "device %d not in [0, %d)", dev, n);
+    const int dev = desc ? desc->device : 0;
+    if (dev != -1) {
+        int n = 0;
+        HIP_TRY(hipGetDeviceCount(&n));
+        if (dev < 0 || dev >= n) return fail(LSNIF_E_INVALID, "device %d not in [0, %d)", dev, n);
+    }
     lsnif_ctx *c = new (std::nothrow) lsnif_ctx();
     if (!c) return fail(LSNIF_E_NOMEM, "host allocation failed");
     c->device = dev;
@@ -256,6 +244,11 @@ lsnif_status lsnif_create(const lsnif_ctx_desc *desc, lsnif_ctx **out)
 void lsnif_destroy(lsnif_ctx *ctx)
 {
     if (!ctx) return;
+    destroy_server(ctx);
+    if (ctx->device < 0) {
+        delete ctx;
+        return;
+    }
     DeviceGuard g(ctx->device);
     for (auto &kv : ctx->objects) {
         (void)hipFree(kv.second.d_occ);
@@ -263,6 +256,11 @@ void lsnif_destroy(lsnif_ctx *ctx)
         (void)hipFree(kv.second.d_w);
     }
     (void)hipFree(ctx->ws);
+    (void)hipFree(ctx->d_table);
+    (void)hipFree(ctx->pws);
+    for (auto &v : ctx->pending)
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -278,6 +276,8 @@ lsnif_status lsnif_desc_bytes(const lsnif_object_desc *desc, uint64_t *bytes)
 lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *object_id)
 {
     if (!ctx || !object_id) return fail(LSNIF_E_INVALID, "ctx or object_id is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->device < 0) return fail(LSNIF_E_DEVICE, "host-only context");
     lsnif_status st = validate(d);
     if (st) return st;
     if ((st = supported(d))) return st;
@@ -297,6 +297,7 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
     g.F = d->F;
     g.log2_T = d->log2_T;
     g.H = d->H;
+    g.recheck = d->grazing_recheck ? 1u : 0u;
     const uint64_t T = (uint64_t)1 << d->log2_T;
     for (int l = 0; l < d->L; ++l) {
         g.R[l] = d->R[l];
@@ -343,8 +344,26 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
     if (d->mlp_dtype == LSNIF_FP32) wf = pack_f32(d, ob.mlp.off);
     else wf = pack_mma(d, ob.mlp.off, KB);
     const int wdt = d->mlp_dtype == LSNIF_FP32 ? LSNIF_FP32 : d->mlp_dtype;
+    for (int k = 0; k < 8; ++k) {
+        ob.mlp.qs[k] = 1.0f;
+        ob.mlp.dq[k] = 1.0f;
+    }
+    if (wdt == LSNIF_FP8_E4M3) {
+        // per-layer weight scale amax|W| / 448; the stored values are W / scale
+        for (int k = 0; k <= d->n_hidden; ++k) {
+            const size_t b = (size_t)ob.mlp.off[k], e = k < d->n_hidden ? (size_t)ob.mlp.off[k + 1] : wf.size();
+            float amax = 0.0f;
+            for (size_t i = b; i < e; ++i) amax = std::max(amax, std::fabs(wf[i]));
+            const float sw = amax > 0.0f ? amax / 448.0f : 1.0f;
+            for (size_t i = b; i < e; ++i) wf[i] /= sw;
+            ob.mlp.qs[k] = 1.0f / d->fp8_act_scale[k];
+            ob.mlp.dq[k] = sw * d->fp8_act_scale[k];
+        }
+    }
     std::vector<uint8_t> wbytes(wf.size() * dtype_size(wdt));
     for (size_t i = 0; i < wf.size(); ++i) store_elem(wbytes.data(), i, wf[i], wdt);
+    if (wdt != LSNIF_FP32)
+        for (int k = 0; k <= d->n_hidden; ++k) ob.mlp.woff[k] = (int32_t)((size_t)ob.mlp.off[k] * dtype_size(wdt) / 4);
     ob.bytes = occ_bytes + tab.size() + wbytes.size();
     if (ctx->budget && ctx->used + ob.bytes > ctx->budget)
         return fail(LSNIF_E_NOMEM, "object needs %llu bytes, %llu of %llu in use", (unsigned long long)ob.bytes,
@@ -354,6 +373,7 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
         (void)hipFree(ob.d_tab);
         (void)hipFree(ob.d_w);
     };
+    tab.resize(tab.size() + kTablePad, 0);   // not counted in the footprint
     if (hipMalloc(&ob.d_occ, occ_bytes) != hipSuccess || hipMalloc(&ob.d_tab, tab.size()) != hipSuccess ||
         hipMalloc(&ob.d_w, wbytes.size()) != hipSuccess) {
         cleanup();
@@ -380,6 +400,8 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
     const uint32_t id = ctx->next_id++;
     ctx->objects[id] = ob;
     ctx->used += ob.bytes;
+    ctx->table_dirty = true;
+    ++ctx->generation;
     *object_id = id;
     return LSNIF_OK;
 }
@@ -387,14 +409,18 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
 lsnif_status lsnif_release(lsnif_ctx *ctx, uint32_t object_id)
 {
     if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     auto it = ctx->objects.find(object_id);
     if (it == ctx->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", object_id);
     DeviceGuard guard(ctx->device);
+    (void)hipDeviceSynchronize();   // queries in flight may still read the object
     (void)hipFree(it->second.d_occ);
     (void)hipFree(it->second.d_tab);
     (void)hipFree(it->second.d_w);
     ctx->used -= it->second.bytes;
     ctx->objects.erase(it);
+    ctx->table_dirty = true;
+    ++ctx->generation;
     return LSNIF_OK;
 }
 
@@ -407,70 +433,80 @@ lsnif_status lsnif_object_bytes(lsnif_ctx *ctx, uint32_t object_id, uint64_t *by
     return LSNIF_OK;
 }
 
-// Batches below this size are processed in the order given.
-constexpr uint32_t kSortMin = 8192;
-
-static lsnif_status ensure_workspace(lsnif_ctx *ctx, uint32_t n)
+lsnif_status lsnif_profile_enable(lsnif_ctx *ctx, int32_t on)
 {
-    const size_t need = ((size_t)2 * n + kSortBins + kSortScanBlocks) * sizeof(uint32_t);
-    if (need <= ctx->ws_bytes) return LSNIF_OK;
-    (void)hipFree(ctx->ws);   // waits for work that may still use the old buffer
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
-    if (hipMalloc(&ctx->ws, need) != hipSuccess)
-        return fail(LSNIF_E_NOMEM, "workspace of %llu bytes", (unsigned long long)need);
-    ctx->ws_bytes = need;
+    if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    ctx->profiling = on != 0;
     return LSNIF_OK;
 }
+
+lsnif_status lsnif_profile_read(lsnif_ctx *ctx, double *sort_ms, double *kernel_ms, uint64_t *launches)
+{
+    if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    double so = 0.0, kq = 0.0;
+    const uint64_t k = ctx->pending.size();
+    lsnif_status st = LSNIF_OK;
+    for (auto &v : ctx->pending) {
+        float a = 0.0f, b = 0.0f;
+        if (st == LSNIF_OK &&
+            (hipEventSynchronize(v[2]) != hipSuccess || hipEventElapsedTime(&a, v[0], v[1]) != hipSuccess ||
+             hipEventElapsedTime(&b, v[1], v[2]) != hipSuccess))
+            st = fail(LSNIF_E_DEVICE, "reading query events failed");
+        so += a;
+        kq += b;
+        for (hipEvent_t e : v) ctx->spare.push_back(e);
+    }
+    ctx->pending.clear();
+    if (sort_ms) *sort_ms = so;
+    if (kernel_ms) *kernel_ms = kq;
+    if (launches) *launches = k;
+    return st;
+}
+
+static lsnif_status grow(void *&buf, size_t &have, size_t need)
+{
+    if (need <= have) return LSNIF_OK;
+    (void)hipFree(buf);   // waits for work that may still use the old buffer
+    buf = nullptr;
+    have = 0;
+    if (hipMalloc(&buf, need) != hipSuccess)
+        return fail(LSNIF_E_NOMEM, "workspace of %llu bytes", (unsigned long long)need);
+    have = need;
+    return LSNIF_OK;
+}
+
 
 static lsnif_status run_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
                               lsnif_hit *d_out, const lsnif_debug_bufs *dbg, void *stream)
 {
     if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
-    auto it = ctx->objects.find(object_id);
-    if (it == ctx->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", object_id);
-    if (n == 0) return LSNIF_OK;
-    if (!d_rays || !d_out) return fail(LSNIF_E_INVALID, "rays or output is NULL");
-    if (reinterpret_cast<uintptr_t>(d_rays) % 16 || reinterpret_cast<uintptr_t>(d_out) % 4)
-        return fail(LSNIF_E_INVALID, "rays must be 16-byte and hits 4-byte aligned");
-    const Object &ob = it->second;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->device < 0) return fail(LSNIF_E_DEVICE, "host-only context");
+    const Object *ob = nullptr;
+    lsnif_status st = check_query(ctx, object_id, d_rays, n, d_out, ob);
+    if (st || n == 0) return st;
     DeviceGuard guard(ctx->device);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    QueryArgs A{};
-    A.g = ob.geom;
-    A.m = ob.mlp;
-    A.tables = ob.d_tab;
-    A.rays = reinterpret_cast<const float4 *>(d_rays);
-    A.hits = d_out;
-    A.n = n;
-    if (dbg) {
-        DebugArgs D{};
-        D.g = ob.geom;
-        D.rays = A.rays;
-        D.n = n;
-        D.b = *dbg;
-        D.b.count = nullptr;
-        D.b.tatb = nullptr;
-        D.b.enc = nullptr;
-        D.b.out = nullptr;
-        HIP_TRY(launch_debug(D, s));
-        A.dbg.count = dbg->count;
-        A.dbg.tatb = dbg->tatb;
-        A.dbg.out = dbg->out;
-        A.dbg.enc = dbg->enc;
-    }
-    if (n >= kSortMin) {
-        lsnif_status st = ensure_workspace(ctx, n);
-        if (st) return st;
-        uint32_t *keys = static_cast<uint32_t *>(ctx->ws);
-        uint32_t *order = keys + n;
-        uint32_t *hist = order + n;
-        HIP_TRY(launch_coherence_sort(ob.geom, A.rays, n, keys, hist, order, s));
-        A.order = order;
-    }
-    if (ob.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, ob.feat_dtype, ob.F, s));
-    else HIP_TRY(launch_mma(A, ob.feat_dtype, ob.mlp_dtype, ob.F, s));
-    return LSNIF_OK;
+    if (n >= kSortMin && (st = grow(ctx->ws, ctx->ws_bytes, query_ws_bytes(n)))) return st;
+    return enqueue_query(ctx, *ob, d_rays, n, d_out, dbg, static_cast<hipStream_t>(stream), ctx->ws);
+}
+
+lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t n_rays, const uint32_t *d_pair_ray,
+                               const uint32_t *d_pair_inst, uint32_t n_pairs, const lsnif_instance *d_inst,
+                               uint32_t n_inst, lsnif_hit *d_out, void *stream)
+{
+    if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (n_rays == 0) return LSNIF_OK;
+    if (ctx->device < 0) return fail(LSNIF_E_DEVICE, "host-only context");
+    DeviceGuard guard(ctx->device);
+    PairsSetup ps;
+    lsnif_status st = pairs_setup(ctx, ps);
+    if (st) return st;
+    if ((st = grow(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs)))) return st;
+    return enqueue_pairs(ctx, ps, d_rays, n_rays, d_pair_ray, d_pair_inst, n_pairs, d_inst, n_inst, d_out,
+                         static_cast<hipStream_t>(stream), ctx->pws);
 }
 
 lsnif_status lsnif_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
@@ -487,3 +523,228 @@ lsnif_status lsnif_query_debug(lsnif_ctx *ctx, uint32_t object_id, const lsnif_r
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ enqueue
+namespace lsnif {
+
+lsnif_status check_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
+                         lsnif_hit *d_out, const Object *&ob)
+{
+    if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
+    auto it = ctx->objects.find(object_id);
+    if (it == ctx->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", object_id);
+    ob = &it->second;
+    if (n == 0) return LSNIF_OK;
+    if (!d_rays || !d_out) return fail(LSNIF_E_INVALID, "rays or output is NULL");
+    if (reinterpret_cast<uintptr_t>(d_rays) % 16 || reinterpret_cast<uintptr_t>(d_out) % 4)
+        return fail(LSNIF_E_INVALID, "rays must be 16-byte and hits 4-byte aligned");
+    return LSNIF_OK;
+}
+
+static hipEvent_t take_event(lsnif_ctx *ctx)
+{
+    if (!ctx->spare.empty()) {
+        hipEvent_t e = ctx->spare.back();
+        ctx->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+size_t query_ws_bytes(uint32_t n)
+{
+    return n >= kSortMin ? ((size_t)2 * n + kSortBins + kSortScanBlocks) * sizeof(uint32_t) : 0;
+}
+
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs)
+{
+    const size_t n_slots = (size_t)(n_pairs + kBlock - 1) / kBlock * kBlock + (size_t)kBlock * n_objs;
+    return al256((size_t)n_rays * 8) + al256((size_t)n_pairs * sizeof(PairRes)) + al256((size_t)n_pairs * 4) +
+           al256(n_slots * 4) + al256(n_slots / kBlock * 4) + al256((size_t)n_objs * kPairBins * 4) +
+           2 * al256((size_t)n_objs * 4);
+}
+
+lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
+                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws)
+{
+    QueryArgs A{};
+    A.g = ob.geom;
+    A.m = ob.mlp;
+    A.tables = ob.d_tab;
+    A.rays = reinterpret_cast<const float4 *>(d_rays);
+    A.hits = d_out;
+    A.n = n;
+    if (dbg) {
+        if (dbg->act_amax && ob.mlp_dtype != LSNIF_FP32)
+            return fail(LSNIF_E_INVALID, "act_amax is reported by objects with an FP32 MLP");
+        DebugArgs D{};
+        D.g = ob.geom;
+        D.rays = A.rays;
+        D.n = n;
+        D.b = *dbg;
+        D.b.count = nullptr;
+        D.b.tatb = nullptr;
+        D.b.enc = nullptr;
+        D.b.out = nullptr;
+        HIP_TRY(launch_debug(D, s));
+        A.dbg.count = dbg->count;
+        A.dbg.tatb = dbg->tatb;
+        A.dbg.out = dbg->out;
+        A.dbg.enc = dbg->enc;
+        A.dbg.act_amax = dbg->act_amax;
+    }
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (ctx->profiling) {
+        for (auto &e : ev)
+            if (!(e = take_event(ctx))) return fail(LSNIF_E_DEVICE, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(ev[0], s));
+    }
+    if (n >= kSortMin) {
+        uint32_t *keys = static_cast<uint32_t *>(ws);
+        uint32_t *order = keys + n;
+        uint32_t *hist = order + n;
+        HIP_TRY(launch_coherence_sort(ob.geom, A.rays, n, keys, hist, order, s));
+        A.order = order;
+    }
+    if (ev[1]) HIP_TRY(hipEventRecord(ev[1], s));
+    const uint32_t grid = (n + kBlock - 1) / kBlock;
+    const int kbm = ob.mlp.kb_point;
+    if (ob.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, ob.feat_dtype, ob.F, false, grid, s));
+    else if (ob.mlp_dtype == LSNIF_FP16) HIP_TRY(launch_mma_f16(A, ob.feat_dtype, ob.F, kbm, false, grid, s));
+    else if (ob.mlp_dtype == LSNIF_BF16) HIP_TRY(launch_mma_bf16(A, ob.feat_dtype, ob.F, kbm, false, grid, s));
+    else HIP_TRY(launch_mma_fp8(A, ob.feat_dtype, ob.F, kbm, false, grid, s));
+    if (ev[2]) {
+        HIP_TRY(hipEventRecord(ev[2], s));
+        ctx->pending.push_back({ev[0], ev[1], ev[2]});
+    }
+    return LSNIF_OK;
+}
+
+static lsnif_status upload_table(lsnif_ctx *ctx, uint32_t &n_objs)
+{
+    n_objs = ctx->objects.empty() ? 1u : ctx->objects.rbegin()->first + 1u;
+    if (!ctx->table_dirty && ctx->d_table) return LSNIF_OK;
+    std::vector<ObjDev> t(n_objs);
+    memset(t.data(), 0, t.size() * sizeof(ObjDev));
+    for (auto &kv : ctx->objects) {
+        ObjDev &d = t[kv.first];
+        d.g = kv.second.geom;
+        d.m = kv.second.mlp;
+        d.tables = kv.second.d_tab;
+        d.live = 1;
+        d.kb_point = kv.second.mlp.kb_point;
+    }
+    const size_t bytes = t.size() * sizeof(ObjDev);
+    // earlier queries may still read the old table
+    HIP_TRY(hipDeviceSynchronize());
+    if (bytes > ctx->table_cap) {
+        (void)hipFree(ctx->d_table);
+        ctx->d_table = nullptr;
+        ctx->table_cap = 0;
+        if (hipMalloc(&ctx->d_table, bytes) != hipSuccess) return fail(LSNIF_E_NOMEM, "object table");
+        ctx->table_cap = bytes;
+    }
+    HIP_TRY(hipMemcpy(ctx->d_table, t.data(), bytes, hipMemcpyHostToDevice));
+    ctx->table_dirty = false;
+    return LSNIF_OK;
+}
+
+lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps)
+{
+    if (ctx->objects.empty()) return fail(LSNIF_E_NOTFOUND, "no objects built");
+    ps.first = &ctx->objects.begin()->second;
+    ps.kbm = 1;
+    ps.maxH = 2;
+    for (auto &kv : ctx->objects) {
+        if (!same_class(kv.second, *ps.first))
+            return fail(LSNIF_E_INVALID, "pair queries need every object of the context in one kernel class "
+                                         "(feature type, MLP type, F, width)");
+        ps.kbm = std::max(ps.kbm, kv.second.mlp.kb_point);
+        ps.maxH = std::max(ps.maxH, kv.second.geom.H);
+    }
+    return upload_table(ctx, ps.n_objs);
+}
+
+lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray *d_rays, uint32_t n_rays,
+                           const uint32_t *d_pair_ray, const uint32_t *d_pair_inst, uint32_t n_pairs,
+                           const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out, hipStream_t s, void *ws)
+{
+    if (!d_rays || !d_out || (n_pairs && (!d_pair_ray || !d_pair_inst || !d_inst)))
+        return fail(LSNIF_E_INVALID, "NULL buffer");
+    if (reinterpret_cast<uintptr_t>(d_rays) % 16 || reinterpret_cast<uintptr_t>(d_out) % 4)
+        return fail(LSNIF_E_INVALID, "rays must be 16-byte and hits 4-byte aligned");
+    const Object &first = *ps.first;
+    const uint32_t n_objs = ps.n_objs;
+    const uint32_t n_slots = (n_pairs + kBlock - 1) / kBlock * kBlock + kBlock * n_objs;
+    const uint32_t n_tiles = n_slots / kBlock;
+    char *w = static_cast<char *>(ws);
+    PairPlan P{};
+    P.rays = reinterpret_cast<const float4 *>(d_rays);
+    P.n_rays = n_rays;
+    P.pair_ray = d_pair_ray;
+    P.pair_inst = d_pair_inst;
+    P.n_pairs = n_pairs;
+    P.inst = d_inst;
+    P.n_inst = n_inst;
+    P.objs = static_cast<const ObjDev *>(ctx->d_table);
+    P.n_objs = n_objs;
+    P.out = d_out;
+    P.minkey = reinterpret_cast<unsigned long long *>(w);
+    w += al256((size_t)n_rays * 8);
+    P.res = reinterpret_cast<PairRes *>(w);
+    w += al256((size_t)n_pairs * sizeof(PairRes));
+    P.keys = reinterpret_cast<uint32_t *>(w);
+    w += al256((size_t)n_pairs * 4);
+    P.slot_pair = reinterpret_cast<uint32_t *>(w);
+    w += al256((size_t)n_slots * 4);
+    P.tile_obj = reinterpret_cast<int32_t *>(w);
+    w += al256((size_t)n_tiles * 4);
+    P.hist = reinterpret_cast<uint32_t *>(w);
+    w += al256((size_t)n_objs * kPairBins * 4);
+    P.obj_total = reinterpret_cast<uint32_t *>(w);
+    w += al256((size_t)n_objs * 4);
+    P.obj_off = reinterpret_cast<uint32_t *>(w);
+    P.n_slots = n_slots;
+    P.n_tiles = n_tiles;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    if (ctx->profiling) {
+        for (auto &e : ev)
+            if (!(e = take_event(ctx))) return fail(LSNIF_E_DEVICE, "hipEventCreate failed");
+        HIP_TRY(hipEventRecord(ev[0], s));
+    }
+    HIP_TRY(launch_pairs_prepare(P, s));
+    if (ev[1]) HIP_TRY(hipEventRecord(ev[1], s));
+    if (n_pairs) {
+        QueryArgs A{};
+        A.g.H = ps.maxH;
+        A.rays = P.rays;
+        A.n = n_slots;
+        A.pr.pair_ray = d_pair_ray;
+        A.pr.pair_inst = d_pair_inst;
+        A.pr.inst = d_inst;
+        A.pr.objs = P.objs;
+        A.pr.tile_obj = P.tile_obj;
+        A.pr.slot_pair = P.slot_pair;
+        A.pr.minkey = P.minkey;
+        A.pr.res = P.res;
+        const int kbm = ps.kbm;
+        if (first.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, first.feat_dtype, first.F, true, n_tiles, s));
+        else if (first.mlp_dtype == LSNIF_FP16)
+            HIP_TRY(launch_mma_f16(A, first.feat_dtype, first.F, kbm, true, n_tiles, s));
+        else if (first.mlp_dtype == LSNIF_BF16)
+            HIP_TRY(launch_mma_bf16(A, first.feat_dtype, first.F, kbm, true, n_tiles, s));
+        else HIP_TRY(launch_mma_fp8(A, first.feat_dtype, first.F, kbm, true, n_tiles, s));
+    }
+    if (ev[2]) {
+        HIP_TRY(hipEventRecord(ev[2], s));
+        ctx->pending.push_back({ev[0], ev[1], ev[2]});
+    }
+    HIP_TRY(launch_pairs_payload(P, s));
+    return LSNIF_OK;
+}
+
+}  // namespace lsnif

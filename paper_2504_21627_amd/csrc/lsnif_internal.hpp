@@ -1,0 +1,116 @@
+// Internals shared by the host units of the library: the context, the object
+// record, error reporting and the enqueue functions behind the query calls.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <condition_variable>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lsnif_kernels.hpp"
+#include "lsnif_launch.hpp"
+#include "lsnif_pairs.hpp"
+#include "../../include/lsnif.h"
+
+namespace lsnif {
+
+// Records a message for lsnif_last_error() (per thread) and returns `st`.
+lsnif_status fail(lsnif_status st, const char *fmt, ...);
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::lsnif::fail(LSNIF_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct Object {
+    Geom geom{};
+    Mlp mlp{};
+    void *d_occ = nullptr, *d_tab = nullptr, *d_w = nullptr;   // d_occ: brick masks, then brick bits
+    int feat_dtype = 0, mlp_dtype = 0, F = 0, width = 0;
+    uint64_t bytes = 0;
+};
+
+// Objects that one query kernel can serve together.
+inline bool same_class(const Object &a, const Object &b)
+{
+    return a.feat_dtype == b.feat_dtype && a.mlp_dtype == b.mlp_dtype && a.F == b.F && a.width == b.width;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+class Server;
+void destroy_server(lsnif_ctx *ctx);   // stops a running serving loop
+
+// Batches below this size are processed in the order given (no coherence sort).
+constexpr uint32_t kSortMin = 8192;
+
+// Workspace bytes of one query of n rays, and of one pair query.
+size_t query_ws_bytes(uint32_t n);
+size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs);
+
+}  // namespace lsnif
+
+struct lsnif_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    uint32_t next_id = 1;
+    std::map<uint32_t, lsnif::Object> objects;
+    // query workspaces of the direct calls (coherence sort; pair work lists), grown on demand
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    void *pws = nullptr;
+    size_t pws_bytes = 0;
+    // device copy of the object table for pair queries, indexed by object id
+    void *d_table = nullptr;
+    size_t table_cap = 0;
+    bool table_dirty = true;
+    // bumped by every build and release: graphs captured before are stale
+    uint64_t generation = 0;
+    // kernel timing: per query, events before the sort, before and after the query kernel
+    bool profiling = false;
+    std::vector<std::vector<hipEvent_t>> pending;
+    std::vector<hipEvent_t> spare;
+    // serving loop, when started; `mu` orders the direct calls against it
+    lsnif::Server *server = nullptr;
+    std::recursive_mutex mu;
+};
+
+namespace lsnif {
+
+// Class of the objects a pair query can reach, uploaded object table included.
+struct PairsSetup {
+    const Object *first = nullptr;
+    int kbm = 1, maxH = 2;
+    uint32_t n_objs = 0;
+};
+lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps);
+// Object `object_id` of ctx and the checks every single-object query makes.
+lsnif_status check_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
+                         const Object *&ob);
+
+// Enqueue one query on `s`.  `ws` must hold query_ws_bytes(n) (pairs_ws_bytes for
+// pairs) bytes and stay untouched until the stream has run the query.
+lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
+                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws);
+lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray *d_rays, uint32_t n_rays,
+                           const uint32_t *d_pair_ray, const uint32_t *d_pair_inst, uint32_t n_pairs,
+                           const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out, hipStream_t s, void *ws);
+
+}  // namespace lsnif

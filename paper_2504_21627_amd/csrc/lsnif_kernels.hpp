@@ -35,6 +35,9 @@ struct Mlp {
     int32_t n_mat, has_albedo;
     int32_t kb_point;         // matrix-core path: K blocks (16 wide) per boundary point
     int32_t fp;               // matrix-core path: features per level after padding
+    int32_t woff[8];          // matrix-core path: dword offset of each layer's fragments
+    float qs[8];              // FP8: 1 / activation scale of each layer's input (1 otherwise)
+    float dq[8];              // FP8: weight scale x activation scale of each layer (1 otherwise)
 };
 
 struct Dbg {
@@ -42,6 +45,34 @@ struct Dbg {
     float *tatb;
     float *out;
     float *enc;
+    float *act_amax;          // float32 path: largest |input| of each layer, for FP8 scales
+};
+
+// Result of one (ray, instance) pair, kept until the nearest hit is known.
+struct PairRes {
+    float t;                  // +inf on a miss
+    float n[3];               // object-space normal
+    int32_t material;
+};
+
+// A built object as the pair kernels see it (device object table, indexed by id).
+struct ObjDev {
+    Geom g;
+    Mlp m;
+    const void *tables;
+    int32_t live;
+    int32_t kb_point;
+};
+
+struct PairArgs {
+    const uint32_t *pair_ray;
+    const uint32_t *pair_inst;
+    const lsnif_instance *inst;
+    const ObjDev *objs;
+    const int32_t *tile_obj;      // object id of each 256-slot tile, -1 for none
+    const uint32_t *slot_pair;    // pair index of each sorted slot, 0xffffffff for padding
+    unsigned long long *minkey;   // per ray: (ordered t << 32) | instance of the nearest hit
+    PairRes *res;                 // per pair
 };
 
 struct QueryArgs {
@@ -50,10 +81,40 @@ struct QueryArgs {
     const void *tables;       // [L][T][F] in the feature type
     const float4 *rays;
     lsnif_hit *hits;
-    uint32_t n;
+    uint32_t n;               // rays (single object) or sorted pair slots (pairs)
     const uint32_t *order;    // processing order of the rays (coherence sort), or NULL
     Dbg dbg;
+    PairArgs pr;
 };
+
+// Order-preserving map of a float to 32 unsigned bits.
+__device__ __forceinline__ uint32_t ordered_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Instance transform x_obj = A x + b (row-major 3x4), evaluated in the order
+// ((m0 x + m1 y) + m2 z) + m3; directions are not renormalised, so t is
+// shared by both spaces.  An invalid world ray stays invalid.
+__device__ __forceinline__ void to_object_space(const lsnif_instance &I, float4 &r0, float4 &r1)
+{
+    const float in[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ok = ok && (__builtin_fabsf(in[i]) <= 3.402823466e38f);
+    ok = ok && (in[6] == in[6]) && (in[7] == in[7]);
+    ok = ok && !(in[3] == 0.0f && in[4] == 0.0f && in[5] == 0.0f) && !(in[6] > in[7]);
+    float o[3], d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float *m = I.world_to_object + 4 * a;
+        o[a] = ((m[0] * in[0] + m[1] * in[1]) + m[2] * in[2]) + m[3];
+        d[a] = (m[0] * in[3] + m[1] * in[4]) + m[2] * in[5];
+    }
+    r0 = make_float4(ok ? o[0] : __builtin_nanf(""), o[1], o[2], d[0]);
+    r1 = make_float4(d[1], d[2], in[6], in[7]);
+}
 
 template <typename TF> __device__ __forceinline__ float to_f32(TF v);
 template <> __device__ __forceinline__ float to_f32<float>(float v) { return v; }
@@ -126,8 +187,8 @@ template <typename TF, int F> struct Entry {
 // set to the selected one, so the 4 zero-weight corners re-read the 4 face
 // corners instead of touching other table entries.
 template <typename TF, int F, int NL>
-__device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restrict__ tab, int l0,
-                                              const float p[3], int face, float out[NL][F])
+__device__ __forceinline__ void encode_levels_corners(const Geom &g, const TF *__restrict__ tab, int l0,
+                                                      const float p[3], int face, float out[NL][F])
 {
     const char *base[NL];
     uint32_t off[NL][8];
@@ -189,9 +250,207 @@ __device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restric
     }
 }
 
+// Cell of point p on level l, as level_cell, with the clamps as min/max.
+__device__ __forceinline__ void level_cell_mm(const Geom &g, int l, const float p[3], uint32_t i[3], float wt[3])
+{
+    const float Rf = (float)g.R[l], sc = g.lsc[l];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const float x = __builtin_fminf(__builtin_fmaxf(p[b] * sc, 0.0f), Rf);
+        const float k = __builtin_fminf(__builtin_floorf(x), Rf - 1.0f);
+        i[b] = (uint32_t)k;
+        wt[b] = x - k;
+    }
+}
+
+// Two table entries side by side, loaded with one instruction from a 4-byte
+// aligned address.
+template <int ESZ> struct EntryPair {
+    static constexpr int W = ESZ / 4;          // dwords per entry
+    uint32_t d[2 * W];
+    __device__ __forceinline__ void load_both(const char *p)
+    {
+        typedef uint32_t v_t __attribute__((ext_vector_type(2 * W)));
+        v_t v;
+        __builtin_memcpy(&v, p, sizeof(v));
+#pragma unroll
+        for (int k = 0; k < 2 * W; ++k) d[k] = v[k];
+    }
+    __device__ __forceinline__ void load_apart(const char *lo, const char *hi)
+    {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            d[k] = reinterpret_cast<const uint32_t *>(lo)[k];
+            d[W + k] = reinterpret_cast<const uint32_t *>(hi)[k];
+        }
+    }
+    __device__ __forceinline__ void pin()
+    {
+#pragma unroll
+        for (int k = 0; k < 2 * W; ++k) asm volatile("" : "+v"(d[k]));
+    }
+};
+
+template <typename TF> __device__ __forceinline__ float entry_feature(const uint32_t *d, int f)
+{
+    if constexpr (sizeof(TF) == 4) return __uint_as_float(d[f]);
+    else return (f & 1) ? hi16<TF>(d[f >> 1]) : lo16<TF>(d[f >> 1]);
+}
+
+// encode_levels for entries of 4 or 8 bytes.  The two vertices x = i and
+// x = i + 1 of a cell edge along x share y and z, so their slots are s and
+// s + 1 on a directly indexed level and s and s ^ (i ^ (i + 1)) on a hashed
+// one: adjacent always in the first case and for about two edges in three in
+// the second.  One load of the lower slot then brings both entries (the other
+// lanes load the two slots separately), which halves the gather instructions
+// of an edge.  Which of the two x vertices sits in the lower slot is folded
+// into the x weights at once, so nothing else has to outlive the loads.  The
+// table allocation ends with one spare entry, for the load at the last slot
+// of a collapsed edge.
+template <typename TF, int F, int NL>
+__device__ __forceinline__ void encode_levels_paired(const Geom &g, const TF *__restrict__ tab, int l0,
+                                                     const float p[3], int face, float out[NL][F])
+{
+    static_assert(NL <= 8, "one swap bit per edge of at most 8 levels");
+    constexpr uint32_t esz = F * sizeof(TF);
+    constexpr uint32_t sh = esz == 4 ? 2 : 3;
+    constexpr int W = EntryPair<esz>::W;
+    EntryPair<esz> e[NL][4];
+    float wx[NL][2], wy[NL][2], wz[NL][2];
+    uint32_t swapbits = 0;    // bit 4 lv + q: vertex x = i + 1 of edge q holds the lower slot
+#pragma unroll
+    for (int lv = 0; lv < NL; ++lv) {
+        const int l = l0 + lv < g.L ? l0 + lv : g.L - 1;
+        uint32_t i[3];
+        float wt[3];
+        level_cell_mm(g, l, p, i, wt);
+        const uint32_t my = g.my[l], mz = g.mz[l];
+        uint32_t ys[2] = {i[1] * my, i[1] * my + my}, zs[2] = {i[2] * mz, i[2] * mz + mz};
+        uint32_t x0 = i[0], x1 = i[0] + 1u;
+        wx[lv][0] = 1.0f - wt[0];
+        wx[lv][1] = wt[0];
+        if ((g.aligned_mask >> l) & 1u) {
+            // the crossing-axis weight is exactly 0 or 1: both vertices on that
+            // axis become the selected one (an x edge collapses to one slot and
+            // all of its weight goes to the lower entry of the pair)
+            const float wf = face == 0 ? wt[0] : (face == 1 ? wt[1] : wt[2]);
+            const bool up = wf != 0.0f;
+            if (face == 0) {
+                x0 = x1 = up ? x1 : x0;
+                wx[lv][0] = 1.0f;
+                wx[lv][1] = 0.0f;
+            } else if (face == 1) {
+                ys[0] = ys[1] = up ? ys[1] : ys[0];
+            } else {
+                zs[0] = zs[1] = up ? zs[1] : zs[0];
+            }
+        }
+        wy[lv][0] = 1.0f - wt[1];
+        wy[lv][1] = wt[1];
+        wz[lv][0] = 1.0f - wt[2];
+        wz[lv][1] = wt[2];
+        const bool dense = (g.dense_mask >> l) & 1u;
+        const uint32_t hm = g.hmask[l] << sh;
+        const char *base = reinterpret_cast<const char *>(tab + ((size_t)l << g.log2_T) * F);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t y = ys[q & 1], z = zs[q >> 1];
+            uint32_t a, b;
+            if (dense) {
+                const uint32_t s = (y + z) << sh;
+                a = (x0 << sh) + s;
+                b = (x1 << sh) + s;
+            } else {
+                const uint32_t s = (y ^ z) << sh;
+                a = ((x0 << sh) ^ s) & hm;
+                b = ((x1 << sh) ^ s) & hm;
+            }
+            const bool swap = a > b;
+            const uint32_t lo = swap ? b : a, hi = swap ? a : b;
+            swapbits |= (swap ? 1u : 0u) << (4 * lv + q);
+            if (hi - lo <= esz) e[lv][q].load_both(base + lo);
+            else e[lv][q].load_apart(base + lo, base + hi);
+        }
+        // form the bits now, so the slots die with their loads
+        asm volatile("" : "+v"(swapbits));
+    }
+    // keep every gather of the batch in flight before the first is consumed
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int lv = 0; lv < NL; ++lv)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e[lv][q].pin();
+#pragma unroll
+    for (int lv = 0; lv < NL; ++lv) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) out[lv][f] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool swap = (swapbits >> (4 * lv + q)) & 1u;
+            const float wyz = wy[lv][q & 1] * wz[lv][q >> 1];
+            const float wl = (swap ? wx[lv][1] : wx[lv][0]) * wyz, wh = (swap ? wx[lv][0] : wx[lv][1]) * wyz;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                out[lv][f] = __builtin_fmaf(wl, entry_feature<TF>(e[lv][q].d, f), out[lv][f]);
+                out[lv][f] = __builtin_fmaf(wh, entry_feature<TF>(e[lv][q].d + W, f), out[lv][f]);
+            }
+        }
+        if (l0 + lv >= g.L) {
+#pragma unroll
+            for (int f = 0; f < F; ++f) out[lv][f] = 0.0f;
+        }
+    }
+}
+
+// Interpolated features of NL consecutive levels from l0 (zeros beyond L).
+template <typename TF, int F, int NL>
+__device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restrict__ tab, int l0,
+                                              const float p[3], int face, float out[NL][F])
+{
+    if constexpr (F * sizeof(TF) == 4 || F * sizeof(TF) == 8)
+        encode_levels_paired<TF, F, NL>(g, tab, l0, p, face, out);
+    else
+        encode_levels_corners<TF, F, NL>(g, tab, l0, p, face, out);
+}
+
 __device__ __forceinline__ float act_f(float x, int act, float slope)
 {
     return x > 0.0f ? x : (act == LSNIF_LEAKY_RELU ? x * slope : 0.0f);
+}
+
+// Lanes of a wave that share a key are served by one atomic on that key's
+// counter (issued by the lowest such lane); returns the counter's old value
+// plus this lane's rank among the lanes with its key, so equal keys of one
+// wave never contend for the same address.
+__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t *ctr, uint32_t key, bool active)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    uint64_t todo = __ballot(active);
+    uint32_t old = 0, leader = lane;
+    uint64_t mine = 0;
+    while (todo) {
+        const uint32_t l = (uint32_t)__builtin_ctzll(todo);
+        const uint32_t k = __shfl(key, l, 64);
+        const uint64_t same = __ballot(active && key == k);
+        if (active && key == k) {
+            leader = l;
+            mine = same;
+        }
+        if (lane == l) old = atomicAdd(&ctr[k], (uint32_t)__builtin_popcountll(same));
+        todo &= ~same;
+    }
+    const uint32_t base = __shfl(old, leader, 64);
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    return base + (uint32_t)__builtin_popcountll(mine & below);
+}
+
+// Largest non-negative value of the wave folded into *dst (float bits of
+// non-negative numbers order like unsigned integers).
+__device__ __forceinline__ void fold_max(float *dst, float v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fmax2(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63u) == 0) atomicMax(reinterpret_cast<unsigned int *>(dst), __float_as_uint(v));
 }
 
 __device__ __forceinline__ int wave_max(int v)
@@ -207,8 +466,9 @@ __device__ __forceinline__ int wave_max(int v)
 // Output heads (Sec. 5.1, 5.3): occlusion logit > 0 is a hit, the hit
 // distance is the sigmoid of its logit over [ta, tb], the normal is the
 // normalised linear head, the material the arg-max logit.
-__device__ __forceinline__ void decode_store(const QueryArgs &A, uint32_t r, const VRay &w, int count,
-                                             const float *o)
+template <bool PAIRS>
+__device__ __forceinline__ void decode_store(const QueryArgs &A, const Mlp &mm, uint32_t r, uint32_t pair,
+                                             const VRay &w, int count, const float *o)
 {
     lsnif_hit h;
     h.hit = 0;
@@ -228,15 +488,30 @@ __device__ __forceinline__ void decode_store(const QueryArgs &A, uint32_t r, con
                 h.n[1] = o[3] * inv;
                 h.n[2] = o[4] * inv;
             }
-            const int m0 = 5 + 3 * A.m.has_albedo;
+            const int m0 = 5 + 3 * mm.has_albedo;
             int best = 0;
             float bv = o[m0];
-            for (int k = 1; k < A.m.n_mat; ++k)
+            for (int k = 1; k < mm.n_mat; ++k)
                 if (o[m0 + k] > bv) { bv = o[m0 + k]; best = k; }
             h.material = best;
         }
     }
-    A.hits[r] = h;
+    if constexpr (!PAIRS) {
+        A.hits[r] = h;
+    } else {
+        PairRes pr;
+        pr.t = h.t;
+        pr.n[0] = h.n[0];
+        pr.n[1] = h.n[1];
+        pr.n[2] = h.n[2];
+        pr.material = h.material;
+        A.pr.res[pair] = pr;
+        if (h.hit) {
+            const unsigned long long key =
+                ((unsigned long long)ordered_bits(h.t) << 32) | (unsigned long long)A.pr.pair_inst[pair];
+            atomicMin(&A.pr.minkey[r], key);
+        }
+    }
 }
 
 // ------------------------------------------------------------- shared prologue
@@ -246,7 +521,7 @@ __device__ __forceinline__ void decode_store(const QueryArgs &A, uint32_t r, con
 // encodes rays with similar numbers of boundary points.  After the prologue,
 // lane `tid` works on ray `src` of the block; its voxel list is at
 // s_list[j * kBlock + src] and its walk state has been reloaded from LDS.
-constexpr int kState = 14;          // words of walk state per ray kept in LDS
+constexpr int kState = 15;          // words of walk state per ray kept in LDS
 
 struct Shared {
     uint32_t coarse[kCoarseLdsWords];
@@ -260,13 +535,15 @@ struct Lane {
     int nvox;
     uint32_t src;     // ray index within the block
     uint32_t r;       // global ray index
+    uint32_t pair;    // pair index (pair queries)
     bool live;
 };
 
-__device__ __forceinline__ void walk_and_sort(const QueryArgs &A, Shared &S, uint32_t *s_list, Lane &L)
+template <bool PAIRS>
+__device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g, Shared &S, uint32_t *s_list,
+                                              Lane &L)
 {
     const uint32_t tid = threadIdx.x;
-    const Geom &g = A.g;
     const int cap = g.H >> 1;
     const bool lds_coarse = g.coarse_words <= kCoarseLdsWords;
     if (lds_coarse)
@@ -274,7 +551,16 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, Shared &S, uin
     if (tid <= (uint32_t)cap) S.hist[tid] = 0;
     __syncthreads();
     const uint32_t slot0 = blockIdx.x * kBlock + tid;
-    const uint32_t r0 = slot0 < A.n ? (A.order ? A.order[slot0] : slot0) : 0u;
+    uint32_t r0 = 0u, pair0 = 0xffffffffu;
+    bool live0;
+    if constexpr (PAIRS) {
+        pair0 = slot0 < A.n ? A.pr.slot_pair[slot0] : 0xffffffffu;
+        live0 = pair0 != 0xffffffffu;
+        if (live0) r0 = A.pr.pair_ray[pair0];
+    } else {
+        live0 = slot0 < A.n;
+        if (live0) r0 = A.order ? A.order[slot0] : slot0;
+    }
     VRay w;
     w.valid = w.cand = false;
     w.ta = w.tb = w.tmax = 0.0f;
@@ -282,8 +568,10 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, Shared &S, uin
 #pragma unroll
     for (int a = 0; a < 3; ++a) w.o[a] = w.d[a] = w.inv[a] = 0.0f;
     int nvox = 0;
-    if (slot0 < A.n) {
-        setup_ray(g, A.rays[2 * r0], A.rays[2 * r0 + 1], w);
+    if (live0) {
+        float4 ra = A.rays[2 * r0], rb = A.rays[2 * r0 + 1];
+        if constexpr (PAIRS) to_object_space(A.pr.inst[A.pr.pair_inst[pair0]], ra, rb);
+        setup_ray(g, ra, rb, w);
         nvox = lds_coarse ? walk_voxels(g, w, S.coarse, s_list + tid, kBlock, cap)
                           : walk_voxels(g, w, g.coarse, s_list + tid, kBlock, cap);
     }
@@ -299,6 +587,7 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, Shared &S, uin
     st[11 * kBlock + tid] = w.tmax;
     st[12 * kBlock + tid] = __uint_as_float(w.mov | (w.valid ? 8u : 0u) | (w.cand ? 16u : 0u) | ((uint32_t)nvox << 8));
     st[13 * kBlock + tid] = __uint_as_float(r0);
+    st[14 * kBlock + tid] = __uint_as_float(live0 ? pair0 : 0xffffffffu);
     const uint32_t pos = atomicAdd(&S.hist[cap - nvox], 1u);
     __syncthreads();
     if (tid == 0) {
@@ -328,8 +617,9 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, Shared &S, uin
     L.w.cand = (pk & 16u) != 0;
     L.nvox = (int)(pk >> 8);
     L.src = src;
-    L.live = blockIdx.x * kBlock + src < A.n;
     L.r = __float_as_uint(st[13 * kBlock + src]);
+    L.pair = __float_as_uint(st[14 * kBlock + src]);
+    L.live = PAIRS ? L.pair != 0xffffffffu : blockIdx.x * kBlock + src < A.n;
 }
 
 // ---------------------------------------------------------------- float32 path
@@ -337,27 +627,46 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, Shared &S, uin
 // Weights: layer k transposed to [in][out_pad] float32 (out_pad = WIDTH for
 // hidden layers, kMaxOut for the head) so the outputs fed by one input are
 // contiguous and every lane reads the same address.
-template <typename TF, int F, int WIDTH>
-__global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
+// Object of this block's tile: one value for the whole block, read through the
+// scalar path so that everything derived from it (tables, weights) stays uniform.
+__device__ __forceinline__ int tile_object(const PairArgs &P)
+{
+    typedef const __attribute__((address_space(4))) int32_t cint;
+    return __builtin_amdgcn_readfirstlane(((cint *)P.tile_obj)[blockIdx.x]);
+}
+// The object table, read through the constant address space in the device pass (the
+// host pass only type-checks kernel bodies and has no such address space).
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef const __attribute__((address_space(4))) ObjDev cObjDev;
+#else
+typedef const ObjDev cObjDev;
+#endif
+
+// A float in the constant address space (read-only during a launch; scalar loads).
+typedef const __attribute__((address_space(4))) float cfloat;
+
+template <typename TF, int F, int WIDTH, bool PAIRS>
+__device__ __forceinline__ void query_f32_body(const QueryArgs &A, const Geom &g, const Mlp &mm,
+                                               const TF *__restrict__ tab, uint32_t *s_list, Shared &S)
 {
     constexpr int NL = 4;
-    extern __shared__ uint32_t s_list[];
-    __shared__ Shared S;
     Lane ln;
-    walk_and_sort(A, S, s_list, ln);
+    walk_and_sort<PAIRS>(A, g, S, s_list, ln);
     const uint32_t src = ln.src, r = ln.r;
     const bool live = ln.live;
     const VRay &w = ln.w;
-    const Geom &g = A.g;
     const int count = 2 * ln.nvox;
     const int wmax = __builtin_amdgcn_readfirstlane(wave_max(count));
-    const float *__restrict__ Wf = reinterpret_cast<const float *>(A.m.W);
-    const TF *__restrict__ tab = reinterpret_cast<const TF *>(A.tables);
+    // The weights are read-only for the whole launch and every lane of a wave reads the same
+    // one: through the constant address space the loads are scalar and the FMAs take them
+    // from scalar registers.
+    const cfloat *Wf = (const cfloat *)(mm.W);
     const int LF = g.L * F;
 
     float acc[WIDTH];
 #pragma unroll
     for (int j = 0; j < WIDTH; ++j) acc[j] = 0.0f;
+    float amax = 0.0f;        // largest |input| of the current layer (calibration)
     for (int h = 0; h < wmax; ++h) {
         if (h < count) {
             float p[3];
@@ -369,12 +678,14 @@ __global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
                 for (int lv = 0; lv < NL; ++lv) {
                     const int l = l0 + lv;
                     if (l < g.L) {
+#pragma unroll
+                        for (int f = 0; f < F; ++f) amax = fmax2(amax, __builtin_fabsf(e[lv][f]));
                         if (A.dbg.enc) {
 #pragma unroll
                             for (int f = 0; f < F; ++f)
                                 A.dbg.enc[(size_t)r * g.H * LF + h * LF + l * F + f] = e[lv][f];
                         }
-                        const float *Wk = Wf + A.m.off[0] + (size_t)(h * LF + l * F) * WIDTH;
+                        const cfloat *Wk = Wf + mm.off[0] + (size_t)(h * LF + l * F) * WIDTH;
 #pragma unroll
                         for (int f = 0; f < F; ++f)
 #pragma unroll
@@ -387,28 +698,35 @@ __global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
     float o[kMaxOut];
 #pragma unroll
     for (int k = 0; k < kMaxOut; ++k) o[k] = 0.0f;
+    if (A.dbg.act_amax) fold_max(A.dbg.act_amax + 0, amax);
     if (wmax > 0) {
-        for (int k = 1; k < A.m.n_hidden; ++k) {
+        for (int k = 1; k < mm.n_hidden; ++k) {
             float nxt[WIDTH];
 #pragma unroll
             for (int j = 0; j < WIDTH; ++j) nxt[j] = 0.0f;
-            const float *Wk = Wf + A.m.off[k];
+            const cfloat *Wk = Wf + mm.off[k];
+            amax = 0.0f;
 #pragma unroll
             for (int i = 0; i < WIDTH; ++i) {
-                const float x = act_f(acc[i], A.m.act, A.m.slope);
+                const float x = act_f(acc[i], mm.act, mm.slope);
+                amax = fmax2(amax, __builtin_fabsf(x));
 #pragma unroll
                 for (int j = 0; j < WIDTH; ++j) nxt[j] = __builtin_fmaf(Wk[i * WIDTH + j], x, nxt[j]);
             }
 #pragma unroll
             for (int j = 0; j < WIDTH; ++j) acc[j] = nxt[j];
+            if (A.dbg.act_amax) fold_max(A.dbg.act_amax + k, amax);
         }
-        const float *Wo = Wf + A.m.off[A.m.n_hidden];
+        const cfloat *Wo = Wf + mm.off[mm.n_hidden];
+        amax = 0.0f;
 #pragma unroll
         for (int i = 0; i < WIDTH; ++i) {
-            const float x = act_f(acc[i], A.m.act, A.m.slope);
+            const float x = act_f(acc[i], mm.act, mm.slope);
+            amax = fmax2(amax, __builtin_fabsf(x));
 #pragma unroll
             for (int j = 0; j < kMaxOut; ++j) o[j] = __builtin_fmaf(Wo[i * kMaxOut + j], x, o[j]);
         }
+        if (A.dbg.act_amax) fold_max(A.dbg.act_amax + mm.n_hidden, amax);
     }
     if (!live) return;
     if (A.dbg.count) A.dbg.count[r] = w.valid ? count : -1;
@@ -417,8 +735,23 @@ __global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
         A.dbg.tatb[2 * r + 1] = w.tb;
     }
     if (A.dbg.out)
-        for (int k = 0; k < A.m.out_dim; ++k) A.dbg.out[(size_t)r * A.m.out_dim + k] = count > 0 ? o[k] : 0.0f;
-    decode_store(A, r, w, count, o);
+        for (int k = 0; k < mm.out_dim; ++k) A.dbg.out[(size_t)r * mm.out_dim + k] = count > 0 ? o[k] : 0.0f;
+    decode_store<PAIRS>(A, mm, r, ln.pair, w, count, o);
+}
+
+template <typename TF, int F, int WIDTH, bool PAIRS>
+__global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
+{
+    extern __shared__ uint32_t s_list[];
+    __shared__ Shared S;
+    if constexpr (PAIRS) {
+        const int o = tile_object(A.pr);
+        if (o < 0) return;
+        const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
+        query_f32_body<TF, F, WIDTH, true>(A, O.g, O.m, (const TF *)O.tables, s_list, S);
+    } else {
+        query_f32_body<TF, F, WIDTH, false>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list, S);
+    }
 }
 
 // ------------------------------------------------------------ matrix-core path
@@ -440,9 +773,16 @@ typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
 typedef float f16_t __attribute__((ext_vector_type(16)));
 
+// MLP types of the matrix-core path.  Every fragment holds 8 values per
+// lane (DW dwords); FP8 values are OCP e4m3 with a per-layer scale.
+struct fp8e4m3 {};
+typedef long f8x8_t;
+
 template <typename TM> struct MmaT;
 template <> struct MmaT<_Float16> {
     typedef h8_t vec;
+    static constexpr int DW = 4;
+    static constexpr bool scaled = false;
     static __device__ __forceinline__ f16_t mma(vec a, vec b, f16_t c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
@@ -450,13 +790,24 @@ template <> struct MmaT<_Float16> {
 };
 template <> struct MmaT<__bf16> {
     typedef b8_t vec;
+    static constexpr int DW = 4;
+    static constexpr bool scaled = false;
     static __device__ __forceinline__ f16_t mma(vec a, vec b, f16_t c)
     {
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
     }
 };
+template <> struct MmaT<fp8e4m3> {
+    typedef f8x8_t vec;
+    static constexpr int DW = 2;
+    static constexpr bool scaled = true;
+    static __device__ __forceinline__ f16_t mma(vec a, vec b, f16_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, b, c, 0, 0, 0);
+    }
+};
 
-// Two TM values in one dword.
+// Two 16-bit TM values in one dword.
 template <typename TM> __device__ __forceinline__ uint32_t pack2(float a, float b)
 {
     TM x = (TM)a, y = (TM)b;
@@ -465,26 +816,66 @@ template <typename TM> __device__ __forceinline__ uint32_t pack2(float a, float 
     __builtin_memcpy(&v, &y, 2);
     return (uint32_t)u | ((uint32_t)v << 16);
 }
-template <typename TM> __device__ __forceinline__ float unpack_lo(uint32_t x)
+
+// Eight values, times `scale`, rounded to TM and packed into DW dwords.
+template <typename TM>
+__device__ __forceinline__ void pack8(const float *v, float scale, uint32_t *d)
 {
-    uint16_t u = (uint16_t)(x & 0xffffu);
-    TM v;
-    __builtin_memcpy(&v, &u, 2);
-    return (float)v;
-}
-template <typename TM> __device__ __forceinline__ float unpack_hi(uint32_t x)
-{
-    uint16_t u = (uint16_t)(x >> 16);
-    TM v;
-    __builtin_memcpy(&v, &u, 2);
-    return (float)v;
+    if constexpr (MmaT<TM>::scaled) {
+        float x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float y = v[e] * scale;
+            x[e] = y < -448.0f ? -448.0f : (y > 448.0f ? 448.0f : y);   // saturate to the e4m3 range
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(x[4 * q], x[4 * q + 1], 0, false);
+            w = __builtin_amdgcn_cvt_pk_fp8_f32(x[4 * q + 2], x[4 * q + 3], w, true);
+            d[q] = (uint32_t)w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[q] = pack2<TM>(v[2 * q], v[2 * q + 1]);
+    }
 }
 
-template <typename V8> __device__ __forceinline__ V8 as_vec(const uint32_t d[4])
+// Value e (0..7) of a packed fragment, widened to float (not rescaled).
+template <typename TM> __device__ __forceinline__ float unpack8(const uint32_t *d, int e)
+{
+    if constexpr (MmaT<TM>::scaled) {
+        const uint32_t w = d[e >> 2];
+        switch (e & 3) {
+        case 0: return __builtin_amdgcn_cvt_f32_fp8((int)w, 0);
+        case 1: return __builtin_amdgcn_cvt_f32_fp8((int)w, 1);
+        case 2: return __builtin_amdgcn_cvt_f32_fp8((int)w, 2);
+        default: return __builtin_amdgcn_cvt_f32_fp8((int)w, 3);
+        }
+    } else {
+        const uint16_t u = (uint16_t)((e & 1) ? (d[e >> 1] >> 16) : (d[e >> 1] & 0xffffu));
+        TM v;
+        __builtin_memcpy(&v, &u, 2);
+        return (float)v;
+    }
+}
+
+template <typename V8, int DW> __device__ __forceinline__ V8 as_vec(const uint32_t *d)
 {
     V8 v;
-    __builtin_memcpy(&v, d, 16);
+    __builtin_memcpy(&v, d, 4 * DW);
     return v;
+}
+
+// One weight fragment (DW dwords of this lane).
+template <int DW> __device__ __forceinline__ void load_frag(const uint32_t *p, uint32_t *d)
+{
+    if constexpr (DW == 4) {
+        const uint4 x = *reinterpret_cast<const uint4 *>(p);
+        d[0] = x.x; d[1] = x.y; d[2] = x.z; d[3] = x.w;
+    } else {
+        const uint2 x = *reinterpret_cast<const uint2 *>(p);
+        d[0] = x.x; d[1] = x.y;
+    }
 }
 
 // Exchange the upper half-wave of x with the lower half-wave of y.
@@ -495,28 +886,26 @@ __device__ __forceinline__ void swap32(uint32_t &x, uint32_t &y)
     y = r[1];
 }
 
-template <typename TF, typename TM, int F, int WIDTH>
-__global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
+template <typename TF, typename TM, int F, int WIDTH, int KBM, bool PAIRS>
+__device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g, const Mlp &mm,
+                                               const TF *__restrict__ tab, uint32_t *s_list, Shared &S)
 {
     typedef typename MmaT<TM>::vec vec_t;
+    constexpr int DW = MmaT<TM>::DW;
     constexpr int FP = F == 3 ? 4 : F;        // features per level, padded to divide 16
     constexpr int MB = WIDTH / 32;            // output blocks of a hidden layer
     constexpr int LPB = 16 / FP;              // levels per K block
     constexpr int NL = (F * sizeof(TF) <= 4 && LPB >= 8) ? 8 : (LPB < 4 ? LPB : 4);   // levels per gather batch
-    extern __shared__ uint32_t s_list[];
-    __shared__ Shared S;
     Lane ln;
-    walk_and_sort(A, S, s_list, ln);
+    walk_and_sort<PAIRS>(A, g, S, s_list, ln);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t src = ln.src, r = ln.r;
     const bool live = ln.live;
     const VRay &w = ln.w;
-    const Geom &g = A.g;
     const int count = 2 * ln.nvox;
     const int wmax = __builtin_amdgcn_readfirstlane(wave_max(count));
-    const TF *__restrict__ tab = reinterpret_cast<const TF *>(A.tables);
-    const uint4 *__restrict__ Wv = reinterpret_cast<const uint4 *>(A.m.W);
-    const int KB = A.m.kb_point;
+    const uint32_t *__restrict__ Wv = reinterpret_cast<const uint32_t *>(mm.W);
+    const int KB = mm.kb_point;
 
     f16_t acc[MB][2];
 #pragma unroll
@@ -526,16 +915,32 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[m][nb][e] = 0.0f;
 
+    // The entry point of a voxel equals the exit point of the voxel before it
+    // when the two share a face (about 30 % of points on c2); such a point
+    // reuses the previous point's features, so its lane issues no gathers.
+    uint32_t plo[KBM][DW], phi[KBM][DW];
+#pragma unroll
+    for (int kb = 0; kb < KBM; ++kb)
+#pragma unroll
+        for (int q = 0; q < DW; ++q) plo[kb][q] = phi[kb][q] = 0u;
+    uint32_t pp[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu};
+    int pface = -1;
     for (int h = 0; h < wmax; ++h) {
         float p[3] = {0.0f, 0.0f, 0.0f};
         int face = 0;
         const bool has = h < count;
         if (has) face = boundary_point(w, s_list[(h >> 1) * kBlock + src], h & 1, p);
-        for (int kb = 0; kb < KB; ++kb) {
-            float e[16];
+        const bool dup = has && (h & 1) == 0 && face == pface && __float_as_uint(p[0]) == pp[0] &&
+                         __float_as_uint(p[1]) == pp[1] && __float_as_uint(p[2]) == pp[2];
+        const bool fresh = has && !dup;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) e[q] = 0.0f;
-            if (has) {
+        for (int kb = 0; kb < KBM; ++kb) {
+            if (kb >= KB) break;
+            uint32_t lo[DW], hi[DW];
+            if (fresh) {
+                float e[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) e[q] = 0.0f;
 #pragma unroll
                 for (int c0 = 0; c0 < LPB; c0 += NL) {
                     float v[NL][F];
@@ -545,37 +950,46 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
 #pragma unroll
                         for (int f = 0; f < F; ++f) e[(c0 + lv) * FP + f] = v[lv][f];
                 }
-            }
-            uint32_t lo[4], hi[4];
+                pack8<TM>(e, mm.qs[0], lo);
+                pack8<TM>(e + 8, mm.qs[0], hi);
+            } else {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                lo[q] = pack2<TM>(e[2 * q], e[2 * q + 1]);
-                hi[q] = pack2<TM>(e[8 + 2 * q], e[8 + 2 * q + 1]);
+                for (int q = 0; q < DW; ++q) {
+                    lo[q] = dup ? plo[kb][q] : 0u;
+                    hi[q] = dup ? phi[kb][q] : 0u;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < DW; ++q) {
+                plo[kb][q] = lo[q];
+                phi[kb][q] = hi[q];
             }
             if (A.dbg.enc && live && has) {
                 const int LFp = g.L * FP;
                 for (int q = 0; q < 16; ++q) {
                     const int k = kb * 16 + q;
                     if (k < LFp) {
-                        uint32_t word = q < 8 ? lo[q >> 1] : hi[(q - 8) >> 1];
-                        A.dbg.enc[(size_t)r * g.H * LFp + h * LFp + k] =
-                            (q & 1) ? unpack_hi<TM>(word) : unpack_lo<TM>(word);
+                        const float v = q < 8 ? unpack8<TM>(lo, q) : unpack8<TM>(hi, q - 8);
+                        A.dbg.enc[(size_t)r * g.H * LFp + h * LFp + k] = MmaT<TM>::scaled ? v / mm.qs[0] : v;
                     }
                 }
             }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) swap32(lo[q], hi[q]);
-            const vec_t b0 = as_vec<vec_t>(lo), b1 = as_vec<vec_t>(hi);
-            const uint4 *Wk = Wv + A.m.off[0] / 8 + (size_t)((h * KB + kb) * MB) * 64 + lane;
+            for (int q = 0; q < DW; ++q) swap32(lo[q], hi[q]);
+            const vec_t b0 = as_vec<vec_t, DW>(lo), b1 = as_vec<vec_t, DW>(hi);
+            const uint32_t *Wk = Wv + mm.woff[0] + ((size_t)((h * KB + kb) * MB) * 64 + lane) * DW;
 #pragma unroll
             for (int m = 0; m < MB; ++m) {
-                const uint4 wa = Wk[m * 64];
-                const uint32_t wd[4] = {wa.x, wa.y, wa.z, wa.w};
-                const vec_t a = as_vec<vec_t>(wd);
+                uint32_t wd[DW];
+                load_frag<DW>(Wk + (size_t)m * 64 * DW, wd);
+                const vec_t a = as_vec<vec_t, DW>(wd);
                 acc[m][0] = MmaT<TM>::mma(a, b0, acc[m][0]);
                 acc[m][1] = MmaT<TM>::mma(a, b1, acc[m][1]);
             }
         }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) pp[b] = __float_as_uint(p[b]);
+        pface = has ? face : -1;
     }
 
     // hidden layers 2..n_hidden, then the head
@@ -583,26 +997,28 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
 #pragma unroll
     for (int k = 0; k < kMaxOut; ++k) o[k] = 0.0f;
     if (wmax > 0) {
-        for (int k = 1; k <= A.m.n_hidden; ++k) {
-            const bool head = k == A.m.n_hidden;
-            // activations -> B operands: 16-block s of output block m
-            uint32_t xb[MB][2][2][4];
+        for (int k = 1; k <= mm.n_hidden; ++k) {
+            const bool head = k == mm.n_hidden;
+            // activations -> B operands: 16-block s of output block m holds the
+            // outputs lying in accumulator registers 8s .. 8s+7
+            const float dqi = mm.dq[k - 1], qsi = mm.qs[k];
+            uint32_t xb[MB][2][2][DW];
 #pragma unroll
             for (int m = 0; m < MB; ++m)
 #pragma unroll
                 for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-                    for (int s = 0; s < 2; ++s)
+                    for (int s = 0; s < 2; ++s) {
+                        float v[8];
 #pragma unroll
-                        for (int q = 0; q < 2; ++q) {
-                            const int r0 = 8 * s + 2 * q;
-                            xb[m][nb][s][q] = pack2<TM>(act_f(acc[m][nb][r0], A.m.act, A.m.slope),
-                                                        act_f(acc[m][nb][r0 + 1], A.m.act, A.m.slope));
-                            xb[m][nb][s][2 + q] = pack2<TM>(act_f(acc[m][nb][r0 + 4], A.m.act, A.m.slope),
-                                                            act_f(acc[m][nb][r0 + 5], A.m.act, A.m.slope));
+                        for (int e = 0; e < 8; ++e) {
+                            const float y = MmaT<TM>::scaled ? acc[m][nb][8 * s + e] * dqi : acc[m][nb][8 * s + e];
+                            v[e] = act_f(y, mm.act, mm.slope);
                         }
+                        pack8<TM>(v, qsi, xb[m][nb][s]);
+                    }
             const int MO = head ? 1 : MB;
-            const uint4 *Wk = Wv + A.m.off[k] / 8 + lane;
+            const uint32_t *Wk = Wv + mm.woff[k] + (size_t)lane * DW;
 #pragma unroll
             for (int m = 0; m < MB; ++m)
 #pragma unroll
@@ -616,11 +1032,11 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
                     for (int m = 0; m < MB; ++m)
 #pragma unroll
                         for (int s = 0; s < 2; ++s) {
-                            const uint4 wa = Wk[(size_t)((mo * MB + m) * 2 + s) * 64];
-                            const uint32_t wd[4] = {wa.x, wa.y, wa.z, wa.w};
-                            const vec_t a = as_vec<vec_t>(wd);
-                            acc[mo][0] = MmaT<TM>::mma(a, as_vec<vec_t>(xb[m][0][s]), acc[mo][0]);
-                            acc[mo][1] = MmaT<TM>::mma(a, as_vec<vec_t>(xb[m][1][s]), acc[mo][1]);
+                            uint32_t wd[DW];
+                            load_frag<DW>(Wk + (size_t)((mo * MB + m) * 2 + s) * 64 * DW, wd);
+                            const vec_t a = as_vec<vec_t, DW>(wd);
+                            acc[mo][0] = MmaT<TM>::mma(a, as_vec<vec_t, DW>(xb[m][0][s]), acc[mo][0]);
+                            acc[mo][1] = MmaT<TM>::mma(a, as_vec<vec_t, DW>(xb[m][1][s]), acc[mo][1]);
                         }
                 }
             }
@@ -633,12 +1049,13 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
             y[e] = __float_as_uint(acc[0][1][e]);
             swap32(x[e], y[e]);
         }
+        const float dqo = MmaT<TM>::scaled ? mm.dq[mm.n_hidden] : 1.0f;
 #pragma unroll
         for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-                o[8 * q + rr] = __uint_as_float(x[4 * q + rr]);
-                o[8 * q + 4 + rr] = __uint_as_float(y[4 * q + rr]);
+                o[8 * q + rr] = __uint_as_float(x[4 * q + rr]) * dqo;
+                o[8 * q + 4 + rr] = __uint_as_float(y[4 * q + rr]) * dqo;
             }
     }
     if (!live) return;
@@ -648,8 +1065,24 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
         A.dbg.tatb[2 * r + 1] = w.tb;
     }
     if (A.dbg.out)
-        for (int k = 0; k < A.m.out_dim; ++k) A.dbg.out[(size_t)r * A.m.out_dim + k] = count > 0 ? o[k] : 0.0f;
-    decode_store(A, r, w, count, o);
+        for (int k = 0; k < mm.out_dim; ++k) A.dbg.out[(size_t)r * mm.out_dim + k] = count > 0 ? o[k] : 0.0f;
+    decode_store<PAIRS>(A, mm, r, ln.pair, w, count, o);
+}
+
+template <typename TF, typename TM, int F, int WIDTH, int KBM, bool PAIRS>
+__global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
+{
+    extern __shared__ uint32_t s_list[];
+    __shared__ Shared S;
+    if constexpr (PAIRS) {
+        const int o = tile_object(A.pr);
+        if (o < 0) return;
+        const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
+        query_mma_body<TF, TM, F, WIDTH, KBM, true>(A, O.g, O.m, (const TF *)O.tables, s_list, S);
+    } else {
+        query_mma_body<TF, TM, F, WIDTH, KBM, false>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list,
+                                                    S);
+    }
 }
 
 // ------------------------------------------------------------------ debug path

@@ -41,12 +41,39 @@ class lsnif_object_desc(C.Structure):
                 ("H", C.c_int32), ("n_hidden", C.c_int32), ("width", C.c_int32),
                 ("act", C.c_int32), ("leaky_slope", C.c_float), ("n_mat", C.c_int32),
                 ("has_albedo", C.c_int32), ("W", C.c_void_p), ("feat_dtype", C.c_int32),
-                ("mlp_dtype", C.c_int32), ("fp8_act_scale", C.c_void_p)]
+                ("mlp_dtype", C.c_int32), ("fp8_act_scale", C.c_void_p),
+                ("grazing_recheck", C.c_int32)]
+
+
+class lsnif_serve_cfg(C.Structure):
+    _fields_ = [("max_inflight", C.c_uint32), ("hbm_budget", C.c_uint64), ("n_streams", C.c_uint32),
+                ("max_queue", C.c_uint32), ("dry_run_ns_per_ray", C.c_uint64)]
+
+
+class lsnif_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("object_id", C.c_uint32), ("d_rays", C.c_void_p), ("n_rays", C.c_uint32),
+                ("d_pair_ray", C.c_void_p), ("d_pair_inst", C.c_void_p), ("n_pairs", C.c_uint32),
+                ("d_inst", C.c_void_p), ("n_inst", C.c_uint32), ("d_out", C.c_void_p),
+                ("timeout_ns", C.c_int64)]
+
+
+class lsnif_serve_stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "admitted", "completed", "rejected", "cancelled",
+                                           "timed_out", "failed", "queued", "inflight",
+                                           "rays_completed", "ws_bytes_peak")] + \
+               [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "elapsed_s")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+LSNIF_REQ_QUEUED, LSNIF_REQ_RUNNING, LSNIF_REQ_DONE = 0, 1, 2
+LSNIF_REQ_SINGLE, LSNIF_REQ_PAIRS = 0, 1
 
 
 class lsnif_debug_bufs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("count", "tatb", "vox_ijk", "vox_t", "vox_axis",
-                                           "points", "slots", "weights", "enc", "out")]
+                                           "points", "slots", "weights", "enc", "out", "act_amax")]
 
 
 _lib = None
@@ -73,8 +100,30 @@ def load():
     lib.lsnif_query.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
     lib.lsnif_query_debug.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
                                       C.POINTER(lsnif_debug_bufs), C.c_void_p]
+    lib.lsnif_query_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
+                                      C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
+    lib.lsnif_serve_start.argtypes = [C.c_void_p, C.POINTER(lsnif_serve_cfg)]
+    lib.lsnif_serve_submit.argtypes = [C.c_void_p, C.POINTER(lsnif_request), C.POINTER(C.c_uint64)]
+    lib.lsnif_serve_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]
+    lib.lsnif_serve_wait.argtypes = [C.c_void_p, C.c_uint64, C.c_int64]
+    lib.lsnif_serve_cancel.argtypes = [C.c_void_p, C.c_uint64]
+    lib.lsnif_serve_stats_get.argtypes = [C.c_void_p, C.POINTER(lsnif_serve_stats)]
+    lib.lsnif_serve_stop.argtypes = [C.c_void_p]
+    lib.lsnif_profile_enable.argtypes = [C.c_void_p, C.c_int32]
+    lib.lsnif_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_uint64)]
+    lib.lsnif_graph_query.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
+                                      C.POINTER(C.c_void_p)]
+    lib.lsnif_graph_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
+                                      C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.lsnif_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
+    lib.lsnif_graph_destroy.argtypes = [C.c_void_p]
+    lib.lsnif_graph_destroy.restype = None
     for name in ("lsnif_create", "lsnif_desc_bytes", "lsnif_build", "lsnif_release",
-                 "lsnif_object_bytes", "lsnif_query", "lsnif_query_debug"):
+                 "lsnif_object_bytes", "lsnif_query", "lsnif_query_debug", "lsnif_profile_enable",
+                 "lsnif_profile_read", "lsnif_query_pairs", "lsnif_serve_start", "lsnif_serve_submit",
+                 "lsnif_serve_poll", "lsnif_serve_wait", "lsnif_serve_cancel", "lsnif_serve_stats_get",
+                 "lsnif_serve_stop", "lsnif_graph_query", "lsnif_graph_pairs", "lsnif_graph_launch"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -129,6 +178,7 @@ class ObjectDesc:
         d.feat_dtype = DTYPES[feat_dtype] if isinstance(feat_dtype, str) else feat_dtype
         d.mlp_dtype = DTYPES[mlp_dtype] if isinstance(mlp_dtype, str) else mlp_dtype
         d.fp8_act_scale = self.scale.ctypes.data if self.scale is not None else None
+        d.grazing_recheck = int(getattr(obj, "grazing_recheck", 0))
         self.d = d
 
 
@@ -177,6 +227,126 @@ def lsnif_query_debug(ctx, object_id, rays, out, bufs: dict, stream=None):
     n = rays.shape[0]
     _check(load().lsnif_query_debug(ctx, object_id, C.c_void_p(rays.data_ptr()), n,
                                     C.c_void_p(out.data_ptr()), C.byref(b), _stream_handle(stream)))
+
+
+def instances_array(instances):
+    """Host array of ``lsnif_instance`` records (n, 13) int32 from [(object_id, 3x4 matrix)]."""
+    a = np.zeros((len(instances), 13), np.int32)
+    for i, (oid, m) in enumerate(instances):
+        a[i, 0] = int(oid)
+        a[i, 1:] = np.asarray(m, np.float32).reshape(12).view(np.int32)
+    return a
+
+
+def lsnif_query_pairs(ctx, rays, pair_ray, pair_inst, inst, out, stream=None):
+    """Nearest hit per ray over pairs.  All arguments are device tensors: rays (n, 8) float32,
+    pair_ray / pair_inst (m,) int32, inst (k, 13) int32 (see ``instances_array``),
+    out (n, 6) 4-byte."""
+    n, m, k = rays.shape[0], pair_ray.shape[0], inst.shape[0]
+    assert pair_inst.shape[0] == m and out.shape[0] >= n
+    _check(load().lsnif_query_pairs(ctx, C.c_void_p(rays.data_ptr()), n,
+                                    C.c_void_p(pair_ray.data_ptr() if m else 0),
+                                    C.c_void_p(pair_inst.data_ptr() if m else 0), m,
+                                    C.c_void_p(inst.data_ptr() if k else 0), k,
+                                    C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+
+
+def lsnif_graph_query(ctx, object_id, rays, out):
+    """Capture ``lsnif_query(ctx, object_id, rays, out)`` into a graph; returns its handle."""
+    g = C.c_void_p()
+    _check(load().lsnif_graph_query(ctx, object_id, C.c_void_p(rays.data_ptr()), rays.shape[0],
+                                    C.c_void_p(out.data_ptr()), C.byref(g)))
+    return g
+
+
+def lsnif_graph_pairs(ctx, rays, pair_ray, pair_inst, inst, out):
+    """Capture ``lsnif_query_pairs`` with these tensors into a graph; returns its handle."""
+    n, m, k = rays.shape[0], pair_ray.shape[0], inst.shape[0]
+    assert pair_inst.shape[0] == m and out.shape[0] >= n
+    g = C.c_void_p()
+    _check(load().lsnif_graph_pairs(ctx, C.c_void_p(rays.data_ptr()), n,
+                                    C.c_void_p(pair_ray.data_ptr() if m else 0),
+                                    C.c_void_p(pair_inst.data_ptr() if m else 0), m,
+                                    C.c_void_p(inst.data_ptr() if k else 0), k,
+                                    C.c_void_p(out.data_ptr()), C.byref(g)))
+    return g
+
+
+def lsnif_graph_launch(graph, stream=None):
+    _check(load().lsnif_graph_launch(graph, _stream_handle(stream)))
+
+
+def lsnif_graph_destroy(graph):
+    load().lsnif_graph_destroy(graph)
+
+
+def lsnif_serve_start(ctx, max_inflight=0, hbm_budget=0, n_streams=0, max_queue=0, dry_run_ns_per_ray=0):
+    cfg = lsnif_serve_cfg(max_inflight, hbm_budget, n_streams, max_queue, dry_run_ns_per_ray)
+    _check(load().lsnif_serve_start(ctx, C.byref(cfg)))
+
+
+def make_request(rays=None, out=None, object_id=0, pair_ray=None, pair_inst=None, inst=None,
+                 n_rays=None, timeout_ns=0):
+    """An ``lsnif_request`` from device tensors (or raw pointers with ``n_rays``, for dry runs)."""
+    ptr = lambda t: (t.data_ptr() if hasattr(t, "data_ptr") else int(t)) if t is not None else None
+    n = n_rays if n_rays is not None else rays.shape[0]
+    r = lsnif_request()
+    r.kind = LSNIF_REQ_SINGLE
+    r.object_id = object_id
+    r.d_rays, r.n_rays, r.d_out = ptr(rays), n, ptr(out)
+    if pair_ray is not None:
+        r.kind = LSNIF_REQ_PAIRS
+        r.d_pair_ray, r.d_pair_inst = ptr(pair_ray), ptr(pair_inst)
+        r.n_pairs = pair_ray.shape[0] if hasattr(pair_ray, "shape") else 0
+        r.d_inst = ptr(inst)
+        r.n_inst = inst.shape[0] if hasattr(inst, "shape") else 0
+    r.timeout_ns = timeout_ns
+    return r
+
+
+def lsnif_serve_submit(ctx, req):
+    t = C.c_uint64()
+    _check(load().lsnif_serve_submit(ctx, C.byref(req), C.byref(t)))
+    return t.value
+
+
+def lsnif_serve_poll(ctx, ticket):
+    st = C.c_int32()
+    _check(load().lsnif_serve_poll(ctx, ticket, C.byref(st)))
+    return st.value
+
+
+def lsnif_serve_wait(ctx, ticket, timeout_ns=-1):
+    """Final status of the request (0 = completed); raises on a wait timeout."""
+    st = load().lsnif_serve_wait(ctx, ticket, timeout_ns)
+    if st == LSNIF_E_TIMEOUT and lsnif_last_error().endswith("not finished"):
+        raise LsnifError(st, lsnif_last_error())
+    return st
+
+
+def lsnif_serve_cancel(ctx, ticket):
+    _check(load().lsnif_serve_cancel(ctx, ticket))
+
+
+def lsnif_serve_stats_get(ctx):
+    s = lsnif_serve_stats()
+    _check(load().lsnif_serve_stats_get(ctx, C.byref(s)))
+    return s.as_dict()
+
+
+def lsnif_serve_stop(ctx):
+    _check(load().lsnif_serve_stop(ctx))
+
+
+def lsnif_profile_enable(ctx, on=True):
+    _check(load().lsnif_profile_enable(ctx, 1 if on else 0))
+
+
+def lsnif_profile_read(ctx):
+    """(sort_ms, kernel_ms, queries) summed over the queries since the last read."""
+    a, b, k = C.c_double(), C.c_double(), C.c_uint64()
+    _check(load().lsnif_profile_read(ctx, C.byref(a), C.byref(b), C.byref(k)))
+    return a.value, b.value, k.value
 
 
 def hits_from(out):

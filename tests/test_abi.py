@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI: exported symbols, descriptor validation, footprint accounting.
+
+None of these touch a GPU: the library loads without one, and lsnif_desc_bytes
+only validates and counts.
+"""
+
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import workloads as W
+from workloads.objects import LsnifObject, make_weights
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2504_21627_amd import lsnif
+    lsnif.load()
+    return lsnif
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(lsnif_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_function(L):
+    names = declared_functions()
+    assert {"lsnif_create", "lsnif_build", "lsnif_query", "lsnif_query_debug"} <= names
+    lib = L.load()
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\b(lsnif_[a-z_0-9]+)$", out, flags=re.M))
+    assert names <= exported, names - exported
+
+
+def paper_default_object():
+    """The paper's default LSNIF (Sec. 5.1): V = 32, two face-aligned levels (64, 128) of
+    2^17 entries x 3 features, H = 18, 108 -> 128 -> 128 -> 12 leaky-ReLU MLP with an
+    albedo head and 4 materials."""
+    V, L_, F, H = 32, 2, 3, 18
+    rng = np.random.default_rng(0)
+    dims = [H * L_ * F, 128, 128, 5 + 3 + 4]
+    return LsnifObject(bmin=np.full(3, -1, np.float32), bmax=np.full(3, 1, np.float32), V=V,
+                       occ=np.zeros(V ** 3 // 32, np.uint32), L=L_, F=F, log2_T=17,
+                       R=np.array([64, 128], np.int32),
+                       tables=np.zeros((L_, 1 << 17, F), np.float32), H=H,
+                       weights=make_weights(rng, dims), act=1, leaky_slope=0.01, n_mat=4,
+                       has_albedo=1)
+
+
+def test_footprint_matches_paper(L):
+    """4 KB of voxels + 1,536 KB of grid + ~62 KB of network (Sec. 5.1), about 1.56 MB."""
+    obj = paper_default_object()
+    assert obj.out_dim == 8 + obj.n_mat                        # 8 + N_mat outputs (Sec. 5.1)
+    b = L.lsnif_desc_bytes(L.ObjectDesc(obj, "fp16", "fp16"))
+    assert b == 4 * 1024 + 1536 * 1024 + 62 * 1024
+    assert abs(b / 2 ** 20 - 1.56) < 0.01
+
+
+@pytest.mark.parametrize("M,kb", [(2 ** 8, 3), (2 ** 11, 24), (2 ** 14, 192), (2 ** 17, 1536)])
+def test_grid_bytes_vs_hash_map_size(L, M, kb):
+    """Grid bytes for the hash-map sizes of the paper's parameter study (2 levels x 3 FP16)."""
+    obj = paper_default_object()
+    obj.log2_T = int(np.log2(M))
+    obj.tables = np.zeros((2, M, 3), np.float32)
+    b = L.lsnif_desc_bytes(L.ObjectDesc(obj, "fp16", "fp16"))
+    assert b - 4 * 1024 - 62 * 1024 == kb * 1024
+
+
+@pytest.mark.parametrize("field,value", [("V", 48), ("V", 2048), ("H", 7), ("H", 0), ("L", 0),
+                                         ("L", 40), ("log2_T", 31), ("F", 5), ("n_mat", 20)])
+def test_invalid_descriptors_rejected(L, field, value):
+    obj = W.configs.c1_object()
+    d = L.ObjectDesc(obj)
+    setattr(d.d, field, value)
+    with pytest.raises(L.LsnifError) as e:
+        L.lsnif_desc_bytes(d)
+    assert e.value.status == L.LSNIF_E_INVALID
+    assert L.lsnif_last_error()
+
+
+def test_c2_footprint(L):
+    obj = W.configs.c2_object()
+    b16 = L.lsnif_desc_bytes(L.ObjectDesc(obj, "fp16", "fp16"))
+    b32 = L.lsnif_desc_bytes(L.ObjectDesc(obj, "fp32", "fp32"))
+    tab16 = 16 * 2 ** 19 * 2 * 2
+    mlp = 576 * 64 + 64 * 64 * 2 + 64 * 9
+    assert b16 == 128 ** 3 // 8 + tab16 + 2 * mlp
+    assert b32 == 128 ** 3 // 8 + 2 * tab16 + 4 * mlp

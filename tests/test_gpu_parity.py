@@ -264,3 +264,32 @@ def test_debug_buffer_subsets(L, ctx, c1, mlp):
                 assert bitwise_equal(v.cpu().numpy(), full[k]), (keys, k)
     finally:
         L.lsnif_release(ctx, oid)
+
+
+@pytest.mark.parametrize("mlp", ["fp32", "fp16"])
+def test_grazing_recheck_parity(L, ctx, mlp):
+    """With the float64 grazing recheck on, voxel lists, points and slots equal the oracle's
+    bit for bit on rays aimed at lattice edges, and some lists differ from the float32 ones."""
+    import dataclasses
+    from tests.test_oracle_pins import tiny_object, edge_grazing_rays
+    V = 8
+    rng = np.random.default_rng(7)
+    occ = rng.uniform(size=V ** 3) < 0.8
+    base = tiny_object(V, occ, H=48, L=2, F=2, R=[V, 2 * V], log2_T=10, width=64, n_hidden=3,
+                       bmin=(0, 0, 0), bmax=(V, V, V), seed=3)
+    rays = edge_grazing_rays(rng, V, 2048)
+    feat = "fp32" if mlp == "fp32" else "fp16"
+    counts = {}
+    for recheck in (0, 1):
+        obj = dataclasses.replace(base, grazing_recheck=recheck)
+        _say(f"grazing recheck={recheck} {feat}/{mlp}: {len(rays)} rays")
+        oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
+        try:
+            g = gpu_query(L, ctx, oid, rays, debug=True, obj=obj)
+            o = oracle.query(obj, rays, debug=True)
+            check_intermediates(g, o, obj)
+            counts[recheck] = o["vox_ijk"].copy()
+        finally:
+            L.lsnif_release(ctx, oid)
+    changed = np.any(counts[0] != counts[1], axis=(1, 2)).sum()
+    assert changed >= 20, changed

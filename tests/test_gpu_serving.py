@@ -1,0 +1,102 @@
+"""Serving on the GPU: continuous batching gives each request the answer it gets alone."""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_2504_21627_amd import lsnif
+    return lsnif
+
+
+@pytest.fixture(scope="module")
+def scene():
+    objs = [W.configs.c4_object(i) for i in range(16)]
+    insts, boxes = W.configs.c5_instances(objs, seed=5)
+    pool = W.configs.c5_pool(objs, n_secondary=1 << 17, side=256, seed=5)
+    rays = pool["rays"]
+    pr, pi = W.configs.ray_box_pairs(rays, boxes)
+    windows = W.configs.c5_requests(pool["n_primary"], len(rays), n_requests=40, lo=256, hi=1 << 15, seed=7)
+    return objs, insts, rays, pr, pi, windows
+
+
+def bits(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def test_serving_matches_alone(L, scene):
+    import torch
+    from paper_2504_21627_amd.serving import RequestSet
+    objs, insts, rays, pr, pi, windows = scene
+    ctx = L.lsnif_create(0)
+    try:
+        ids = [L.lsnif_build(ctx, L.ObjectDesc(o, "fp16", "fp16")) for o in objs]
+        insts_dev = [(ids[k], m) for k, m in insts]
+        rs = RequestSet(L, rays, pr, pi, insts_dev, windows)
+        # alone: each request by itself through the direct call
+        alone = []
+        for j in range(len(windows)):
+            out = torch.empty_like(rs.outs[j])
+            L.lsnif_query_pairs(ctx, rs.rays_of(j), rs.pr[j], rs.pi[j], rs.inst, out)
+            alone.append(out)
+        torch.cuda.synchronize()
+        # in the mix: all submitted at once to the serving loop, 4 streams, 6 slots
+        L.lsnif_serve_start(ctx, max_inflight=6, hbm_budget=256 << 20, n_streams=4)
+        tickets = [L.lsnif_serve_submit(ctx, rs.request(j)) for j in range(len(windows))]
+        for t in tickets:
+            assert L.lsnif_serve_wait(ctx, t, 60_000_000_000) == L.LSNIF_OK
+        st = L.lsnif_serve_stats_get(ctx)
+        L.lsnif_serve_stop(ctx)
+        print({k: st[k] for k in ("completed", "rays_completed", "p50_ms", "p99_ms", "ws_bytes_peak")})
+        assert st["completed"] == len(windows) and st["failed"] == 0
+        for j in range(len(windows)):
+            assert np.array_equal(bits(alone[j]), bits(rs.outs[j])), j
+        # and the direct answers themselves agree with the oracle on a few requests
+        for j in (0, 1, 2):
+            s, n, _ = windows[j]
+            o = oracle.query_pairs(objs, insts, rays[s:s + n], rs.pr[j].cpu().numpy().astype(np.uint32),
+                                   rs.pi[j].cpu().numpy().astype(np.uint32))
+            g = alone[j].cpu().numpy()
+            agree = (g[:, 0].view(np.uint32) == o["hit"]).mean()
+            assert agree >= 0.99, (j, agree)
+    finally:
+        L.lsnif_destroy(ctx)
+
+
+def test_serving_budget_and_overlap(L, scene):
+    """A budget that fits one large request at a time still completes everything; several
+    small requests overlap (more than one in flight at once)."""
+    import torch
+    from paper_2504_21627_amd.serving import RequestSet
+    objs, insts, rays, pr, pi, windows = scene
+    ctx = L.lsnif_create(0)
+    try:
+        ids = [L.lsnif_build(ctx, L.ObjectDesc(o, "fp16", "fp16")) for o in objs]
+        rs = RequestSet(L, rays, pr, pi, [(ids[k], m) for k, m in insts], windows)
+        L.lsnif_serve_start(ctx, max_inflight=8, hbm_budget=48 << 20, n_streams=4)
+        tickets = [L.lsnif_serve_submit(ctx, rs.request(j)) for j in range(len(windows))]
+        peak_inflight = 0
+        while True:
+            s = L.lsnif_serve_stats_get(ctx)
+            peak_inflight = max(peak_inflight, s["inflight"])
+            if s["completed"] + s["failed"] >= len(windows):
+                break
+            time.sleep(0.0002)
+        for t in tickets:
+            assert L.lsnif_serve_wait(ctx, t) == L.LSNIF_OK
+        s = L.lsnif_serve_stats_get(ctx)
+        L.lsnif_serve_stop(ctx)
+        assert s["ws_bytes_peak"] <= 48 << 20
+        assert peak_inflight >= 2
+    finally:
+        L.lsnif_destroy(ctx)

@@ -101,3 +101,204 @@ def subsample(rays, n, seed=12345):
         return rays
     idx = np.sort(np.random.Generator(np.random.PCG64(seed)).choice(len(rays), n, replace=False))
     return rays[idx]
+
+
+# ----------------------------------------------------------------------------- c4
+C4_OBJECTS = 64
+C4_TOTAL_RAYS = 1 << 24
+
+
+def c4_ray_counts(n_objects=C4_OBJECTS, total=C4_TOTAL_RAYS, lo=1e3, hi=1e6, seed=4):
+    """Per-object ray counts: the mid-quantiles of a power law p(n) ~ n^-beta truncated to
+    [lo, hi], beta solved so that the rounded counts sum to `total`; assigned to objects by a
+    seeded permutation."""
+    from scipy.optimize import brentq
+
+    def counts(beta):
+        q = (np.arange(n_objects) + 0.5) / n_objects
+        e = 1.0 - beta
+        return (lo ** e + q * (hi ** e - lo ** e)) ** (1.0 / e)
+
+    beta = brentq(lambda b: counts(b).sum() - total, 0.05, 0.99)
+    c = np.round(counts(beta)).astype(np.int64)
+    c[-1] += total - c.sum()
+    perm = np.random.Generator(np.random.PCG64(seed)).permutation(n_objects)
+    return c[perm], beta
+
+
+def c4_object_params(i, seed_base=100):
+    """Shape, triangle count, V, L and log2_T of c4 object i (seeded per object)."""
+    rng = streams(seed_base + i)[GEOMETRY]
+    kind = ("torus", "displaced-sphere", "box-soup")[i % 3]
+    n_tris = int(round(np.exp(rng.uniform(np.log(1e3), np.log(5e5)))))
+    V = int(rng.choice([32, 64, 128, 256]))
+    L = int(rng.integers(8, 17))
+    log2_T = int(rng.integers(14, 20))
+    return kind, n_tris, V, L, log2_T, rng
+
+
+def c4_mesh(i, seed_base=100):
+    from .meshes import torus, box_soup
+    kind, n_tris, V, L, log2_T, rng = c4_object_params(i, seed_base)
+    if kind == "torus":
+        verts, tris = torus(n_tris)
+    elif kind == "displaced-sphere":
+        stacks = max(int(round((n_tris / 4.0) ** 0.5)), 3)
+        verts, tris = displaced_sphere(rng, slices=2 * stacks, stacks=stacks, amplitude=0.1)
+    else:
+        verts, tris = box_soup(rng, n_tris)
+    return verts, tris
+
+
+def c4_object(i, seed_base=100):
+    kind, n_tris, V, L, log2_T, _ = c4_object_params(i, seed_base)
+    verts, tris = c4_mesh(i, seed_base)
+    s = float(np.abs(verts).max()) * 1.05
+    bmin, bmax = [-s] * 3, [s] * 3
+    occ = _cached_voxels(f"c4-{seed_base}-{i}-{V}", verts, tris, V, bmin, bmax)
+    R = level_resolutions(16, 16 * V, L)
+    return make_object(verts, tris, V=V, bmin=bmin, bmax=bmax, L=L, F=2, log2_T=log2_T, R=R,
+                       H=18, n_hidden=3, width=64, n_mat=4, seed=seed_base + i,
+                       name=f"c4-{i}-{kind}-{len(tris)}tri-V{V}-L{L}-T{log2_T}", occ=occ)
+
+
+def c4(n_objects=C4_OBJECTS, total=C4_TOTAL_RAYS, scale=1.0, seed_base=100):
+    """64 objects with power-law ray counts (16,777,216 pairs at scale 1).
+
+    Rays of object k are in its object space: half from its AABB's bounding sphere toward
+    the centre, half leaving its surface (balanced sampling).  ``scale`` shrinks every
+    ray count (for tests).  Returns objects, rays (all objects concatenated, object-major)
+    and the object index of each ray.
+    """
+    from .rays import balanced_rays
+    counts, beta = c4_ray_counts(n_objects, total)
+    counts = np.maximum((counts * scale).astype(np.int64), 1)
+    objects, rays, owner = [], [], []
+    for i in range(n_objects):
+        obj = c4_object(i, seed_base)
+        verts, tris = c4_mesh(i, seed_base)
+        r = balanced_rays(streams(seed_base + i)[RAYS], verts, tris, int(counts[i]),
+                          obj.bmin.astype(np.float64), obj.bmax.astype(np.float64))
+        objects.append(obj)
+        rays.append(r)
+        owner.append(np.full(len(r), i, np.uint32))
+    return {"name": "c4", "objects": objects, "rays": np.concatenate(rays),
+            "owner": np.concatenate(owner), "counts": counts, "beta": beta}
+
+
+# ----------------------------------------------------------------------------- c5
+def c5_instances(objects, seed=5, spacing=3.0):
+    """c4's objects as instances on an 8 x 8 grid with seeded yaw and scale in [0.8, 1.2].
+
+    Returns [(object index, world_to_object 3x4)] and the world-space AABBs."""
+    rng = streams(seed)[GEOMETRY]
+    insts, boxes = [], []
+    n = len(objects)
+    side = int(np.ceil(np.sqrt(n)))
+    for k, obj in enumerate(objects):
+        i, j = k % side, k // side
+        c = np.array([spacing * i - spacing * (side - 1) / 2, 0.0, spacing * j - spacing * (side - 1) / 2])
+        th = rng.uniform(0, 2 * np.pi)
+        s = rng.uniform(0.8, 1.2)
+        Rm = np.array([[np.cos(th), 0, np.sin(th)], [0, 1, 0], [-np.sin(th), 0, np.cos(th)]])
+        A = Rm.T / s                      # world -> object
+        b = -A @ c
+        insts.append((k, np.concatenate([A, b[:, None]], 1).astype(np.float32)))
+        corners = np.array([[x, y, z] for x in obj.bmin[[0]].tolist() + obj.bmax[[0]].tolist()
+                            for y in obj.bmin[[1]].tolist() + obj.bmax[[1]].tolist()
+                            for z in obj.bmin[[2]].tolist() + obj.bmax[[2]].tolist()], np.float64)
+        w = (s * (Rm @ corners.T)).T + c
+        boxes.append((w.min(0), w.max(0)))
+    return insts, boxes
+
+
+def ray_box_pairs(rays, boxes, chunk=1 << 17):
+    """Brute-force broad phase: every (ray, instance) whose slab interval overlaps
+    [tmin, tmax] with positive length; sorted by instance, then ray."""
+    lo = np.array([b[0] for b in boxes], np.float32)     # (k, 3)
+    hi = np.array([b[1] for b in boxes], np.float32)
+    pr, pi = [], []
+    for s in range(0, len(rays), chunk):
+        r = rays[s:s + chunk]
+        with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+            inv = (np.float32(1.0) / r[:, 3:6])
+            tn = np.maximum(r[:, 6:7], np.full((len(r), 1), -np.inf, np.float32))
+            tn = np.broadcast_to(tn, (len(r), len(boxes))).copy()
+            tf = np.broadcast_to(r[:, 7:8], (len(r), len(boxes))).copy()
+            for a in range(3):
+                t0 = (lo[None, :, a] - r[:, a:a + 1]) * inv[:, a:a + 1]
+                t1 = (hi[None, :, a] - r[:, a:a + 1]) * inv[:, a:a + 1]
+                np.maximum(tn, np.nan_to_num(np.minimum(t0, t1), nan=-np.inf), out=tn)
+                np.minimum(tf, np.nan_to_num(np.maximum(t0, t1), nan=np.inf), out=tf)
+        ray_i, inst_i = np.nonzero(tn < tf)
+        pr.append(ray_i + s)
+        pi.append(inst_i)
+    pr, pi = np.concatenate(pr).astype(np.uint32), np.concatenate(pi).astype(np.uint32)
+    order = np.lexsort((pr, pi))
+    return pr[order], pi[order]
+
+
+def _instance_surface(rng, meshes, insts, n):
+    """World-space area-uniform points on randomly chosen instances, with world normals."""
+    from .rays import surface_points
+    k = rng.integers(0, len(insts), n)
+    P = np.empty((n, 3))
+    N = np.empty((n, 3))
+    for idx in np.unique(k):
+        sel = np.nonzero(k == idx)[0]
+        verts, tris = meshes[insts[idx][0]]
+        p, nrm = surface_points(rng, verts, tris, len(sel))
+        m = insts[idx][1].astype(np.float64)
+        A, b = m[:, :3], m[:, 3]
+        Ainv = np.linalg.inv(A)
+        P[sel] = (p - b) @ Ainv.T
+        nw = nrm @ A                                   # normals go with A^T
+        N[sel] = nw / np.linalg.norm(nw, axis=1, keepdims=True)
+    return P, N
+
+
+C5_LIGHT = (5.0, 20.0, -5.0)
+
+
+def c5_pool(objects, n_secondary=3 << 20, side=1024, seed=5):
+    """Rays a path tracer over the c5 scene would ask about, in world space.
+
+    Rays [0, side^2) are the primary rays of a pinhole camera in row-major
+    pixel order; the rest are secondary: half cosine-weighted bounces leaving
+    instance surfaces, half shadow rays from instance surfaces toward a point
+    light (tmax = distance)."""
+    from .rays import pinhole_rays, ray_array, _cosine_about
+    insts, boxes = c5_instances(objects, seed)
+    meshes = [c4_mesh(i) for i in range(len(objects))]
+    prim = pinhole_rays(side, side, eye=(0.0, 18.0, -22.0), look_at=(0.0, 0.0, 0.0),
+                        up=(0.0, 1.0, 0.0), vfov_deg=50.0)
+    rng = streams(seed)[RAYS]
+    half = n_secondary // 2
+    P, N = _instance_surface(rng, meshes, insts, half)
+    bounce = ray_array(P + 1e-4 * N, _cosine_about(rng, N))
+    P, N = _instance_surface(rng, meshes, insts, n_secondary - half)
+    o = P + 1e-4 * N
+    to = np.asarray(C5_LIGHT)[None] - o
+    dist = np.linalg.norm(to, axis=1)
+    shadow = ray_array(o, to / dist[:, None], 0.0, dist)
+    sec = np.concatenate([bounce, shadow])
+    sec = sec[rng.permutation(len(sec))]
+    return {"rays": np.concatenate([prim, sec]), "n_primary": side * side, "insts": insts, "boxes": boxes}
+
+
+def c5_requests(n_primary, n_total, n_requests=2000, lo=256, hi=1 << 21, seed=6):
+    """Request windows of the pool: size log-uniform in [lo, hi], depth uniform in 1..4.
+    Depth 1 draws from the primary region, depths 2-4 from the secondary region."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(n_requests):
+        n = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        depth = int(rng.integers(1, 5))
+        if depth == 1:
+            n = min(n, n_primary)
+            s = int(rng.integers(0, n_primary - n + 1))
+        else:
+            n = min(n, n_total - n_primary)
+            s = n_primary + int(rng.integers(0, n_total - n_primary - n + 1))
+        out.append((s, n, depth))
+    return out
