@@ -116,7 +116,7 @@ def bytes_per_point(obj, feat_bytes=2):
     return sum(4 if int(R) % obj.V == 0 else 8 for R in obj.R) * obj.F * feat_bytes
 
 
-def bench_c4(L, steps, warmup):
+def bench_c4(L, steps, warmup, tune=True):
     """64 objects, 16,777,216 (ray, object) pairs with power-law counts, one pair query per step
     (identity instances), timed as direct calls and as replays of a captured graph."""
     import torch
@@ -134,7 +134,8 @@ def bench_c4(L, steps, warmup):
         pr = torch.arange(n, dtype=torch.int32, device="cuda")
         pi = torch.from_numpy(owner.astype(np.int32)).cuda()
         out = torch.empty((n, 6), dtype=torch.float32, device="cuda")
-        print(f"[bench] timing c4 direct: {warmup} warmup + {steps} steps", file=sys.stderr, flush=True)
+        tuning = L.lsnif_autotune_pairs(ctx, rays, pr, pi, inst, out) if tune else L.lsnif_get_tuning(ctx, ids[0])
+        print(f"[bench] timing c4 direct ({tuning}): {warmup} warmup + {steps} steps", file=sys.stderr, flush=True)
         wall_d, lat_d, prep_ms, kern_ms = time_calls(
             L, ctx, lambda st: L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out, st), steps, warmup)
         g = L.lsnif_graph_pairs(ctx, rays, pr, pi, inst, out)
@@ -165,7 +166,7 @@ def bench_c4(L, steps, warmup):
         "workload": "c4: 64 objects (tori, displaced spheres, box soups; 1k-500k triangles; V 32-256; "
                     "8-16 levels x 2^14-2^19 entries x 2 fp16 features; MLP 3x64 fp16), 16,777,216 "
                     "(ray, object) pairs, power-law counts 1,189-977,190 per object, one pair query",
-        "pairs": n, "objects": len(objs),
+        "pairs": n, "objects": len(objs), "tuning": tuning,
         "direct": {"value": val(wall_d), "unit": "Mpairs/s", "ms_per_step": wall_d * 1e3 / steps,
                    "p50_ms": float(np.percentile(lat_d, 50)), "p99_ms": float(np.percentile(lat_d, 99)),
                    "prepare_ms": prep_ms, "kernel_ms": kern_ms},
@@ -264,12 +265,16 @@ def bench_c2(L, args):
         if args.only and name != args.only:
             continue
         oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
-        print(f"[bench] timing the {name} path: {args.warmup} warmup + {args.steps} steps",
+        if args.tuning:
+            L.lsnif_set_tuning(ctx, oid, *[int(x) for x in args.tuning.split(",")])
+        tuning = (L.lsnif_autotune(ctx, oid, rays, out) if not (args.no_tune or args.tuning)
+                  else L.lsnif_get_tuning(ctx, oid))
+        print(f"[bench] timing the {name} path ({tuning}): {args.warmup} warmup + {args.steps} steps",
               file=sys.stderr, flush=True)
         wall, lat, sort_ms, kern_ms = time_path(L, ctx, oid, rays, out, args.steps, args.warmup)
         pts, cand = points_per_launch(L, ctx, oid, rays, out)
         paths[name] = {"wall": wall, "lat": lat, "points": pts, "cand": cand, "sort_ms": sort_ms,
-                       "kern_ms": kern_ms, "feat_bytes": 2 if feat == "fp16" else 4}
+                       "kern_ms": kern_ms, "feat_bytes": 2 if feat == "fp16" else 4, "tuning": tuning}
         L.lsnif_release(ctx, oid)
     L.lsnif_destroy(ctx)
 
@@ -303,12 +308,13 @@ def bench_c2(L, args):
                      "alg_bytes_per_launch": alg_bytes, "points_per_launch": head["points"],
                      "bytes_per_point": bpp, "mean_kernel_ms": mean_ms,
                      "mean_sort_ms": float(head["sort_ms"]),
+                     "tuning": head["tuning"],
                      "mfma_tflops": flops / (mean_ms * 1e-3) / 1e12,
                      "mfma_frac": flops / (mean_ms * 1e-3) / 1e12 / MFMA_FP16_PEAK_TFLOPS},
     }
     if "fp32" in paths:
         p = paths["fp32"]
-        rec["fp32_plain"] = {"value": n / (p["wall"] / args.steps) / 1e6, "unit": "Mrays/s",
+        rec["fp32_plain"] = {"value": n / (p["wall"] / args.steps) / 1e6, "unit": "Mrays/s", "tuning": p["tuning"],
                              "p50_ms": float(np.percentile(p["lat"], 50)),
                              "p99_ms": float(np.percentile(p["lat"], 99))}
         if "fp16" in paths:
@@ -328,6 +334,10 @@ def main():
     ap.add_argument("--legs", default="c2,c4,c5",
                     help="comma list: c2 (headline), c4 (batched objects), c5 (serving)")
     ap.add_argument("--c5-requests", type=int, default=2000)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tuning (no autotuner)")
+    ap.add_argument("--tuning", default=None,
+                    help="sort_bits,pair_bits,hot_lds_bytes for the c2 object instead of the autotuner "
+                         "(profiling runs repeat the tuning the autotuner chose)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first copy a device buffer of this size (MiB): the copy of known size "
                          "against which rocprofv3's FETCH_SIZE/WRITE_SIZE counters are scaled")
@@ -354,7 +364,7 @@ def main():
         rec = {"metric": "Mrays/s LSNIF queries (FP16 MFMA vs FP32 plain) + p50/p99 batch latency",
                "legs": sorted(legs), "note": "headline (c2) leg not run"}
     if "c4" in legs:
-        rec["batched_c4"] = bench_c4(L, max(args.steps // 10, 5), min(args.warmup, 3))
+        rec["batched_c4"] = bench_c4(L, max(args.steps // 10, 5), min(args.warmup, 3), not args.no_tune)
     if "c5" in legs:
         rec["serving_c5"] = bench_c5(L, args.c5_requests)
     if not args.no_cpu and "c2" in legs:

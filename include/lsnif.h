@@ -211,6 +211,45 @@ lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
                                const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out,
                                void *stream);
 
+/* ------------------------------------------------------------------ tuning
+ *
+ * Launch parameters of an object that change speed but never a result (a
+ * ray's answer does not depend on which rays share its tile or in what order
+ * rays run, nor on whether a table entry is read from HBM or from LDS):
+ *  sort_bits      single-object queries of at least 8192 rays are first sorted
+ *                 by direction octant and by the cell of the voxel grid where
+ *                 the ray's segment starts, 2^sort_bits cells per axis
+ *                 (0 = no sort, 1..5); rays that meet the grid close together
+ *                 then share 256-ray tiles (the work decomposition of Sec. 4:
+ *                 dispatch sorted rays rather than scattered ones).
+ *  pair_bits      the same grouping, 2^pair_bits cells per axis (1..4), for the
+ *                 object's pairs in pair queries, within the object's tiles.
+ *  hot_lds_bytes  LDS per workgroup for the object's coarsest levels (0..40960):
+ *                 those levels, all of whose used entries fit, are copied into
+ *                 LDS by every workgroup and gathered from there.
+ * lsnif_autotune times each candidate (sort_bits 0, 3, 4, 5 x hot_lds_bytes 0,
+ * 20480, 40960) on the caller's batch, a warm-up and three timed queries each
+ * on a private stream, keeps the fastest for the object and returns it.
+ * lsnif_autotune_pairs does the same for a pair query (pair_bits 2, 3, 4 x
+ * hot_lds_bytes), applying one choice to every object of the context.  Both
+ * overwrite d_out, synchronise the device and, like lsnif_set_tuning, make the
+ * context's captured graphs stale.
+ */
+typedef struct {
+    int32_t sort_bits;
+    int32_t pair_bits;
+    int32_t hot_lds_bytes;
+} lsnif_tuning;
+
+lsnif_status lsnif_get_tuning(lsnif_ctx *ctx, uint32_t object_id, lsnif_tuning *tuning);
+lsnif_status lsnif_set_tuning(lsnif_ctx *ctx, uint32_t object_id, const lsnif_tuning *tuning);
+lsnif_status lsnif_autotune(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
+                            lsnif_hit *d_out, lsnif_tuning *best);
+lsnif_status lsnif_autotune_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t n_rays,
+                                  const uint32_t *d_pair_ray, const uint32_t *d_pair_inst, uint32_t n_pairs,
+                                  const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out,
+                                  lsnif_tuning *best);
+
 /* ------------------------------------------------------------------ graphs
  *
  * A query captured once into a HIP graph and replayed with one launch.  A

@@ -8,7 +8,7 @@ template <typename TF, int F, int KBM>
 static void go(const QueryArgs &A, bool pairs, uint32_t grid, hipStream_t s)
 {
     // voxel lists of H/2 entries per lane (for pairs, H is the largest over the objects)
-    const size_t lds = (size_t)(A.g.H >> 1) * kBlock * sizeof(uint32_t);
+    const size_t lds = (size_t)(A.g.H >> 1) * kBlock * sizeof(uint32_t) + A.hot_lds;
     if (pairs) hipLaunchKernelGGL((k_query_mma<TF, _Float16, F, 64, KBM, true>), dim3(grid), dim3(kBlock), lds, s, A);
     else hipLaunchKernelGGL((k_query_mma<TF, _Float16, F, 64, KBM, false>), dim3(grid), dim3(kBlock), lds, s, A);
 }

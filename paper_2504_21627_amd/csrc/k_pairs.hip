@@ -1,8 +1,8 @@
 // Instanced pair queries: the work list and the nearest-hit update.
 //
 // Before the query kernel, the (ray, instance) pairs are grouped by object
-// and, within an object, by direction octant and the 8^3 cell of the segment
-// start in that object's voxel grid (a counting sort with wave-aggregated
+// and, within an object, by direction octant and the cell (2^b per axis,
+// b <= 4 chosen per object) of the segment start in that object's voxel grid (a counting sort with wave-aggregated
 // atomics).  Each object's run is padded to whole 256-slot tiles, so every
 // workgroup of the query kernel serves one object with one set of weights.
 // Pairs whose ray misses the object's box, or that name a ray, instance or
@@ -39,10 +39,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs_fill(PairPlan P)
     if (i < P.n_tiles) P.tile_obj[i] = -1;
 }
 
-__device__ __forceinline__ uint32_t spread3(uint32_t x)
+__device__ __forceinline__ uint32_t spread4(uint32_t x)
 {
-    x &= 7u;
-    return (x & 1u) | ((x & 2u) << 2) | ((x & 4u) << 4);
+    x &= 15u;
+    return (x & 1u) | ((x & 2u) << 2) | ((x & 4u) << 4) | ((x & 8u) << 6);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pairs_keys(PairPlan P)
@@ -61,16 +61,17 @@ __global__ __launch_bounds__(kBlock) void k_pairs_keys(PairPlan P)
                 setup_ray(g, ra, rb, w);
                 if (w.cand) {
                     uint32_t c[3];
-                    const float sc = 8.0f / (float)g.V;
+                    const float cells = (float)(1u << g.pair_bits);
+                    const float sc = cells / (float)g.V;
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         float x = (w.o[a] + w.ta * w.d[a]) * sc;
-                        x = x < 0.0f ? 0.0f : (x > 7.0f ? 7.0f : x);
+                        x = x < 0.0f ? 0.0f : (x > cells - 1.0f ? cells - 1.0f : x);
                         c[a] = (uint32_t)x;
                     }
                     const uint32_t oct = (w.d[0] < 0.0f ? 1u : 0u) | (w.d[1] < 0.0f ? 2u : 0u) |
                                          (w.d[2] < 0.0f ? 4u : 0u);
-                    bin = o * kPairBins + ((oct << 9) | spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2));
+                    bin = o * kPairBins + ((oct << 12) | spread4(c[0]) | (spread4(c[1]) << 1) | (spread4(c[2]) << 2));
                 }
             }
         }

@@ -1,6 +1,7 @@
 // Coherence order of a ray batch: a one-pass counting sort of the rays by a
-// coarse key -- direction octant, then the Morton code of the 32^3 cell of the
-// voxel grid where the ray's segment [ta, tb] starts.  Rays that meet the
+// coarse key -- direction octant, then the Morton code of the cell (2^b per
+// axis, b <= 5 chosen per object) of the voxel grid where the ray's segment
+// [ta, tb] starts.  Rays that meet the
 // grid close together and head the same way then share waves, so their
 // walks and their hash-grid gathers touch the same cache lines.  Order within
 // a key is whatever the atomics give; every ray's result is independent of
@@ -25,11 +26,12 @@ __device__ __forceinline__ uint32_t coherence_key(const Geom &g, float4 r0, floa
     setup_ray(g, r0, r1, w);
     if (!w.cand) return kSortBins - 1;
     uint32_t cell[3];
-    const float sc = 32.0f / (float)g.V;
+    const float cells = (float)(1u << g.sort_bits);
+    const float sc = cells / (float)g.V;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float x = (w.o[a] + w.ta * w.d[a]) * sc;
-        x = x < 0.0f ? 0.0f : (x > 31.0f ? 31.0f : x);
+        x = x < 0.0f ? 0.0f : (x > cells - 1.0f ? cells - 1.0f : x);
         cell[a] = (uint32_t)x;
     }
     const uint32_t oct = (w.d[0] < 0.0f ? 1u : 0u) | (w.d[1] < 0.0f ? 2u : 0u) | (w.d[2] < 0.0f ? 4u : 0u);

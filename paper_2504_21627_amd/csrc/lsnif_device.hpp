@@ -16,6 +16,7 @@ namespace lsnif {
 constexpr int kMaxLevels = 32;
 constexpr int kMaxList = 32;          // H/2 <= 32
 constexpr int kCoarseLdsWords = 2048; // brick bits staged in LDS when the grid has <= 65536 bricks
+constexpr uint32_t kHotLdsBudget = 40 << 10;  // LDS bytes per block for hot levels (two blocks per CU still fit)
 constexpr uint32_t kTablePad = 16;     // spare bytes after an object's tables (a paired gather may read one entry past the slot it needs)
 constexpr uint32_t kPrimeY = 2654435761u;   // spatial hash of Mueller et al. 2022, Eq. 4
 constexpr uint32_t kPrimeZ = 805459861u;
@@ -42,6 +43,11 @@ struct Geom {
     uint32_t dense_mask;      // bit l: level l indexed directly ((R+1)^3 <= T)
     uint32_t aligned_mask;    // bit l: R % V == 0, the crossing-axis weight is 0 or 1
     uint32_t recheck;         // 1: grazing voxels of the walk are re-decided in float64
+    uint32_t sort_bits;       // coherence sort of single-object batches: 2^bits cells per axis (0 = no sort, <= 5)
+    uint32_t pair_bits;       // grouping of pairs within an object: 2^bits cells per axis (<= 4)
+    uint32_t hot_mask;        // bit l: level l is copied into LDS for the launch (hot level)
+    uint32_t hot_bytes;       // LDS bytes of the hot levels
+    uint32_t hot_off[kMaxLevels], hot_len[kMaxLevels];   // LDS byte offset, bytes copied (multiples of 16)
     int32_t R[kMaxLevels];
     float lsc[kMaxLevels];    // (float)R / (float)V
     uint32_t my[kMaxLevels], mz[kMaxLevels], dmask[kMaxLevels], hmask[kMaxLevels];

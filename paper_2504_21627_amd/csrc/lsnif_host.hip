@@ -298,6 +298,8 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
     g.log2_T = d->log2_T;
     g.H = d->H;
     g.recheck = d->grazing_recheck ? 1u : 0u;
+    g.sort_bits = 5;
+    g.pair_bits = d->V >= 64 ? 4 : 3;
     const uint64_t T = (uint64_t)1 << d->log2_T;
     for (int l = 0; l < d->L; ++l) {
         g.R[l] = d->R[l];
@@ -317,6 +319,8 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
         }
         if (d->R[l] % d->V == 0) g.aligned_mask |= 1u << l;
     }
+    ob.esz = (uint32_t)(d->F * dtype_size(d->feat_dtype));
+    plan_hot_levels(g, ob.esz, kHotLdsBudget);
     // occupancy as 4x4x4 bricks: one 64-bit mask per brick, then one bit per brick
     const int V = d->V, NB = (V + 3) / 4;
     const size_t nbricks = (size_t)NB * NB * NB;
@@ -465,17 +469,6 @@ lsnif_status lsnif_profile_read(lsnif_ctx *ctx, double *sort_ms, double *kernel_
     return st;
 }
 
-static lsnif_status grow(void *&buf, size_t &have, size_t need)
-{
-    if (need <= have) return LSNIF_OK;
-    (void)hipFree(buf);   // waits for work that may still use the old buffer
-    buf = nullptr;
-    have = 0;
-    if (hipMalloc(&buf, need) != hipSuccess)
-        return fail(LSNIF_E_NOMEM, "workspace of %llu bytes", (unsigned long long)need);
-    have = need;
-    return LSNIF_OK;
-}
 
 
 static lsnif_status run_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
@@ -488,7 +481,7 @@ static lsnif_status run_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ra
     lsnif_status st = check_query(ctx, object_id, d_rays, n, d_out, ob);
     if (st || n == 0) return st;
     DeviceGuard guard(ctx->device);
-    if (n >= kSortMin && (st = grow(ctx->ws, ctx->ws_bytes, query_ws_bytes(n)))) return st;
+    if (n >= kSortMin && (st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n)))) return st;
     return enqueue_query(ctx, *ob, d_rays, n, d_out, dbg, static_cast<hipStream_t>(stream), ctx->ws);
 }
 
@@ -504,7 +497,7 @@ lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
     PairsSetup ps;
     lsnif_status st = pairs_setup(ctx, ps);
     if (st) return st;
-    if ((st = grow(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs)))) return st;
+    if ((st = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs)))) return st;
     return enqueue_pairs(ctx, ps, d_rays, n_rays, d_pair_ray, d_pair_inst, n_pairs, d_inst, n_inst, d_out,
                          static_cast<hipStream_t>(stream), ctx->pws);
 }
@@ -526,6 +519,45 @@ lsnif_status lsnif_query_debug(lsnif_ctx *ctx, uint32_t object_id, const lsnif_r
 
 // ------------------------------------------------------------------ enqueue
 namespace lsnif {
+
+lsnif_status grow_workspace(void *&buf, size_t &have, size_t need)
+{
+    if (need <= have) return LSNIF_OK;
+    (void)hipFree(buf);   // waits for work that may still use the old buffer
+    buf = nullptr;
+    have = 0;
+    if (hipMalloc(&buf, need) != hipSuccess)
+        return fail(LSNIF_E_NOMEM, "workspace of %llu bytes", (unsigned long long)need);
+    have = need;
+    return LSNIF_OK;
+}
+
+// Hot levels: the coarsest levels, in order, while all their used slots (plus
+// the spare entry a paired gather may read) fit `budget` bytes of LDS and two
+// blocks still fit a CU (static LDS + voxel lists + hot levels within half of
+// its 160 KiB); 4- and 8-byte entries only.
+void plan_hot_levels(Geom &g, uint32_t esz, uint32_t budget)
+{
+    g.hot_mask = 0;
+    g.hot_bytes = 0;
+    for (int l = 0; l < kMaxLevels; ++l) g.hot_off[l] = g.hot_len[l] = 0;
+    if (esz != 4 && esz != 8) return;
+    const int64_t lds_left = (int64_t)(80 << 10) - (int64_t)sizeof(Shared) - (int64_t)(g.H / 2) * kBlock * 4;
+    const uint32_t cap = (uint32_t)std::max<int64_t>(0, std::min<int64_t>(std::min(budget, kHotLdsBudget), lds_left));
+    const uint64_t T = (uint64_t)1 << g.log2_T;
+    uint32_t off = 0;
+    for (int l = 0; l < g.L; ++l) {
+        const uint64_t side = (uint64_t)g.R[l] + 1;
+        const uint64_t used = (g.dense_mask >> l) & 1u ? side * side * side : T;
+        const uint64_t len = ((used + 1) * esz + 15) / 16 * 16;
+        if (off + len > cap) break;
+        g.hot_mask |= 1u << l;
+        g.hot_off[l] = off;
+        g.hot_len[l] = (uint32_t)len;
+        off += (uint32_t)len;
+    }
+    g.hot_bytes = off;
+}
 
 lsnif_status check_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
                          lsnif_hit *d_out, const Object *&ob)
@@ -573,6 +605,7 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
 {
     QueryArgs A{};
     A.g = ob.geom;
+    A.hot_lds = ob.geom.hot_bytes;
     A.m = ob.mlp;
     A.tables = ob.d_tab;
     A.rays = reinterpret_cast<const float4 *>(d_rays);
@@ -603,7 +636,7 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
             if (!(e = take_event(ctx))) return fail(LSNIF_E_DEVICE, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(ev[0], s));
     }
-    if (n >= kSortMin) {
+    if (n >= kSortMin && ob.geom.sort_bits) {
         uint32_t *keys = static_cast<uint32_t *>(ws);
         uint32_t *order = keys + n;
         uint32_t *hist = order + n;
@@ -659,12 +692,14 @@ lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps)
     ps.first = &ctx->objects.begin()->second;
     ps.kbm = 1;
     ps.maxH = 2;
+    ps.hot_max = 0;
     for (auto &kv : ctx->objects) {
         if (!same_class(kv.second, *ps.first))
             return fail(LSNIF_E_INVALID, "pair queries need every object of the context in one kernel class "
                                          "(feature type, MLP type, F, width)");
         ps.kbm = std::max(ps.kbm, kv.second.mlp.kb_point);
         ps.maxH = std::max(ps.maxH, kv.second.geom.H);
+        ps.hot_max = std::max(ps.hot_max, kv.second.geom.hot_bytes);
     }
     return upload_table(ctx, ps.n_objs);
 }
@@ -721,6 +756,7 @@ lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray
     if (n_pairs) {
         QueryArgs A{};
         A.g.H = ps.maxH;
+        A.hot_lds = ps.hot_max;   // every object's hot levels fit
         A.rays = P.rays;
         A.n = n_slots;
         A.pr.pair_ray = d_pair_ray;

@@ -31,6 +31,8 @@ struct Object {
     Mlp mlp{};
     void *d_occ = nullptr, *d_tab = nullptr, *d_w = nullptr;   // d_occ: brick masks, then brick bits
     int feat_dtype = 0, mlp_dtype = 0, F = 0, width = 0;
+    uint32_t esz = 0;             // bytes of one table entry on the device
+    uint32_t hot_budget = kHotLdsBudget;   // LDS budget the hot levels were planned for
     uint64_t bytes = 0;
 };
 
@@ -98,9 +100,14 @@ namespace lsnif {
 struct PairsSetup {
     const Object *first = nullptr;
     int kbm = 1, maxH = 2;
+    uint32_t hot_max = 0;   // largest hot-level LDS footprint of the objects
     uint32_t n_objs = 0;
 };
 lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps);
+// Grow a device workspace to `need` bytes (frees the old one, which waits for its users).
+lsnif_status grow_workspace(void *&buf, size_t &have, size_t need);
+// Choose an object's hot levels for an LDS budget (bytes).
+void plan_hot_levels(Geom &g, uint32_t esz, uint32_t budget);
 // Object `object_id` of ctx and the checks every single-object query makes.
 lsnif_status check_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
                          const Object *&ob);

@@ -85,6 +85,7 @@ struct QueryArgs {
     const uint32_t *order;    // processing order of the rays (coherence sort), or NULL
     Dbg dbg;
     PairArgs pr;
+    uint32_t hot_lds;         // dynamic LDS bytes after the voxel lists for hot levels
 };
 
 // Order-preserving map of a float to 32 unsigned bits.
@@ -263,6 +264,12 @@ __device__ __forceinline__ void level_cell_mm(const Geom &g, int l, const float 
     }
 }
 
+// Entries of 4 or 8 bytes take the paired gathers (and may be hot in LDS).
+template <typename TF, int F> constexpr bool paired_entries()
+{
+    return F * sizeof(TF) == 4 || F * sizeof(TF) == 8;
+}
+
 // Two table entries side by side, loaded with one instruction from a 4-byte
 // aligned address.
 template <int ESZ> struct EntryPair {
@@ -308,8 +315,8 @@ template <typename TF> __device__ __forceinline__ float entry_feature(const uint
 // table allocation ends with one spare entry, for the load at the last slot
 // of a collapsed edge.
 template <typename TF, int F, int NL>
-__device__ __forceinline__ void encode_levels_paired(const Geom &g, const TF *__restrict__ tab, int l0,
-                                                     const float p[3], int face, float out[NL][F])
+__device__ __forceinline__ void encode_levels_paired(const Geom &g, const TF *__restrict__ tab, const uint32_t *hot,
+                                                     int l0, const float p[3], int face, float out[NL][F])
 {
     static_assert(NL <= 8, "one swap bit per edge of at most 8 levels");
     constexpr uint32_t esz = F * sizeof(TF);
@@ -352,6 +359,8 @@ __device__ __forceinline__ void encode_levels_paired(const Geom &g, const TF *__
         const bool dense = (g.dense_mask >> l) & 1u;
         const uint32_t hm = g.hmask[l] << sh;
         const char *base = reinterpret_cast<const char *>(tab + ((size_t)l << g.log2_T) * F);
+        const bool in_lds = (g.hot_mask >> l) & 1u;
+        const char *hbase = reinterpret_cast<const char *>(hot) + g.hot_off[l];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint32_t y = ys[q & 1], z = zs[q >> 1];
@@ -368,8 +377,13 @@ __device__ __forceinline__ void encode_levels_paired(const Geom &g, const TF *__
             const bool swap = a > b;
             const uint32_t lo = swap ? b : a, hi = swap ? a : b;
             swapbits |= (swap ? 1u : 0u) << (4 * lv + q);
-            if (hi - lo <= esz) e[lv][q].load_both(base + lo);
-            else e[lv][q].load_apart(base + lo, base + hi);
+            if (in_lds) {
+                if (hi - lo <= esz) e[lv][q].load_both(hbase + lo);
+                else e[lv][q].load_apart(hbase + lo, hbase + hi);
+            } else {
+                if (hi - lo <= esz) e[lv][q].load_both(base + lo);
+                else e[lv][q].load_apart(base + lo, base + hi);
+            }
         }
         // form the bits now, so the slots die with their loads
         asm volatile("" : "+v"(swapbits));
@@ -404,13 +418,29 @@ __device__ __forceinline__ void encode_levels_paired(const Geom &g, const TF *__
 
 // Interpolated features of NL consecutive levels from l0 (zeros beyond L).
 template <typename TF, int F, int NL>
-__device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restrict__ tab, int l0,
+__device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restrict__ tab, const uint32_t *hot, int l0,
                                               const float p[3], int face, float out[NL][F])
 {
-    if constexpr (F * sizeof(TF) == 4 || F * sizeof(TF) == 8)
-        encode_levels_paired<TF, F, NL>(g, tab, l0, p, face, out);
+    if constexpr (paired_entries<TF, F>())
+        encode_levels_paired<TF, F, NL>(g, tab, hot, l0, p, face, out);
     else
         encode_levels_corners<TF, F, NL>(g, tab, l0, p, face, out);
+}
+
+// Copy the object's hot levels (the coarsest, all of whose used slots fit the
+// LDS budget) into LDS; every ray of the block reads them.  Visible after the
+// block's next barrier.
+template <typename TF, int F>
+__device__ __forceinline__ void stage_hot_levels(const Geom &g, const TF *__restrict__ tab, uint32_t *hot)
+{
+    if constexpr (paired_entries<TF, F>()) {
+        for (int l = 0; l < g.L; ++l) {
+            if (!((g.hot_mask >> l) & 1u)) continue;
+            const uint4 *src = reinterpret_cast<const uint4 *>(tab + ((size_t)l << g.log2_T) * F);
+            uint4 *dst = reinterpret_cast<uint4 *>(hot) + (g.hot_off[l] >> 4);
+            for (uint32_t i = threadIdx.x; i < (g.hot_len[l] >> 4); i += kBlock) dst[i] = src[i];
+        }
+    }
 }
 
 __device__ __forceinline__ float act_f(float x, int act, float slope)
@@ -563,7 +593,7 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g,
     }
     VRay w;
     w.valid = w.cand = false;
-    w.ta = w.tb = w.tmax = 0.0f;
+    w.ta = w.tb = w.tmax = w.tmin = 0.0f;
     w.mov = 0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) w.o[a] = w.d[a] = w.inv[a] = 0.0f;
@@ -651,6 +681,8 @@ __device__ __forceinline__ void query_f32_body(const QueryArgs &A, const Geom &g
 {
     constexpr int NL = 4;
     Lane ln;
+    uint32_t *hot = s_list + (A.g.H >> 1) * kBlock;   // after the voxel lists (sized for the launch)
+    stage_hot_levels<TF, F>(g, tab, hot);
     walk_and_sort<PAIRS>(A, g, S, s_list, ln);
     const uint32_t src = ln.src, r = ln.r;
     const bool live = ln.live;
@@ -673,7 +705,7 @@ __device__ __forceinline__ void query_f32_body(const QueryArgs &A, const Geom &g
             const int face = boundary_point(w, s_list[(h >> 1) * kBlock + src], h & 1, p);
             for (int l0 = 0; l0 < g.L; l0 += NL) {
                 float e[NL][F];
-                encode_levels<TF, F, NL>(g, tab, l0, p, face, e);
+                encode_levels<TF, F, NL>(g, tab, hot, l0, p, face, e);
 #pragma unroll
                 for (int lv = 0; lv < NL; ++lv) {
                     const int l = l0 + lv;
@@ -897,6 +929,8 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
     constexpr int LPB = 16 / FP;              // levels per K block
     constexpr int NL = (F * sizeof(TF) <= 4 && LPB >= 8) ? 8 : (LPB < 4 ? LPB : 4);   // levels per gather batch
     Lane ln;
+    uint32_t *hot = s_list + (A.g.H >> 1) * kBlock;   // after the voxel lists (sized for the launch)
+    stage_hot_levels<TF, F>(g, tab, hot);
     walk_and_sort<PAIRS>(A, g, S, s_list, ln);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t src = ln.src, r = ln.r;
@@ -944,7 +978,7 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
 #pragma unroll
                 for (int c0 = 0; c0 < LPB; c0 += NL) {
                     float v[NL][F];
-                    encode_levels<TF, F, NL>(g, tab, kb * LPB + c0, p, face, v);
+                    encode_levels<TF, F, NL>(g, tab, hot, kb * LPB + c0, p, face, v);
 #pragma unroll
                     for (int lv = 0; lv < NL; ++lv)
 #pragma unroll

@@ -4,7 +4,7 @@
 
 namespace lsnif {
 
-constexpr uint32_t kPairBins = 4096;   // per object: 8 octants x 8^3 cells
+constexpr uint32_t kPairBins = 32768;  // per object: 8 octants x 16^3 cells (coarser grids use a subset)
 
 struct PairPlan {
     const float4 *rays;

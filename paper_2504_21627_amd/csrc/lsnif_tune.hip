@@ -1,0 +1,205 @@
+// Per-object launch parameters and the autotuner that picks them by timing.
+//
+// Every candidate runs the real query on the caller's batch (one warm-up, then
+// three timed queries between HIP events on a private stream), so the choice
+// reflects the batch's own coherence, the object's table sizes and the LDS
+// left for hot levels.  None of the parameters changes a result.
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "lsnif_internal.hpp"
+
+using namespace lsnif;
+
+namespace {
+
+constexpr int kTimedReps = 3;
+
+lsnif_status check_tuning(const lsnif_tuning *t)
+{
+    if (!t) return fail(LSNIF_E_INVALID, "tuning is NULL");
+    if (t->sort_bits < 0 || t->sort_bits > 5) return fail(LSNIF_E_INVALID, "sort_bits must be 0..5");
+    if (t->pair_bits < 1 || t->pair_bits > 4) return fail(LSNIF_E_INVALID, "pair_bits must be 1..4");
+    if (t->hot_lds_bytes < 0 || t->hot_lds_bytes > (int32_t)kHotLdsBudget)
+        return fail(LSNIF_E_INVALID, "hot_lds_bytes must be 0..%u", kHotLdsBudget);
+    return LSNIF_OK;
+}
+
+void apply(lsnif_ctx *ctx, Object &ob, const lsnif_tuning &t)
+{
+    ob.geom.sort_bits = (uint32_t)t.sort_bits;
+    ob.geom.pair_bits = (uint32_t)t.pair_bits;
+    ob.hot_budget = (uint32_t)t.hot_lds_bytes;
+    plan_hot_levels(ob.geom, ob.esz, ob.hot_budget);
+    ctx->table_dirty = true;
+    ++ctx->generation;
+}
+
+lsnif_tuning current(const Object &ob)
+{
+    return lsnif_tuning{(int32_t)ob.geom.sort_bits, (int32_t)ob.geom.pair_bits, (int32_t)ob.hot_budget};
+}
+
+// Milliseconds per call of `enqueue(stream)`, averaged over kTimedReps after a warm-up.
+template <typename Enqueue> lsnif_status time_ms(Enqueue &&enqueue, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float &ms)
+{
+    lsnif_status st = enqueue(s);
+    if (st) return st;
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int i = 0; i < kTimedReps; ++i)
+        if ((st = enqueue(s))) return st;
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    ms /= kTimedReps;
+    return LSNIF_OK;
+}
+
+// Runs `fn(stream, e0, e1)` with a private stream and two events, releasing them after.
+template <typename Fn> lsnif_status with_stream(Fn &&fn)
+{
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        return fail(LSNIF_E_DEVICE, "hipStreamCreateWithFlags failed");
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipStreamDestroy(s);
+        return fail(LSNIF_E_DEVICE, "hipEventCreate failed");
+    }
+    const lsnif_status st = fn(s, e0, e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    return st;
+}
+
+const int32_t kHotCandidates[] = {0, 20 << 10, 40 << 10};
+
+}  // namespace
+
+extern "C" {
+
+lsnif_status lsnif_get_tuning(lsnif_ctx *ctx, uint32_t object_id, lsnif_tuning *tuning)
+{
+    if (!ctx || !tuning) return fail(LSNIF_E_INVALID, "ctx or tuning is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->objects.find(object_id);
+    if (it == ctx->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", object_id);
+    *tuning = current(it->second);
+    return LSNIF_OK;
+}
+
+lsnif_status lsnif_set_tuning(lsnif_ctx *ctx, uint32_t object_id, const lsnif_tuning *tuning)
+{
+    if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
+    lsnif_status st = check_tuning(tuning);
+    if (st) return st;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->objects.find(object_id);
+    if (it == ctx->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", object_id);
+    if (ctx->device >= 0) {
+        DeviceGuard guard(ctx->device);
+        HIP_TRY(hipDeviceSynchronize());   // queries in flight read the old parameters by value
+    }
+    apply(ctx, it->second, *tuning);
+    return LSNIF_OK;
+}
+
+lsnif_status lsnif_autotune(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
+                            lsnif_hit *d_out, lsnif_tuning *best)
+{
+    if (!ctx || !best) return fail(LSNIF_E_INVALID, "ctx or best is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->device < 0) return fail(LSNIF_E_DEVICE, "host-only context");
+    const Object *cob = nullptr;
+    lsnif_status st = check_query(ctx, object_id, d_rays, n, d_out, cob);
+    if (st) return st;
+    if (n == 0) return fail(LSNIF_E_INVALID, "nothing to time (n = 0)");
+    Object &ob = ctx->objects[object_id];
+    DeviceGuard guard(ctx->device);
+    if (n >= kSortMin && (st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n)))) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    const lsnif_tuning start = current(ob);
+    lsnif_tuning win = start;
+    float win_ms = -1.0f;
+    st = with_stream([&](hipStream_t s, hipEvent_t e0, hipEvent_t e1) -> lsnif_status {
+        for (int sb : {0, 3, 4, 5})
+            for (int32_t hot : kHotCandidates) {
+                const lsnif_tuning t{sb, start.pair_bits, hot};
+                apply(ctx, ob, t);
+                float ms = 0.0f;
+                lsnif_status e = time_ms(
+                    [&](hipStream_t q) { return enqueue_query(ctx, ob, d_rays, n, d_out, nullptr, q, ctx->ws); }, s,
+                    e0, e1, ms);
+                if (e) return e;
+                if (win_ms < 0.0f || ms < win_ms) {
+                    win_ms = ms;
+                    win = t;
+                }
+            }
+        return LSNIF_OK;
+    });
+    apply(ctx, ob, st ? start : win);
+    if (st) return st;
+    *best = win;
+    return LSNIF_OK;
+}
+
+lsnif_status lsnif_autotune_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t n_rays,
+                                  const uint32_t *d_pair_ray, const uint32_t *d_pair_inst, uint32_t n_pairs,
+                                  const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out,
+                                  lsnif_tuning *best)
+{
+    if (!ctx || !best) return fail(LSNIF_E_INVALID, "ctx or best is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->device < 0) return fail(LSNIF_E_DEVICE, "host-only context");
+    if (n_rays == 0 || n_pairs == 0) return fail(LSNIF_E_INVALID, "nothing to time");
+    if (ctx->objects.empty()) return fail(LSNIF_E_NOTFOUND, "no objects built");
+    DeviceGuard guard(ctx->device);
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<std::pair<uint32_t, lsnif_tuning>> start;
+    for (auto &kv : ctx->objects) start.push_back({kv.first, current(kv.second)});
+    auto apply_all = [&](const lsnif_tuning &t) {
+        for (auto &kv : ctx->objects)
+            apply(ctx, kv.second, lsnif_tuning{(int32_t)kv.second.geom.sort_bits, t.pair_bits, t.hot_lds_bytes});
+    };
+    lsnif_tuning win{};
+    float win_ms = -1.0f;
+    lsnif_status st = with_stream([&](hipStream_t s, hipEvent_t e0, hipEvent_t e1) -> lsnif_status {
+        for (int pb : {2, 3, 4})
+            for (int32_t hot : kHotCandidates) {
+                const lsnif_tuning t{0, pb, hot};
+                apply_all(t);
+                PairsSetup ps;
+                lsnif_status e = pairs_setup(ctx, ps);   // uploads the changed object table
+                if (e) return e;
+                if ((e = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs)))) return e;
+                float ms = 0.0f;
+                e = time_ms(
+                    [&](hipStream_t q) {
+                        return enqueue_pairs(ctx, ps, d_rays, n_rays, d_pair_ray, d_pair_inst, n_pairs, d_inst, n_inst,
+                                             d_out, q, ctx->pws);
+                    },
+                    s, e0, e1, ms);
+                if (e) return e;
+                if (win_ms < 0.0f || ms < win_ms) {
+                    win_ms = ms;
+                    win = t;
+                }
+            }
+        return LSNIF_OK;
+    });
+    if (st) {
+        for (auto &p : start) apply(ctx, ctx->objects[p.first], p.second);
+        return st;
+    }
+    apply_all(win);
+    *best = current(ctx->objects.begin()->second);
+    return LSNIF_OK;
+}
+
+}  // extern "C"

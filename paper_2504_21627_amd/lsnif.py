@@ -45,6 +45,13 @@ class lsnif_object_desc(C.Structure):
                 ("grazing_recheck", C.c_int32)]
 
 
+class lsnif_tuning(C.Structure):
+    _fields_ = [("sort_bits", C.c_int32), ("pair_bits", C.c_int32), ("hot_lds_bytes", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class lsnif_serve_cfg(C.Structure):
     _fields_ = [("max_inflight", C.c_uint32), ("hbm_budget", C.c_uint64), ("n_streams", C.c_uint32),
                 ("max_queue", C.c_uint32), ("dry_run_ns_per_ray", C.c_uint64)]
@@ -119,11 +126,19 @@ def load():
     lib.lsnif_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
     lib.lsnif_graph_destroy.argtypes = [C.c_void_p]
     lib.lsnif_graph_destroy.restype = None
+    lib.lsnif_get_tuning.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(lsnif_tuning)]
+    lib.lsnif_set_tuning.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(lsnif_tuning)]
+    lib.lsnif_autotune.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
+                                   C.POINTER(lsnif_tuning)]
+    lib.lsnif_autotune_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
+                                         C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
+                                         C.POINTER(lsnif_tuning)]
     for name in ("lsnif_create", "lsnif_desc_bytes", "lsnif_build", "lsnif_release",
                  "lsnif_object_bytes", "lsnif_query", "lsnif_query_debug", "lsnif_profile_enable",
                  "lsnif_profile_read", "lsnif_query_pairs", "lsnif_serve_start", "lsnif_serve_submit",
                  "lsnif_serve_poll", "lsnif_serve_wait", "lsnif_serve_cancel", "lsnif_serve_stats_get",
-                 "lsnif_serve_stop", "lsnif_graph_query", "lsnif_graph_pairs", "lsnif_graph_launch"):
+                 "lsnif_serve_stop", "lsnif_graph_query", "lsnif_graph_pairs", "lsnif_graph_launch",
+                 "lsnif_get_tuning", "lsnif_set_tuning", "lsnif_autotune", "lsnif_autotune_pairs"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -249,6 +264,35 @@ def lsnif_query_pairs(ctx, rays, pair_ray, pair_inst, inst, out, stream=None):
                                     C.c_void_p(pair_inst.data_ptr() if m else 0), m,
                                     C.c_void_p(inst.data_ptr() if k else 0), k,
                                     C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+
+
+def lsnif_get_tuning(ctx, object_id):
+    t = lsnif_tuning()
+    _check(load().lsnif_get_tuning(ctx, object_id, C.byref(t)))
+    return t.as_dict()
+
+
+def lsnif_set_tuning(ctx, object_id, sort_bits, pair_bits, hot_lds_bytes):
+    t = lsnif_tuning(sort_bits, pair_bits, hot_lds_bytes)
+    _check(load().lsnif_set_tuning(ctx, object_id, C.byref(t)))
+
+
+def lsnif_autotune(ctx, object_id, rays, out):
+    """Time the tuning candidates on this batch, keep the fastest for the object, return it."""
+    t = lsnif_tuning()
+    _check(load().lsnif_autotune(ctx, object_id, C.c_void_p(rays.data_ptr()), rays.shape[0],
+                                 C.c_void_p(out.data_ptr()), C.byref(t)))
+    return t.as_dict()
+
+
+def lsnif_autotune_pairs(ctx, rays, pair_ray, pair_inst, inst, out):
+    """Time the pair-query candidates on this batch, apply the fastest to every object, return it."""
+    n, m, k = rays.shape[0], pair_ray.shape[0], inst.shape[0]
+    t = lsnif_tuning()
+    _check(load().lsnif_autotune_pairs(ctx, C.c_void_p(rays.data_ptr()), n, C.c_void_p(pair_ray.data_ptr()),
+                                       C.c_void_p(pair_inst.data_ptr()), m, C.c_void_p(inst.data_ptr()), k,
+                                       C.c_void_p(out.data_ptr()), C.byref(t)))
+    return t.as_dict()
 
 
 def lsnif_graph_query(ctx, object_id, rays, out):

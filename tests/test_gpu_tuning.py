@@ -1,0 +1,90 @@
+"""Tuning parameters change speed, never results; the autotuner returns a valid choice."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_2504_21627_amd import lsnif
+    return lsnif
+
+
+def bits(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def test_single_object_tunings_agree(L):
+    import torch
+    obj = W.configs.c2_object()
+    rays_np = W.configs.subsample(W.configs.c2_rays(), 60000, seed=8)
+    ctx = L.lsnif_create(0)
+    try:
+        rays = torch.from_numpy(rays_np).cuda()
+        for feat, mlp in (("fp16", "fp16"), ("fp32", "fp32")):
+            oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
+            ref = None
+            for sb, hot in ((5, 40960), (0, 0), (3, 20480), (4, 0)):
+                L.lsnif_set_tuning(ctx, oid, sb, 4, hot)
+                assert L.lsnif_get_tuning(ctx, oid) == {"sort_bits": sb, "pair_bits": 4, "hot_lds_bytes": hot}
+                out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
+                L.lsnif_query(ctx, oid, rays, out)
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = bits(out)
+                else:
+                    assert np.array_equal(bits(out), ref), (feat, sb, hot)
+            out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
+            best = L.lsnif_autotune(ctx, oid, rays, out)
+            print(feat, "autotuned", best, flush=True)
+            assert best["sort_bits"] in (0, 3, 4, 5) and best["hot_lds_bytes"] in (0, 20480, 40960)
+            assert L.lsnif_get_tuning(ctx, oid) == best
+            L.lsnif_query(ctx, oid, rays, out)
+            torch.cuda.synchronize()
+            assert np.array_equal(bits(out), ref)
+            with pytest.raises(L.LsnifError):
+                L.lsnif_set_tuning(ctx, oid, 6, 4, 0)
+            L.lsnif_release(ctx, oid)
+    finally:
+        L.lsnif_destroy(ctx)
+
+
+def test_pair_tunings_agree(L):
+    import torch
+    d = W.configs.c4(n_objects=6, total=6 * 200000, scale=0.1)
+    objs, rays_np, owner = d["objects"], d["rays"], d["owner"]
+    ctx = L.lsnif_create(0)
+    try:
+        ids = [L.lsnif_build(ctx, L.ObjectDesc(o, "fp16", "fp16")) for o in objs]
+        eye = np.concatenate([np.eye(3), np.zeros((3, 1))], 1).astype(np.float32)
+        inst = torch.from_numpy(L.instances_array([(i, eye) for i in ids])).cuda()
+        rays = torch.from_numpy(rays_np).cuda()
+        pr = torch.arange(len(rays_np), dtype=torch.int32, device="cuda")
+        pi = torch.from_numpy(owner.astype(np.int32)).cuda()
+        ref = None
+        for pb, hot in ((4, 40960), (2, 0), (3, 20480)):
+            for i in ids:
+                L.lsnif_set_tuning(ctx, i, 5, pb, hot)
+            out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
+            L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = bits(out)
+                assert (ref[:, 0] == 1).sum() > 100
+            else:
+                assert np.array_equal(bits(out), ref), (pb, hot)
+        out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
+        best = L.lsnif_autotune_pairs(ctx, rays, pr, pi, inst, out)
+        print("pairs autotuned", best, flush=True)
+        assert best["pair_bits"] in (2, 3, 4)
+        L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out)
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(out), ref)
+    finally:
+        L.lsnif_destroy(ctx)
