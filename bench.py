@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_FP16_PEAK_TFLOPS = 2500.0
-KERNEL = "k_query_mma<_Float16, _Float16, 2, 64, 2>"
+KERNEL = "k_query_mma<_Float16, _Float16, F=2, WIDTH=64, KBM=2, PAIRS=false, HOT=false>"
 
 
 KERNEL_SOURCES = ("lsnif_device.hpp", "lsnif_kernels.hpp", "lsnif_launch.hpp", "k_mma_f16.hip",

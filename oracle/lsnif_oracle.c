@@ -31,7 +31,9 @@
  * 2022 (Eq. 4) with direct indexing when a level's (R+1)^3 vertices fit in
  * the table; level vertices 0..R spanning the voxel-grid box; a hit iff the
  * occlusion logit is > 0 and the hit distance is <= tmax; material = lowest
- * index among the maximal logits; normal = normalised linear head.
+ * index among the maximal logits; normal = normalised linear head; when an
+ * object asks for it, a grazing voxel (float32 overlap at most
+ * 2^-16 max(1, |entry|)) is listed by its float64 slab interval instead.
  */
 #include <math.h>
 #include <stddef.h>

@@ -9,8 +9,16 @@ static void go(const QueryArgs &A, bool pairs, uint32_t grid, hipStream_t s)
 {
     // voxel lists of H/2 entries per lane (for pairs, H is the largest over the objects)
     const size_t lds = (size_t)(A.g.H >> 1) * kBlock * sizeof(uint32_t) + A.hot_lds;
-    if (pairs) hipLaunchKernelGGL((k_query_mma<TF, _Float16, F, 64, KBM, true>), dim3(grid), dim3(kBlock), lds, s, A);
-    else hipLaunchKernelGGL((k_query_mma<TF, _Float16, F, 64, KBM, false>), dim3(grid), dim3(kBlock), lds, s, A);
+    // objects with hot levels take the variant that reads them from LDS
+    if constexpr (hot_entries<TF, F>()) {
+        if (A.hot_lds) {
+            if (pairs) hipLaunchKernelGGL((k_query_mma<TF, _Float16, F, 64, KBM, true, true>), dim3(grid), dim3(kBlock), lds, s, A);
+            else hipLaunchKernelGGL((k_query_mma<TF, _Float16, F, 64, KBM, false, true>), dim3(grid), dim3(kBlock), lds, s, A);
+            return;
+        }
+    }
+    if (pairs) hipLaunchKernelGGL((k_query_mma<TF, _Float16, F, 64, KBM, true, false>), dim3(grid), dim3(kBlock), lds, s, A);
+    else hipLaunchKernelGGL((k_query_mma<TF, _Float16, F, 64, KBM, false, false>), dim3(grid), dim3(kBlock), lds, s, A);
 }
 
 template <typename TF, int F>

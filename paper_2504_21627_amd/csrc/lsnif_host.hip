@@ -320,7 +320,8 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
         if (d->R[l] % d->V == 0) g.aligned_mask |= 1u << l;
     }
     ob.esz = (uint32_t)(d->F * dtype_size(d->feat_dtype));
-    plan_hot_levels(g, ob.esz, kHotLdsBudget);
+    ob.hot_budget = 0;   // hot levels are off until a tuning asks for them
+    plan_hot_levels(g, ob.esz, ob.hot_budget);
     // occupancy as 4x4x4 bricks: one 64-bit mask per brick, then one bit per brick
     const int V = d->V, NB = (V + 3) / 4;
     const size_t nbricks = (size_t)NB * NB * NB;

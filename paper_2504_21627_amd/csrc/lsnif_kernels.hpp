@@ -187,11 +187,13 @@ template <typename TF, int F> struct Entry {
 // crossing-axis weight is exactly 0 or 1; both of that axis' vertex terms are
 // set to the selected one, so the 4 zero-weight corners re-read the 4 face
 // corners instead of touching other table entries.
-template <typename TF, int F, int NL>
-__device__ __forceinline__ void encode_levels_corners(const Geom &g, const TF *__restrict__ tab, int l0,
-                                                      const float p[3], int face, float out[NL][F])
+template <typename TF, int F, int NL, bool HOT>
+__device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restrict__ tab, const uint32_t *hot, int l0,
+                                              const float p[3], int face, float out[NL][F])
 {
     const char *base[NL];
+    bool in_lds[NL];
+    uint32_t hoff[NL];
     uint32_t off[NL][8];
     float wx[NL][2], wy[NL][2], wz[NL][2];
     constexpr uint32_t esz = F * sizeof(TF);
@@ -221,13 +223,19 @@ __device__ __forceinline__ void encode_levels_corners(const Geom &g, const TF *_
         wx[lv][0] = 1.0f - wt[0]; wx[lv][1] = wt[0];
         wy[lv][0] = 1.0f - wt[1]; wy[lv][1] = wt[1];
         wz[lv][0] = 1.0f - wt[2]; wz[lv][1] = wt[2];
+        in_lds[lv] = HOT && ((g.hot_mask >> l) & 1u);
+        hoff[lv] = HOT ? g.hot_off[l] : 0u;
         base[lv] = reinterpret_cast<const char *>(tab + ((size_t)l << g.log2_T) * F);
     }
     Entry<TF, F> e[NL][8];
 #pragma unroll
     for (int lv = 0; lv < NL; ++lv)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) e[lv][c].load(base[lv], off[lv][c]);
+        for (int c = 0; c < 8; ++c) {
+            // a hot level is read from its LDS copy (the pointer stays in the LDS address space)
+            if (HOT && in_lds[lv]) e[lv][c].load(reinterpret_cast<const char *>(hot) + hoff[lv], off[lv][c]);
+            else e[lv][c].load(base[lv], off[lv][c]);
+        }
     // keep every gather of the batch in flight before the first is consumed
     asm volatile("" ::: "memory");
 #pragma unroll
@@ -251,180 +259,10 @@ __device__ __forceinline__ void encode_levels_corners(const Geom &g, const TF *_
     }
 }
 
-// Cell of point p on level l, as level_cell, with the clamps as min/max.
-__device__ __forceinline__ void level_cell_mm(const Geom &g, int l, const float p[3], uint32_t i[3], float wt[3])
-{
-    const float Rf = (float)g.R[l], sc = g.lsc[l];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        const float x = __builtin_fminf(__builtin_fmaxf(p[b] * sc, 0.0f), Rf);
-        const float k = __builtin_fminf(__builtin_floorf(x), Rf - 1.0f);
-        i[b] = (uint32_t)k;
-        wt[b] = x - k;
-    }
-}
-
-// Entries of 4 or 8 bytes take the paired gathers (and may be hot in LDS).
-template <typename TF, int F> constexpr bool paired_entries()
+// Tables with 4- or 8-byte entries may keep their coarsest levels in LDS.
+template <typename TF, int F> constexpr bool hot_entries()
 {
     return F * sizeof(TF) == 4 || F * sizeof(TF) == 8;
-}
-
-// Two table entries side by side, loaded with one instruction from a 4-byte
-// aligned address.
-template <int ESZ> struct EntryPair {
-    static constexpr int W = ESZ / 4;          // dwords per entry
-    uint32_t d[2 * W];
-    __device__ __forceinline__ void load_both(const char *p)
-    {
-        typedef uint32_t v_t __attribute__((ext_vector_type(2 * W)));
-        v_t v;
-        __builtin_memcpy(&v, p, sizeof(v));
-#pragma unroll
-        for (int k = 0; k < 2 * W; ++k) d[k] = v[k];
-    }
-    __device__ __forceinline__ void load_apart(const char *lo, const char *hi)
-    {
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            d[k] = reinterpret_cast<const uint32_t *>(lo)[k];
-            d[W + k] = reinterpret_cast<const uint32_t *>(hi)[k];
-        }
-    }
-    __device__ __forceinline__ void pin()
-    {
-#pragma unroll
-        for (int k = 0; k < 2 * W; ++k) asm volatile("" : "+v"(d[k]));
-    }
-};
-
-template <typename TF> __device__ __forceinline__ float entry_feature(const uint32_t *d, int f)
-{
-    if constexpr (sizeof(TF) == 4) return __uint_as_float(d[f]);
-    else return (f & 1) ? hi16<TF>(d[f >> 1]) : lo16<TF>(d[f >> 1]);
-}
-
-// encode_levels for entries of 4 or 8 bytes.  The two vertices x = i and
-// x = i + 1 of a cell edge along x share y and z, so their slots are s and
-// s + 1 on a directly indexed level and s and s ^ (i ^ (i + 1)) on a hashed
-// one: adjacent always in the first case and for about two edges in three in
-// the second.  One load of the lower slot then brings both entries (the other
-// lanes load the two slots separately), which halves the gather instructions
-// of an edge.  Which of the two x vertices sits in the lower slot is folded
-// into the x weights at once, so nothing else has to outlive the loads.  The
-// table allocation ends with one spare entry, for the load at the last slot
-// of a collapsed edge.
-template <typename TF, int F, int NL>
-__device__ __forceinline__ void encode_levels_paired(const Geom &g, const TF *__restrict__ tab, const uint32_t *hot,
-                                                     int l0, const float p[3], int face, float out[NL][F])
-{
-    static_assert(NL <= 8, "one swap bit per edge of at most 8 levels");
-    constexpr uint32_t esz = F * sizeof(TF);
-    constexpr uint32_t sh = esz == 4 ? 2 : 3;
-    constexpr int W = EntryPair<esz>::W;
-    EntryPair<esz> e[NL][4];
-    float wx[NL][2], wy[NL][2], wz[NL][2];
-    uint32_t swapbits = 0;    // bit 4 lv + q: vertex x = i + 1 of edge q holds the lower slot
-#pragma unroll
-    for (int lv = 0; lv < NL; ++lv) {
-        const int l = l0 + lv < g.L ? l0 + lv : g.L - 1;
-        uint32_t i[3];
-        float wt[3];
-        level_cell_mm(g, l, p, i, wt);
-        const uint32_t my = g.my[l], mz = g.mz[l];
-        uint32_t ys[2] = {i[1] * my, i[1] * my + my}, zs[2] = {i[2] * mz, i[2] * mz + mz};
-        uint32_t x0 = i[0], x1 = i[0] + 1u;
-        wx[lv][0] = 1.0f - wt[0];
-        wx[lv][1] = wt[0];
-        if ((g.aligned_mask >> l) & 1u) {
-            // the crossing-axis weight is exactly 0 or 1: both vertices on that
-            // axis become the selected one (an x edge collapses to one slot and
-            // all of its weight goes to the lower entry of the pair)
-            const float wf = face == 0 ? wt[0] : (face == 1 ? wt[1] : wt[2]);
-            const bool up = wf != 0.0f;
-            if (face == 0) {
-                x0 = x1 = up ? x1 : x0;
-                wx[lv][0] = 1.0f;
-                wx[lv][1] = 0.0f;
-            } else if (face == 1) {
-                ys[0] = ys[1] = up ? ys[1] : ys[0];
-            } else {
-                zs[0] = zs[1] = up ? zs[1] : zs[0];
-            }
-        }
-        wy[lv][0] = 1.0f - wt[1];
-        wy[lv][1] = wt[1];
-        wz[lv][0] = 1.0f - wt[2];
-        wz[lv][1] = wt[2];
-        const bool dense = (g.dense_mask >> l) & 1u;
-        const uint32_t hm = g.hmask[l] << sh;
-        const char *base = reinterpret_cast<const char *>(tab + ((size_t)l << g.log2_T) * F);
-        const bool in_lds = (g.hot_mask >> l) & 1u;
-        const char *hbase = reinterpret_cast<const char *>(hot) + g.hot_off[l];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t y = ys[q & 1], z = zs[q >> 1];
-            uint32_t a, b;
-            if (dense) {
-                const uint32_t s = (y + z) << sh;
-                a = (x0 << sh) + s;
-                b = (x1 << sh) + s;
-            } else {
-                const uint32_t s = (y ^ z) << sh;
-                a = ((x0 << sh) ^ s) & hm;
-                b = ((x1 << sh) ^ s) & hm;
-            }
-            const bool swap = a > b;
-            const uint32_t lo = swap ? b : a, hi = swap ? a : b;
-            swapbits |= (swap ? 1u : 0u) << (4 * lv + q);
-            if (in_lds) {
-                if (hi - lo <= esz) e[lv][q].load_both(hbase + lo);
-                else e[lv][q].load_apart(hbase + lo, hbase + hi);
-            } else {
-                if (hi - lo <= esz) e[lv][q].load_both(base + lo);
-                else e[lv][q].load_apart(base + lo, base + hi);
-            }
-        }
-        // form the bits now, so the slots die with their loads
-        asm volatile("" : "+v"(swapbits));
-    }
-    // keep every gather of the batch in flight before the first is consumed
-    asm volatile("" ::: "memory");
-#pragma unroll
-    for (int lv = 0; lv < NL; ++lv)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) e[lv][q].pin();
-#pragma unroll
-    for (int lv = 0; lv < NL; ++lv) {
-#pragma unroll
-        for (int f = 0; f < F; ++f) out[lv][f] = 0.0f;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const bool swap = (swapbits >> (4 * lv + q)) & 1u;
-            const float wyz = wy[lv][q & 1] * wz[lv][q >> 1];
-            const float wl = (swap ? wx[lv][1] : wx[lv][0]) * wyz, wh = (swap ? wx[lv][0] : wx[lv][1]) * wyz;
-#pragma unroll
-            for (int f = 0; f < F; ++f) {
-                out[lv][f] = __builtin_fmaf(wl, entry_feature<TF>(e[lv][q].d, f), out[lv][f]);
-                out[lv][f] = __builtin_fmaf(wh, entry_feature<TF>(e[lv][q].d + W, f), out[lv][f]);
-            }
-        }
-        if (l0 + lv >= g.L) {
-#pragma unroll
-            for (int f = 0; f < F; ++f) out[lv][f] = 0.0f;
-        }
-    }
-}
-
-// Interpolated features of NL consecutive levels from l0 (zeros beyond L).
-template <typename TF, int F, int NL>
-__device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restrict__ tab, const uint32_t *hot, int l0,
-                                              const float p[3], int face, float out[NL][F])
-{
-    if constexpr (paired_entries<TF, F>())
-        encode_levels_paired<TF, F, NL>(g, tab, hot, l0, p, face, out);
-    else
-        encode_levels_corners<TF, F, NL>(g, tab, l0, p, face, out);
 }
 
 // Copy the object's hot levels (the coarsest, all of whose used slots fit the
@@ -433,7 +271,7 @@ __device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restric
 template <typename TF, int F>
 __device__ __forceinline__ void stage_hot_levels(const Geom &g, const TF *__restrict__ tab, uint32_t *hot)
 {
-    if constexpr (paired_entries<TF, F>()) {
+    if constexpr (hot_entries<TF, F>()) {
         for (int l = 0; l < g.L; ++l) {
             if (!((g.hot_mask >> l) & 1u)) continue;
             const uint4 *src = reinterpret_cast<const uint4 *>(tab + ((size_t)l << g.log2_T) * F);
@@ -675,14 +513,14 @@ typedef const ObjDev cObjDev;
 // A float in the constant address space (read-only during a launch; scalar loads).
 typedef const __attribute__((address_space(4))) float cfloat;
 
-template <typename TF, int F, int WIDTH, bool PAIRS>
+template <typename TF, int F, int WIDTH, bool PAIRS, bool HOT>
 __device__ __forceinline__ void query_f32_body(const QueryArgs &A, const Geom &g, const Mlp &mm,
                                                const TF *__restrict__ tab, uint32_t *s_list, Shared &S)
 {
     constexpr int NL = 4;
     Lane ln;
     uint32_t *hot = s_list + (A.g.H >> 1) * kBlock;   // after the voxel lists (sized for the launch)
-    stage_hot_levels<TF, F>(g, tab, hot);
+    if constexpr (HOT) stage_hot_levels<TF, F>(g, tab, hot);
     walk_and_sort<PAIRS>(A, g, S, s_list, ln);
     const uint32_t src = ln.src, r = ln.r;
     const bool live = ln.live;
@@ -705,7 +543,7 @@ __device__ __forceinline__ void query_f32_body(const QueryArgs &A, const Geom &g
             const int face = boundary_point(w, s_list[(h >> 1) * kBlock + src], h & 1, p);
             for (int l0 = 0; l0 < g.L; l0 += NL) {
                 float e[NL][F];
-                encode_levels<TF, F, NL>(g, tab, hot, l0, p, face, e);
+                encode_levels<TF, F, NL, HOT>(g, tab, hot, l0, p, face, e);
 #pragma unroll
                 for (int lv = 0; lv < NL; ++lv) {
                     const int l = l0 + lv;
@@ -771,7 +609,7 @@ __device__ __forceinline__ void query_f32_body(const QueryArgs &A, const Geom &g
     decode_store<PAIRS>(A, mm, r, ln.pair, w, count, o);
 }
 
-template <typename TF, int F, int WIDTH, bool PAIRS>
+template <typename TF, int F, int WIDTH, bool PAIRS, bool HOT>
 __global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
 {
     extern __shared__ uint32_t s_list[];
@@ -780,9 +618,9 @@ __global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
         const int o = tile_object(A.pr);
         if (o < 0) return;
         const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
-        query_f32_body<TF, F, WIDTH, true>(A, O.g, O.m, (const TF *)O.tables, s_list, S);
+        query_f32_body<TF, F, WIDTH, true, HOT>(A, O.g, O.m, (const TF *)O.tables, s_list, S);
     } else {
-        query_f32_body<TF, F, WIDTH, false>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list, S);
+        query_f32_body<TF, F, WIDTH, false, HOT>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list, S);
     }
 }
 
@@ -918,7 +756,7 @@ __device__ __forceinline__ void swap32(uint32_t &x, uint32_t &y)
     y = r[1];
 }
 
-template <typename TF, typename TM, int F, int WIDTH, int KBM, bool PAIRS>
+template <typename TF, typename TM, int F, int WIDTH, int KBM, bool PAIRS, bool HOT>
 __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g, const Mlp &mm,
                                                const TF *__restrict__ tab, uint32_t *s_list, Shared &S)
 {
@@ -930,7 +768,7 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
     constexpr int NL = (F * sizeof(TF) <= 4 && LPB >= 8) ? 8 : (LPB < 4 ? LPB : 4);   // levels per gather batch
     Lane ln;
     uint32_t *hot = s_list + (A.g.H >> 1) * kBlock;   // after the voxel lists (sized for the launch)
-    stage_hot_levels<TF, F>(g, tab, hot);
+    if constexpr (HOT) stage_hot_levels<TF, F>(g, tab, hot);
     walk_and_sort<PAIRS>(A, g, S, s_list, ln);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t src = ln.src, r = ln.r;
@@ -978,7 +816,7 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
 #pragma unroll
                 for (int c0 = 0; c0 < LPB; c0 += NL) {
                     float v[NL][F];
-                    encode_levels<TF, F, NL>(g, tab, hot, kb * LPB + c0, p, face, v);
+                    encode_levels<TF, F, NL, HOT>(g, tab, hot, kb * LPB + c0, p, face, v);
 #pragma unroll
                     for (int lv = 0; lv < NL; ++lv)
 #pragma unroll
@@ -1103,7 +941,7 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
     decode_store<PAIRS>(A, mm, r, ln.pair, w, count, o);
 }
 
-template <typename TF, typename TM, int F, int WIDTH, int KBM, bool PAIRS>
+template <typename TF, typename TM, int F, int WIDTH, int KBM, bool PAIRS, bool HOT>
 __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
 {
     extern __shared__ uint32_t s_list[];
@@ -1112,9 +950,9 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
         const int o = tile_object(A.pr);
         if (o < 0) return;
         const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
-        query_mma_body<TF, TM, F, WIDTH, KBM, true>(A, O.g, O.m, (const TF *)O.tables, s_list, S);
+        query_mma_body<TF, TM, F, WIDTH, KBM, true, HOT>(A, O.g, O.m, (const TF *)O.tables, s_list, S);
     } else {
-        query_mma_body<TF, TM, F, WIDTH, KBM, false>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list,
+        query_mma_body<TF, TM, F, WIDTH, KBM, false, HOT>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list,
                                                     S);
     }
 }
