@@ -101,7 +101,9 @@ typedef struct {
  *  tables         float32 [L][2^log2_T][F].
  *  H              cap on boundary points per ray (even, 2..64); a ray uses
  *                 the entry and exit point of its first H/2 occupied voxels.
- *  n_hidden,width hidden layers and their width (width 64 or 128).
+ *  n_hidden,width hidden layers and their width; the query kernels are built
+ *                 for width 64 (lsnif_build returns LSNIF_E_INVALID for other widths;
+ *                 lsnif_desc_bytes accounts any width).
  *  act, leaky_slope  hidden activation.
  *  n_mat, has_albedo output heads: [occlusion, t, normal x3, (albedo x3),
  *                 material x n_mat], so 5 + 3*has_albedo + n_mat outputs.
@@ -219,7 +221,7 @@ lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
  *  sort_bits      single-object queries of at least 8192 rays are first sorted
  *                 by direction octant and by the cell of the voxel grid where
  *                 the ray's segment starts, 2^sort_bits cells per axis
- *                 (0 = no sort, 1..5); rays that meet the grid close together
+ *                 (0 = no sort, 1..6); rays that meet the grid close together
  *                 then share 256-ray tiles (the work decomposition of Sec. 4:
  *                 dispatch sorted rays rather than scattered ones).
  *  pair_bits      the same grouping, 2^pair_bits cells per axis (1..4), for the
@@ -227,7 +229,7 @@ lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
  *  hot_lds_bytes  LDS per workgroup for the object's coarsest levels (0..40960):
  *                 those levels, all of whose used entries fit, are copied into
  *                 LDS by every workgroup and gathered from there.
- * lsnif_autotune times each candidate (sort_bits 0, 3, 4, 5 x hot_lds_bytes 0,
+ * lsnif_autotune times each candidate (sort_bits 0, 4, 5, 6 x hot_lds_bytes 0,
  * 20480, 40960) on the caller's batch, a warm-up and three timed queries each
  * on a private stream, keeps the fastest for the object and returns it.
  * lsnif_autotune_pairs does the same for a pair query (pair_bits 2, 3, 4 x

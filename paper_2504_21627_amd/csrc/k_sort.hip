@@ -1,6 +1,6 @@
 // Coherence order of a ray batch: a one-pass counting sort of the rays by a
 // coarse key -- direction octant, then the Morton code of the cell (2^b per
-// axis, b <= 5 chosen per object) of the voxel grid where the ray's segment
+// axis, b <= 6 chosen per object) of the voxel grid where the ray's segment
 // [ta, tb] starts.  Rays that meet the
 // grid close together and head the same way then share waves, so their
 // walks and their hash-grid gathers touch the same cache lines.  Order within
@@ -11,20 +11,22 @@
 
 namespace lsnif {
 
-__device__ __forceinline__ uint32_t spread5(uint32_t x)
+// Bits 0..5 of x spread to bits 0, 3, 6, ..., 15 (one axis of a 3-D Morton code).
+__device__ __forceinline__ uint32_t spread6(uint32_t x)
 {
-    x &= 31u;
+    x &= 63u;
     x = (x | (x << 8)) & 0x0000f00fu;
     x = (x | (x << 4)) & 0x000c30c3u;
     x = (x | (x << 2)) & 0x00249249u;
     return x;
 }
 
+
 __device__ __forceinline__ uint32_t coherence_key(const Geom &g, float4 r0, float4 r1)
 {
     VRay w;
     setup_ray(g, r0, r1, w);
-    if (!w.cand) return kSortBins - 1;
+    if (!w.cand) return sort_bins(g.sort_bits) - 1;
     uint32_t cell[3];
     const float cells = (float)(1u << g.sort_bits);
     const float sc = cells / (float)g.V;
@@ -35,7 +37,7 @@ __device__ __forceinline__ uint32_t coherence_key(const Geom &g, float4 r0, floa
         cell[a] = (uint32_t)x;
     }
     const uint32_t oct = (w.d[0] < 0.0f ? 1u : 0u) | (w.d[1] < 0.0f ? 2u : 0u) | (w.d[2] < 0.0f ? 4u : 0u);
-    return (oct << 15) | spread5(cell[0]) | (spread5(cell[1]) << 1) | (spread5(cell[2]) << 2);
+    return (oct << (3u * g.sort_bits)) | spread6(cell[0]) | (spread6(cell[1]) << 1) | (spread6(cell[2]) << 2);
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(uint32_t *p, uint32_t n, uint32_t v)
@@ -61,7 +63,6 @@ __global__ __launch_bounds__(kBlock) void k_sort_keys(Geom g, const float4 *rays
 // counters [1024 b, 1024 b + 1024), then rescans them with the sum of the
 // blocks before it as the carry-in.
 constexpr uint32_t kScanChunk = 1024;
-constexpr uint32_t kScanBlocks = (kSortBins + kScanChunk - 1) / kScanChunk;
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp, uint32_t &total)
 {
@@ -81,7 +82,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *t
     return incl - v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_partial(const uint32_t *hist, uint32_t *part)
+__global__ __launch_bounds__(kBlock) void k_scan_partial(const uint32_t *hist, uint32_t nbins, uint32_t *part)
 {
     __shared__ uint32_t tmp[kBlock];
     const uint32_t b0 = blockIdx.x * kScanChunk;
@@ -89,14 +90,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_partial(const uint32_t *hist, u
 #pragma unroll
     for (uint32_t q = 0; q < kScanChunk / kBlock; ++q) {
         const uint32_t i = b0 + q * kBlock + threadIdx.x;
-        if (i < kSortBins) v += hist[i];
+        if (i < nbins) v += hist[i];
     }
     uint32_t total;
     (void)block_exclusive_scan(v, tmp, total);
     if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t *hist, const uint32_t *part)
+__global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t *hist, uint32_t nbins, const uint32_t *part)
 {
     __shared__ uint32_t tmp[kBlock];
     const uint32_t t = threadIdx.x;
@@ -110,14 +111,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t *hist, const uin
     uint32_t v[4], sum = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        v[q] = i0 + q < kSortBins ? hist[i0 + q] : 0u;
+        v[q] = i0 + q < nbins ? hist[i0 + q] : 0u;
         sum += v[q];
     }
     uint32_t total;
     uint32_t run = carry + block_exclusive_scan(sum, tmp, total);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (i0 + q < kSortBins) hist[i0 + q] = run;
+        if (i0 + q < nbins) hist[i0 + q] = run;
         run += v[q];
     }
 }
@@ -135,12 +136,14 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint32_t *keys, u
 hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *keys, uint32_t *hist,
                                  uint32_t *order, hipStream_t s)
 {
-    const dim3 gb((kSortBins + kBlock - 1) / kBlock), gr((n + kBlock - 1) / kBlock);
-    uint32_t *part = hist + kSortBins;
-    hipLaunchKernelGGL(k_fill, gb, dim3(kBlock), 0, s, hist, (uint32_t)kSortBins, 0u);
+    // the workspace holds this resolution's bins, then one partial sum per 1024 bins
+    const uint32_t nbins = sort_bins(g.sort_bits), nblocks = sort_scan_blocks(g.sort_bits);
+    const dim3 gb((nbins + kBlock - 1) / kBlock), gr((n + kBlock - 1) / kBlock);
+    uint32_t *part = hist + nbins;
+    hipLaunchKernelGGL(k_fill, gb, dim3(kBlock), 0, s, hist, nbins, 0u);
     hipLaunchKernelGGL(k_sort_keys, gr, dim3(kBlock), 0, s, g, rays, n, keys, hist);
-    hipLaunchKernelGGL(k_scan_partial, dim3(kScanBlocks), dim3(kBlock), 0, s, hist, part);
-    hipLaunchKernelGGL(k_scan_final, dim3(kScanBlocks), dim3(kBlock), 0, s, hist, part);
+    hipLaunchKernelGGL(k_scan_partial, dim3(nblocks), dim3(kBlock), 0, s, hist, nbins, part);
+    hipLaunchKernelGGL(k_scan_final, dim3(nblocks), dim3(kBlock), 0, s, hist, nbins, part);
     hipLaunchKernelGGL(k_sort_scatter, gr, dim3(kBlock), 0, s, keys, n, hist, order);
     return hipGetLastError();
 }

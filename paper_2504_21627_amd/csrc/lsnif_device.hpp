@@ -43,7 +43,7 @@ struct Geom {
     uint32_t dense_mask;      // bit l: level l indexed directly ((R+1)^3 <= T)
     uint32_t aligned_mask;    // bit l: R % V == 0, the crossing-axis weight is 0 or 1
     uint32_t recheck;         // 1: grazing voxels of the walk are re-decided in float64
-    uint32_t sort_bits;       // coherence sort of single-object batches: 2^bits cells per axis (0 = no sort, <= 5)
+    uint32_t sort_bits;       // coherence sort of single-object batches: 2^bits cells per axis (0 = no sort, <= 6)
     uint32_t pair_bits;       // grouping of pairs within an object: 2^bits cells per axis (<= 4)
     uint32_t hot_mask;        // bit l: level l is copied into LDS for the launch (hot level)
     uint32_t hot_bytes;       // LDS bytes of the hot levels
@@ -196,12 +196,6 @@ __device__ __forceinline__ int start_cell(const Geom &g, const VRay &w, int a)
     return k;
 }
 
-// The voxel walk.  Emits, in order along the ray, the packed coordinates of
-// the first `cap` occupied voxels whose [entry, exit] overlaps [ta, tb] with
-// positive length; list[j * stride] receives voxel j.  Steps the axis of the
-// earliest exit, the lowest axis on ties.  Occupancy is read a brick at a
-// time: the coarse bit (from `coarse`, LDS or global) and, for a non-empty
-// brick, its 64-bit mask, loaded once on entering the brick.
 // Optional float64 re-decision of a voxel the float32 walk finds grazing: its
 // overlap with [ta, tb] is no longer than 2^-16 max(1, |entry|), or all of
 // [ta, tb] is that short.  The slab intervals of the voxel and of the grid are
@@ -234,6 +228,14 @@ __device__ __forceinline__ bool keep_f64(const VRay &w, const int c[3], int V)
     return __builtin_fmin(tout, tb) > __builtin_fmax(tin, ta);
 }
 
+// The voxel walk.  Emits, in order along the ray, the packed coordinates of
+// the first `cap` occupied voxels whose [entry, exit] overlaps [ta, tb] with
+// positive length; list[j * stride] receives voxel j.  Steps the axis of the
+// earliest exit, the lowest axis on ties.  Occupancy is read a brick at a
+// time: the coarse bit (from `coarse`, LDS or global) and, for a non-empty
+// brick, its 64-bit mask, loaded once on entering the brick.  An empty brick
+// is crossed in one step that lands on the cell the cell-by-cell walk reaches
+// next; every decision still compares values of the same plane functions.
 __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, const uint32_t *coarse,
                                            uint32_t *list, int stride, int cap)
 {
@@ -255,6 +257,53 @@ __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, const u
     uint32_t cur = 0xffffffffu;
     uint64_t mask = 0;
     for (int it = 0; it < 3 * V; ++it) {
+        const uint32_t b = brick_of(g, c);
+        if (b != cur) {
+            cur = b;
+            mask = ((coarse[b >> 5] >> (b & 31u)) & 1u) ? g.fine[b] : 0ull;
+        }
+        if (mask == 0ull) {
+            // An empty brick lists nothing: go straight to the cell where the cell-by-cell
+            // walk would leave it.  That walk merges the axes' plane crossings in order of
+            // t, ties to the lowest axis, so it leaves along the axis whose brick-boundary
+            // plane comes first in that order, after every other axis has crossed exactly
+            // its in-brick planes that come before it.
+            float T = __builtin_inff();
+            int as = -1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (w.mov & (1u << a)) {
+                    const int lo = c[a] & ~3, hi = lo + 4 < V ? lo + 4 : V;
+                    const float ta = plane_t((float)(w.d[a] > 0.0f ? hi : lo), w.o[a], w.inv[a]);
+                    if (as < 0 || ta < T) { T = ta; as = a; }
+                }
+            }
+            if (T >= w.tb) break;   // the segment ends inside the brick
+            bool out = false;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (!(w.mov & (1u << a))) continue;
+                const bool up = w.d[a] > 0.0f;
+                if (a == as) {
+                    const int lo = c[a] & ~3;
+                    c[a] = up ? lo + 4 : lo - 1;
+                    out = c[a] < 0 || c[a] >= V;
+                } else {
+                    for (int s = 0; s < 3; ++s) {
+                        const int nk = up ? c[a] + 1 : c[a] - 1;
+                        if ((nk & ~3) != (c[a] & ~3)) break;
+                        const float t = plane_t((float)(up ? c[a] + 1 : c[a]), w.o[a], w.inv[a]);
+                        if (t < T || (t == T && a < as)) c[a] = nk;
+                        else break;
+                    }
+                }
+            }
+            if (out) break;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (w.mov & (1u << a)) cell_span(w, a, c[a], en[a], ex[a]);
+            continue;
+        }
         float tin = -__builtin_inff(), tout = __builtin_inff();
         int ia = -1, oa = -1;
 #pragma unroll
@@ -267,11 +316,6 @@ __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, const u
         bool keep = fmin2(tout, w.tb) > fmax2(tin, w.ta);
         if (g.recheck && grazing(tin, tout, w.ta, w.tb)) keep = keep_f64(w, c, V);
         if (keep) {
-            const uint32_t b = brick_of(g, c);
-            if (b != cur) {
-                cur = b;
-                mask = ((coarse[b >> 5] >> (b & 31u)) & 1u) ? g.fine[b] : 0ull;
-            }
             if ((mask >> bit_in_brick(c)) & 1ull) {
                 list[n * stride] = pack_ijk(c);
                 if (++n == cap) break;

@@ -79,7 +79,7 @@ lsnif_status lsnif_graph_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_r
     if (n == 0) return fail(LSNIF_E_INVALID, "nothing to capture (n = 0)");
     DeviceGuard guard(ctx->device);
     return capture(
-        ctx, query_ws_bytes(n),
+        ctx, query_ws_bytes(n, ob->geom.sort_bits),
         [&](hipStream_t s, void *ws) { return enqueue_query(ctx, *ob, d_rays, n, d_out, nullptr, s, ws); }, out);
 }
 

@@ -482,7 +482,7 @@ static lsnif_status run_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ra
     lsnif_status st = check_query(ctx, object_id, d_rays, n, d_out, ob);
     if (st || n == 0) return st;
     DeviceGuard guard(ctx->device);
-    if (n >= kSortMin && (st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n)))) return st;
+    if ((st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n, ob->geom.sort_bits)))) return st;
     return enqueue_query(ctx, *ob, d_rays, n, d_out, dbg, static_cast<hipStream_t>(stream), ctx->ws);
 }
 
@@ -586,9 +586,10 @@ static hipEvent_t take_event(lsnif_ctx *ctx)
     return e;
 }
 
-size_t query_ws_bytes(uint32_t n)
+size_t query_ws_bytes(uint32_t n, uint32_t sort_bits)
 {
-    return n >= kSortMin ? ((size_t)2 * n + kSortBins + kSortScanBlocks) * sizeof(uint32_t) : 0;
+    if (n < kSortMin || sort_bits == 0) return 0;
+    return ((size_t)2 * n + sort_bins(sort_bits) + sort_scan_blocks(sort_bits)) * sizeof(uint32_t);
 }
 
 static size_t al256(size_t x) { return (x + 255) / 256 * 256; }

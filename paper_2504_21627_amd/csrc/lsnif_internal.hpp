@@ -63,7 +63,7 @@ void destroy_server(lsnif_ctx *ctx);   // stops a running serving loop
 constexpr uint32_t kSortMin = 8192;
 
 // Workspace bytes of one query of n rays, and of one pair query.
-size_t query_ws_bytes(uint32_t n);
+size_t query_ws_bytes(uint32_t n, uint32_t sort_bits);
 size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs);
 
 }  // namespace lsnif

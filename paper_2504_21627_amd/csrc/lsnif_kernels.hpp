@@ -180,6 +180,20 @@ template <typename TF, int F> struct Entry {
     }
 };
 
+// Cell of point p on level l and the weights inside it, as level_cell, with the
+// clamps as min/max (the debug path keeps level_cell itself).
+__device__ __forceinline__ void level_cell_mm(const Geom &g, int l, const float p[3], uint32_t i[3], float wt[3])
+{
+    const float Rf = (float)g.R[l], sc = g.lsc[l];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const float x = __builtin_fminf(__builtin_fmaxf(p[b] * sc, 0.0f), Rf);
+        const float k = __builtin_fminf(__builtin_floorf(x), Rf - 1.0f);
+        i[b] = (uint32_t)k;
+        wt[b] = x - k;
+    }
+}
+
 // Interpolated features of NL consecutive levels l0 .. l0 + NL - 1 at the
 // boundary point p (voxel units) whose crossing axis is `face`; levels at or
 // beyond L give zeros.  All slots are formed first and all gathers issued
@@ -202,23 +216,60 @@ __device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restric
         const int l = l0 + lv < g.L ? l0 + lv : g.L - 1;
         uint32_t i[3];
         float wt[3];
-        level_cell(g, l, p, i, wt);
-        const uint32_t my = g.my[l], mz = g.mz[l];
-        uint32_t t[3][2] = {{i[0], i[0] + 1u}, {i[1] * my, i[1] * my + my}, {i[2] * mz, i[2] * mz + mz}};
-        const bool al = (g.aligned_mask >> l) & 1u;
-        const float wf = face == 0 ? wt[0] : (face == 1 ? wt[1] : wt[2]);
+        if constexpr (HOT) {
+            // the LDS variant keeps the branch-free form: with the wave-uniform branches
+            // below, the compiler merges the LDS and HBM gathers into flat loads
+            level_cell(g, l, p, i, wt);
+            const uint32_t my = g.my[l], mz = g.mz[l];
+            uint32_t t[3][2] = {{i[0], i[0] + 1u}, {i[1] * my, i[1] * my + my}, {i[2] * mz, i[2] * mz + mz}};
+            const bool al = (g.aligned_mask >> l) & 1u;
+            const float wf = face == 0 ? wt[0] : (face == 1 ? wt[1] : wt[2]);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const bool col = al && a == face;
-            const uint32_t sel = wf != 0.0f ? t[a][1] : t[a][0];
-            t[a][0] = col ? sel : t[a][0];
-            t[a][1] = col ? sel : t[a][1];
-        }
-        const uint32_t dm = g.dmask[l], hm = g.hmask[l];
+            for (int a = 0; a < 3; ++a) {
+                const bool col = al && a == face;
+                const uint32_t sel = wf != 0.0f ? t[a][1] : t[a][0];
+                t[a][0] = col ? sel : t[a][0];
+                t[a][1] = col ? sel : t[a][1];
+            }
+            const uint32_t dm = g.dmask[l], hm = g.hmask[l];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const uint32_t x = t[0][c & 1], y = t[1][(c >> 1) & 1], z = t[2][c >> 2];
-            off[lv][c] = (((x + y + z) & dm) | ((x ^ y ^ z) & hm)) * esz;
+            for (int c = 0; c < 8; ++c) {
+                const uint32_t x = t[0][c & 1], y = t[1][(c >> 1) & 1], z = t[2][c >> 2];
+                off[lv][c] = (((x + y + z) & dm) | ((x ^ y ^ z) & hm)) * esz;
+            }
+        } else {
+            level_cell_mm(g, l, p, i, wt);
+            const uint32_t my = g.my[l], mz = g.mz[l];
+            uint32_t t[3][2] = {{i[0], i[0] + 1u}, {i[1] * my, i[1] * my + my}, {i[2] * mz, i[2] * mz + mz}};
+            if ((g.aligned_mask >> l) & 1u) {
+                // one value for the whole wave: only aligned levels pay for the collapse
+                const float wf = face == 0 ? wt[0] : (face == 1 ? wt[1] : wt[2]);
+                const bool up = wf != 0.0f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const uint32_t sel = up ? t[a][1] : t[a][0];
+                    t[a][0] = a == face ? sel : t[a][0];
+                    t[a][1] = a == face ? sel : t[a][1];
+                }
+            }
+            // vertex slot: x + y + z on a directly indexed level, (x ^ y ^ z) & (T - 1) on a
+            // hashed one (y, z already times their multipliers); the level kind is wave-uniform
+            if ((g.dense_mask >> l) & 1u) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t yz = t[1][q & 1] + t[2][q >> 1];
+                    off[lv][2 * q] = (t[0][0] + yz) * esz;
+                    off[lv][2 * q + 1] = (t[0][1] + yz) * esz;
+                }
+            } else {
+                const uint32_t hm = g.hmask[l];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t yz = t[1][q & 1] ^ t[2][q >> 1];
+                    off[lv][2 * q] = ((t[0][0] ^ yz) & hm) * esz;
+                    off[lv][2 * q + 1] = ((t[0][1] ^ yz) & hm) * esz;
+                }
+            }
         }
         wx[lv][0] = 1.0f - wt[0]; wx[lv][1] = wt[0];
         wy[lv][0] = 1.0f - wt[1]; wy[lv][1] = wt[1];
@@ -247,10 +298,14 @@ __device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restric
 #pragma unroll
         for (int f = 0; f < F; ++f) out[lv][f] = 0.0f;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const float w = (wx[lv][c & 1] * wy[lv][(c >> 1) & 1]) * wz[lv][c >> 2];
+        for (int q = 0; q < 4; ++q) {
+            const float wyz = wy[lv][q & 1] * wz[lv][q >> 1];
 #pragma unroll
-            for (int f = 0; f < F; ++f) out[lv][f] = __builtin_fmaf(w, e[lv][c].get(f), out[lv][f]);
+            for (int xb = 0; xb < 2; ++xb) {
+                const float w = wx[lv][xb] * wyz;
+#pragma unroll
+                for (int f = 0; f < F; ++f) out[lv][f] = __builtin_fmaf(w, e[lv][2 * q + xb].get(f), out[lv][f]);
+            }
         }
         if (l0 + lv >= g.L) {
 #pragma unroll
@@ -837,12 +892,13 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
                 phi[kb][q] = hi[q];
             }
             if (A.dbg.enc && live && has) {
-                const int LFp = g.L * FP;
+                // K slot k holds feature k % FP of level k / FP; the buffer is [H][L][F]
+                const int LF = g.L * F;
                 for (int q = 0; q < 16; ++q) {
-                    const int k = kb * 16 + q;
-                    if (k < LFp) {
+                    const int k = kb * 16 + q, l = k / FP, f = k % FP;
+                    if (l < g.L && f < F) {
                         const float v = q < 8 ? unpack8<TM>(lo, q) : unpack8<TM>(hi, q - 8);
-                        A.dbg.enc[(size_t)r * g.H * LFp + h * LFp + k] = MmaT<TM>::scaled ? v / mm.qs[0] : v;
+                        A.dbg.enc[(size_t)r * g.H * LF + h * LF + l * F + f] = MmaT<TM>::scaled ? v / mm.qs[0] : v;
                     }
                 }
             }

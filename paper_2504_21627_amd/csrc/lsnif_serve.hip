@@ -268,11 +268,14 @@ private:
             need = pairs_ws_bytes(r.n_rays, r.n_pairs, ps.n_objs);
             return LSNIF_OK;
         }
+        uint32_t bits = 5;   // dry runs: the default resolution
         if (!dry_) {
             std::lock_guard<std::recursive_mutex> g(ctx_->mu);
-            if (!ctx_->objects.count(r.object_id)) return fail(LSNIF_E_NOTFOUND, "no object %u", r.object_id);
+            auto it = ctx_->objects.find(r.object_id);
+            if (it == ctx_->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", r.object_id);
+            bits = it->second.geom.sort_bits;
         }
-        need = query_ws_bytes(r.n_rays);
+        need = query_ws_bytes(r.n_rays, bits);
         return LSNIF_OK;
     }
 

@@ -20,7 +20,7 @@ constexpr int kTimedReps = 3;
 lsnif_status check_tuning(const lsnif_tuning *t)
 {
     if (!t) return fail(LSNIF_E_INVALID, "tuning is NULL");
-    if (t->sort_bits < 0 || t->sort_bits > 5) return fail(LSNIF_E_INVALID, "sort_bits must be 0..5");
+    if (t->sort_bits < 0 || t->sort_bits > 6) return fail(LSNIF_E_INVALID, "sort_bits must be 0..6");
     if (t->pair_bits < 1 || t->pair_bits > 4) return fail(LSNIF_E_INVALID, "pair_bits must be 1..4");
     if (t->hot_lds_bytes < 0 || t->hot_lds_bytes > (int32_t)kHotLdsBudget)
         return fail(LSNIF_E_INVALID, "hot_lds_bytes must be 0..%u", kHotLdsBudget);
@@ -121,13 +121,13 @@ lsnif_status lsnif_autotune(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray 
     if (n == 0) return fail(LSNIF_E_INVALID, "nothing to time (n = 0)");
     Object &ob = ctx->objects[object_id];
     DeviceGuard guard(ctx->device);
-    if (n >= kSortMin && (st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n)))) return st;
+    if ((st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n, 6)))) return st;   // the finest candidate
     HIP_TRY(hipDeviceSynchronize());
     const lsnif_tuning start = current(ob);
     lsnif_tuning win = start;
     float win_ms = -1.0f;
     st = with_stream([&](hipStream_t s, hipEvent_t e0, hipEvent_t e1) -> lsnif_status {
-        for (int sb : {0, 3, 4, 5})
+        for (int sb : {0, 4, 5, 6})
             for (int32_t hot : kHotCandidates) {
                 const lsnif_tuning t{sb, start.pair_bits, hot};
                 apply(ctx, ob, t);

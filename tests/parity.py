@@ -34,8 +34,7 @@ def gpu_query(L, ctx, oid, rays_np, debug=False, obj=None, stream=None):
                 "points": torch.empty((n, H, 3), dtype=torch.float32, device="cuda"),
                 "slots": torch.empty((n, H, Lv, 8), dtype=torch.int32, device="cuda"),
                 "weights": torch.empty((n, H, Lv, 3), dtype=torch.float32, device="cuda"),
-                "enc": torch.zeros((n, H * Lv * (4 if F == 3 else F)), dtype=torch.float32,
-                                   device="cuda"),
+                "enc": torch.zeros((n, H * Lv * F), dtype=torch.float32, device="cuda"),
                 "out": torch.empty((n, od), dtype=torch.float32, device="cuda")}
         L.lsnif_query_debug(ctx, oid, rays, out, bufs, stream)
         torch.cuda.synchronize()

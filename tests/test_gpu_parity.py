@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.parity import gpu_query, compare_hits
+from tests.parity import gpu_query, compare_hits, output_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -67,10 +67,7 @@ def check_intermediates(g, o, obj):
 
 
 def enc_compare(g_enc, o_enc, obj, count, rel):
-    F = obj.F
-    FP = 4 if F == 3 else F
-    n, H, Lv = len(count), obj.H, obj.L
-    ge = g_enc.reshape(n, H, Lv, FP)[..., :F].reshape(n, H * Lv * F)
+    ge = g_enc   # [n][H * L * F], as the oracle's
     scale = np.abs(o_enc).max()
     err = np.abs(ge - o_enc).max() / scale
     assert err <= rel, err
@@ -293,3 +290,87 @@ def test_grazing_recheck_parity(L, ctx, mlp):
             L.lsnif_release(ctx, oid)
     changed = np.any(counts[0] != counts[1], axis=(1, 2)).sum()
     assert changed >= 20, changed
+
+
+@pytest.mark.parametrize("feat,mlp", [("fp32", "fp32"), ("fp16", "fp16")])
+def test_paper_shaped_object_parity(L, ctx, c1, feat, mlp):
+    """An object shaped like the paper's default (Sec. 5.1), at width 64: V = 32 surface
+    voxels, two face-aligned hashed levels (R = 64, 128; 2^17 entries) of 3 features, a
+    2-hidden-layer leaky-ReLU MLP and the albedo head (8 + 4 outputs).  Exercises the F = 3
+    gathers, the 4-corner collapse on both levels, leaky ReLU and the albedo outputs."""
+    from tests.test_oracle_pins import tiny_object
+    base = c1["objects"][0]
+    occ = np.unpackbits(base.occ.view(np.uint8), bitorder="little").astype(bool)[: base.V ** 3]
+    obj = tiny_object(base.V, occ, L=2, F=3, log2_T=17, R=[64, 128], H=18, width=64, n_hidden=2,
+                      n_mat=4, has_albedo=1, act=1, bmin=tuple(base.bmin), bmax=tuple(base.bmax), seed=21)
+    obj.tables *= np.float32(1e-2)
+    assert obj.out_dim == 12
+    rays = c1["rays"]
+    _say(f"paper-shaped object {feat}/{mlp}: {len(rays)} rays")
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
+    try:
+        g = gpu_query(L, ctx, oid, rays, debug=True, obj=obj)
+        o = oracle.query(obj, rays, debug=True)
+        check_intermediates(g, o, obj)
+        u = max(U[feat], U[mlp])
+        enc_compare(g["enc"], o["enc"], obj, o["count"], 1e-6 if mlp == "fp32" else 4 * u)
+        cand = o["count"] > 0
+        ob = output_bound(obj, o["enc"], u)
+        # every raw output (albedo logits included) within its forward-error bound (x4 slack)
+        err = np.abs(g["out"][cand].astype(np.float64) - o["out"][cand])
+        assert np.all(err <= 4 * ob[cand] + 1e-30), float((err / np.maximum(ob[cand], 1e-30)).max())
+        st = compare_hits(g, o, o["tatb"], o["enc"], o["out"], obj, u, 1e-5 if mlp == "fp32" else 1e-3,
+                          1e-4 if mlp == "fp32" else 1e-2, 0.9999 if mlp == "fp32" else 0.999)
+        _say(str(st))
+        assert st["ok"], st
+    finally:
+        L.lsnif_release(ctx, oid)
+
+
+def sparse_blobs(rng, V, n_blobs):
+    occ3 = np.zeros((V, V, V), bool)
+    for _ in range(n_blobs):
+        cx, cy, cz = rng.integers(0, V, 3)
+        r = int(rng.integers(1, 4))
+        sl = (slice(max(cx - r, 0), cx + r), slice(max(cy - r, 0), cy + r), slice(max(cz - r, 0), cz + r))
+        occ3[sl] = rng.uniform(size=occ3[sl].shape) < 0.7
+    return occ3.transpose(2, 1, 0).ravel()          # bit x + V (y + V z)
+
+
+@pytest.mark.parametrize("V", [16, 32, 64])
+def test_sparse_grid_walk_parity(L, ctx, V):
+    """Grids that are mostly empty bricks (the walk crosses an empty 4x4x4 brick in one step):
+    voxel lists, points and slots equal the oracle's bit for bit on adversarial rays."""
+    from tests.test_oracle_pins import tiny_object, adversarial_rays
+    rng = np.random.default_rng(40 + V)
+    occ = sparse_blobs(rng, V, max(2, V // 8))
+    obj = tiny_object(V, occ, H=48, L=2, F=2, R=[V, 2 * V], log2_T=12, width=64, n_hidden=1, seed=V)
+    rays = adversarial_rays(rng, V, n_random=1500)
+    _say(f"sparse grid V={V}: {occ.sum()} occupied voxels, {len(rays)} rays")
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp32", "fp32"))
+    try:
+        g = gpu_query(L, ctx, oid, rays, debug=True, obj=obj)
+        o = oracle.query(obj, rays, debug=True)
+        check_intermediates(g, o, obj)
+        assert (o["count"] > 0).sum() > 100
+    finally:
+        L.lsnif_release(ctx, oid)
+
+
+def test_large_sparse_object_walk_parity(L, ctx):
+    """A V = 256 c4 object (mostly empty bricks) with its own balanced rays: bit-exact lists."""
+    obj = W.configs.c4_object(3)
+    assert obj.V == 256
+    from workloads.rays import balanced_rays
+    from workloads.rng import streams, RAYS
+    verts, tris = W.configs.c4_mesh(3)
+    rays = balanced_rays(streams(777)[RAYS], verts, tris, 3000, obj.bmin.astype(np.float64),
+                         obj.bmax.astype(np.float64))
+    _say(f"c4 object 3 (V={obj.V}): {len(rays)} rays")
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp16", "fp16"))
+    try:
+        g = gpu_query(L, ctx, oid, rays, debug=True, obj=obj)
+        o = oracle.query(obj, rays, debug=True)
+        check_intermediates(g, o, obj)
+    finally:
+        L.lsnif_release(ctx, oid)

@@ -30,7 +30,7 @@ def test_single_object_tunings_agree(L):
         for feat, mlp in (("fp16", "fp16"), ("fp32", "fp32")):
             oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
             ref = None
-            for sb, hot in ((5, 40960), (0, 0), (3, 20480), (4, 0)):
+            for sb, hot in ((5, 40960), (0, 0), (3, 20480), (4, 0), (6, 0)):
                 L.lsnif_set_tuning(ctx, oid, sb, 4, hot)
                 assert L.lsnif_get_tuning(ctx, oid) == {"sort_bits": sb, "pair_bits": 4, "hot_lds_bytes": hot}
                 out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
@@ -43,13 +43,13 @@ def test_single_object_tunings_agree(L):
             out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
             best = L.lsnif_autotune(ctx, oid, rays, out)
             print(feat, "autotuned", best, flush=True)
-            assert best["sort_bits"] in (0, 3, 4, 5) and best["hot_lds_bytes"] in (0, 20480, 40960)
+            assert best["sort_bits"] in (0, 4, 5, 6) and best["hot_lds_bytes"] in (0, 20480, 40960)
             assert L.lsnif_get_tuning(ctx, oid) == best
             L.lsnif_query(ctx, oid, rays, out)
             torch.cuda.synchronize()
             assert np.array_equal(bits(out), ref)
             with pytest.raises(L.LsnifError):
-                L.lsnif_set_tuning(ctx, oid, 6, 4, 0)
+                L.lsnif_set_tuning(ctx, oid, 7, 4, 0)
             L.lsnif_release(ctx, oid)
     finally:
         L.lsnif_destroy(ctx)
