@@ -124,6 +124,11 @@ lsnif_status supported(const lsnif_object_desc *d)
 {
     if (d->F != 2 && d->F != 3) return fail(LSNIF_E_INVALID, "kernels support F = 2 or 3 (got %d)", d->F);
     if (d->width != 64) return fail(LSNIF_E_INVALID, "kernels support width 64 (got %d)", d->width);
+    // the gathers address a level with 32-bit byte offsets
+    const uint64_t level_bytes = ((uint64_t)1 << d->log2_T) * d->F * dtype_size(d->feat_dtype);
+    if (level_bytes > ((uint64_t)1 << 32))
+        return fail(LSNIF_E_INVALID, "a level of 2^%d entries x %d features is %llu bytes; kernels address at most 4 GiB",
+                    d->log2_T, d->F, (unsigned long long)level_bytes);
     if (d->mlp_dtype == LSNIF_FP8_E4M3) {
         if (!d->fp8_act_scale) return fail(LSNIF_E_INVALID, "an FP8 MLP needs fp8_act_scale");
         for (int k = 0; k <= d->n_hidden; ++k)

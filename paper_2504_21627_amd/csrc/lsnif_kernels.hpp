@@ -187,7 +187,7 @@ __device__ __forceinline__ void level_cell_mm(const Geom &g, int l, const float 
     const float Rf = (float)g.R[l], sc = g.lsc[l];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        const float x = __builtin_fminf(__builtin_fmaxf(p[b] * sc, 0.0f), Rf);
+        const float x = __builtin_amdgcn_fmed3f(p[b] * sc, 0.0f, Rf);   // clamp to [0, R]
         const float k = __builtin_fminf(__builtin_floorf(x), Rf - 1.0f);
         i[b] = (uint32_t)k;
         wt[b] = x - k;
@@ -239,8 +239,14 @@ __device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restric
             }
         } else {
             level_cell_mm(g, l, p, i, wt);
-            const uint32_t my = g.my[l], mz = g.mz[l];
-            uint32_t t[3][2] = {{i[0], i[0] + 1u}, {i[1] * my, i[1] * my + my}, {i[2] * mz, i[2] * mz + mz}};
+            // With a power-of-two entry size the byte offset is formed directly: scaling
+            // x, y my and z mz by esz commutes with the sum and, as a shift, with the xor
+            // and the mask.
+            constexpr uint32_t sh = esz == 4 ? 2u : (esz == 8 ? 3u : (esz == 16 ? 4u : 0u));
+            constexpr bool scaled = sh != 0u;
+            const uint32_t my = g.my[l] << sh, mz = g.mz[l] << sh;
+            const uint32_t x0 = i[0] << sh;
+            uint32_t t[3][2] = {{x0, x0 + (1u << sh)}, {i[1] * my, i[1] * my + my}, {i[2] * mz, i[2] * mz + mz}};
             if ((g.aligned_mask >> l) & 1u) {
                 // one value for the whole wave: only aligned levels pay for the collapse
                 const float wf = face == 0 ? wt[0] : (face == 1 ? wt[1] : wt[2]);
@@ -254,20 +260,18 @@ __device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restric
             }
             // vertex slot: x + y + z on a directly indexed level, (x ^ y ^ z) & (T - 1) on a
             // hashed one (y, z already times their multipliers); the level kind is wave-uniform
+            constexpr uint32_t m = scaled ? 1u : esz;
             if ((g.dense_mask >> l) & 1u) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint32_t yz = t[1][q & 1] + t[2][q >> 1];
-                    off[lv][2 * q] = (t[0][0] + yz) * esz;
-                    off[lv][2 * q + 1] = (t[0][1] + yz) * esz;
-                }
+                for (int c = 0; c < 8; ++c)
+                    off[lv][c] = (t[0][c & 1] + t[1][(c >> 1) & 1] + t[2][c >> 2]) * m;
             } else {
-                const uint32_t hm = g.hmask[l];
+                const uint32_t hm = g.hmask[l] << sh;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t yz = t[1][q & 1] ^ t[2][q >> 1];
-                    off[lv][2 * q] = ((t[0][0] ^ yz) & hm) * esz;
-                    off[lv][2 * q + 1] = ((t[0][1] ^ yz) & hm) * esz;
+                    off[lv][2 * q] = ((t[0][0] ^ yz) & hm) * m;
+                    off[lv][2 * q + 1] = ((t[0][1] ^ yz) & hm) * m;
                 }
             }
         }
@@ -462,6 +466,23 @@ struct Lane {
     bool live;
 };
 
+// Tile of rays (or pairs) this block works on.  The dispatcher deals
+// workgroups to the 8 XCDs in turn (block b runs on XCD b mod 8), each XCD with
+// an L2 of its own, and tiles follow the coherence order of the rays.  Runs of
+// C consecutive tiles go to one XCD, so the rays an XCD has in flight lie in
+// fewer regions of the object and share more of its L2; short runs keep the
+// work of the XCDs even where the cost per tile drifts along the order.  Any
+// grid size maps one to one (the last partial round keeps b itself).
+__device__ __forceinline__ uint32_t block_tile()
+{
+    constexpr uint32_t C = 8;
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
+    const uint32_t full = nb / (8u * C) * (8u * C);
+    if (b >= full) return b;
+    const uint32_t x = b & 7u, k = b >> 3;
+    return ((k / C) * 8u + x) * C + k % C;
+}
+
 template <bool PAIRS>
 __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g, Shared &S, uint32_t *s_list,
                                               Lane &L)
@@ -473,7 +494,7 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g,
         for (int i = tid; i < g.coarse_words; i += kBlock) S.coarse[i] = g.coarse[i];
     if (tid <= (uint32_t)cap) S.hist[tid] = 0;
     __syncthreads();
-    const uint32_t slot0 = blockIdx.x * kBlock + tid;
+    const uint32_t slot0 = block_tile() * kBlock + tid;
     uint32_t r0 = 0u, pair0 = 0xffffffffu;
     bool live0;
     if constexpr (PAIRS) {
@@ -542,7 +563,7 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g,
     L.src = src;
     L.r = __float_as_uint(st[13 * kBlock + src]);
     L.pair = __float_as_uint(st[14 * kBlock + src]);
-    L.live = PAIRS ? L.pair != 0xffffffffu : blockIdx.x * kBlock + src < A.n;
+    L.live = PAIRS ? L.pair != 0xffffffffu : block_tile() * kBlock + src < A.n;
 }
 
 // ---------------------------------------------------------------- float32 path
@@ -555,7 +576,7 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g,
 __device__ __forceinline__ int tile_object(const PairArgs &P)
 {
     typedef const __attribute__((address_space(4))) int32_t cint;
-    return __builtin_amdgcn_readfirstlane(((cint *)P.tile_obj)[blockIdx.x]);
+    return __builtin_amdgcn_readfirstlane(((cint *)P.tile_obj)[block_tile()]);
 }
 // The object table, read through the constant address space in the device pass (the
 // host pass only type-checks kernel bodies and has no such address space).

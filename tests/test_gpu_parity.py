@@ -190,6 +190,16 @@ def test_edge_cases(L, ctx, c1, mlp):
         L.lsnif_release(ctx, oid)
 
 
+def test_level_beyond_offset_range_rejected(L, ctx):
+    """The gathers address a level with 32-bit byte offsets: 2^30 entries of two fp32
+    features (8 GiB a level) are refused before any table is read or allocated."""
+    d = L.ObjectDesc(W.configs.c1_object(), "fp32", "fp32")
+    d.d.log2_T = 30
+    with pytest.raises(L.LsnifError) as e:
+        L.lsnif_build(ctx, d)
+    assert e.value.status == L.LSNIF_E_INVALID and "4 GiB" in L.lsnif_last_error()
+
+
 def test_batch_invariance(L, ctx, c1):
     """A ray's result does not depend on its neighbours: shuffled batches agree bit for bit."""
     obj, rays = c1["objects"][0], c1["rays"]
