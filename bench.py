@@ -59,7 +59,8 @@ def stored_traffic(workload):
 
 def time_calls(L, ctx, call, steps, warmup):
     """Time `call(stream)` on torch's current stream: wall clock over `steps` calls, per-call
-    HIP event latency, and the library's own per-query sort and kernel time."""
+    HIP event latency, and the library's own per-query sort (or pair preparation), walk-kernel
+    and query-kernel times."""
     import torch
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -77,9 +78,10 @@ def time_calls(L, ctx, call, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     L.lsnif_profile_enable(ctx, False)
-    sort_ms, kern_ms, k = L.lsnif_profile_read(ctx)
+    sort_ms, walk_ms, kern_ms, k = L.lsnif_profile_read(ctx)
     lat = np.array([a.elapsed_time(b) for a, b in ev])
-    return wall, lat, (sort_ms / k if k else None), (kern_ms / k if k else None)
+    per = lambda x: x / k if k else None
+    return wall, lat, per(sort_ms), per(walk_ms), per(kern_ms)
 
 
 def time_path(L, ctx, oid, rays, out, steps, warmup):
@@ -136,12 +138,12 @@ def bench_c4(L, steps, warmup, tune=True):
         out = torch.empty((n, 6), dtype=torch.float32, device="cuda")
         tuning = L.lsnif_autotune_pairs(ctx, rays, pr, pi, inst, out) if tune else L.lsnif_get_tuning(ctx, ids[0])
         print(f"[bench] timing c4 direct ({tuning}): {warmup} warmup + {steps} steps", file=sys.stderr, flush=True)
-        wall_d, lat_d, prep_ms, kern_ms = time_calls(
+        wall_d, lat_d, prep_ms, walk_ms, kern_ms = time_calls(
             L, ctx, lambda st: L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out, st), steps, warmup)
         g = L.lsnif_graph_pairs(ctx, rays, pr, pi, inst, out)
         try:
             print(f"[bench] timing c4 graph replays", file=sys.stderr, flush=True)
-            wall_g, lat_g, _, _ = time_calls(L, ctx, lambda st: L.lsnif_graph_launch(g, st), steps, warmup)
+            wall_g, lat_g, _, _, _ = time_calls(L, ctx, lambda st: L.lsnif_graph_launch(g, st), steps, warmup)
         finally:
             L.lsnif_graph_destroy(g)
         # algorithmic gather bytes: boundary points per object from the per-ray voxel counts
@@ -169,7 +171,7 @@ def bench_c4(L, steps, warmup, tune=True):
         "pairs": n, "objects": len(objs), "tuning": tuning,
         "direct": {"value": val(wall_d), "unit": "Mpairs/s", "ms_per_step": wall_d * 1e3 / steps,
                    "p50_ms": float(np.percentile(lat_d, 50)), "p99_ms": float(np.percentile(lat_d, 99)),
-                   "prepare_ms": prep_ms, "kernel_ms": kern_ms},
+                   "prepare_ms": prep_ms, "walk_ms": walk_ms, "kernel_ms": kern_ms},
         "graph": {"value": val(wall_g), "unit": "Mpairs/s", "ms_per_step": wall_g * 1e3 / steps,
                   "p50_ms": float(np.percentile(lat_g, 50)), "p99_ms": float(np.percentile(lat_g, 99))},
         "roofline": {"bound": "hbm", "alg_bytes_per_launch": alg, "points_per_launch": pts,
@@ -271,10 +273,10 @@ def bench_c2(L, args):
                   else L.lsnif_get_tuning(ctx, oid))
         print(f"[bench] timing the {name} path ({tuning}): {args.warmup} warmup + {args.steps} steps",
               file=sys.stderr, flush=True)
-        wall, lat, sort_ms, kern_ms = time_path(L, ctx, oid, rays, out, args.steps, args.warmup)
+        wall, lat, sort_ms, walk_ms, kern_ms = time_path(L, ctx, oid, rays, out, args.steps, args.warmup)
         pts, cand = points_per_launch(L, ctx, oid, rays, out)
         paths[name] = {"wall": wall, "lat": lat, "points": pts, "cand": cand, "sort_ms": sort_ms,
-                       "kern_ms": kern_ms, "feat_bytes": 2 if feat == "fp16" else 4, "tuning": tuning}
+                       "walk_ms": walk_ms, "kern_ms": kern_ms, "feat_bytes": 2 if feat == "fp16" else 4, "tuning": tuning}
         L.lsnif_release(ctx, oid)
     L.lsnif_destroy(ctx)
 
@@ -307,7 +309,7 @@ def bench_c2(L, args):
                      "kernel": KERNEL if "fp16" in paths else "k_query_f32",
                      "alg_bytes_per_launch": alg_bytes, "points_per_launch": head["points"],
                      "bytes_per_point": bpp, "mean_kernel_ms": mean_ms,
-                     "mean_sort_ms": float(head["sort_ms"]),
+                     "mean_sort_ms": float(head["sort_ms"]), "mean_walk_ms": float(head["walk_ms"]),
                      "tuning": head["tuning"],
                      "mfma_tflops": flops / (mean_ms * 1e-3) / 1e12,
                      "mfma_frac": flops / (mean_ms * 1e-3) / 1e12 / MFMA_FP16_PEAK_TFLOPS},

@@ -348,12 +348,14 @@ lsnif_status lsnif_serve_stats_get(lsnif_ctx *ctx, lsnif_serve_stats *stats);
 lsnif_status lsnif_serve_stop(lsnif_ctx *ctx);
 
 /* Kernel timing.  While enabled, every query on the context records HIP
- * events on its stream before the coherence sort, between the sort and the
- * query kernel, and after the query kernel.  lsnif_profile_read waits for the
- * recorded queries, returns the summed sort and query-kernel milliseconds and
- * the number of queries since the last read, and forgets them. */
+ * events on its stream before the coherence sort (pair queries: the pair
+ * preparation), before the voxel-walk kernel, before the query kernel and
+ * after it.  lsnif_profile_read waits for the recorded queries, returns the
+ * summed milliseconds of the three phases and the number of queries since the
+ * last read, and forgets them.  Any output pointer may be NULL. */
 lsnif_status lsnif_profile_enable(lsnif_ctx *ctx, int32_t on);
-lsnif_status lsnif_profile_read(lsnif_ctx *ctx, double *sort_ms, double *kernel_ms, uint64_t *launches);
+lsnif_status lsnif_profile_read(lsnif_ctx *ctx, double *sort_ms, double *walk_ms, double *kernel_ms,
+                                uint64_t *launches);
 
 #ifdef __cplusplus
 }

@@ -237,7 +237,7 @@ __device__ __forceinline__ bool keep_f64(const VRay &w, const int c[3], int V)
 // is crossed in one step that lands on the cell the cell-by-cell walk reaches
 // next; every decision still compares values of the same plane functions.
 __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, const uint32_t *coarse,
-                                           uint32_t *list, int stride, int cap)
+                                           uint32_t *list, uint32_t stride, int cap)
 {
     if (!w.cand) return 0;
     int c[3];
@@ -317,7 +317,7 @@ __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, const u
         if (g.recheck && grazing(tin, tout, w.ta, w.tb)) keep = keep_f64(w, c, V);
         if (keep) {
             if ((mask >> bit_in_brick(c)) & 1ull) {
-                list[n * stride] = pack_ijk(c);
+                list[(size_t)n * stride] = pack_ijk(c);
                 if (++n == cap) break;
             }
         }

@@ -79,7 +79,7 @@ lsnif_status lsnif_graph_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_r
     if (n == 0) return fail(LSNIF_E_INVALID, "nothing to capture (n = 0)");
     DeviceGuard guard(ctx->device);
     return capture(
-        ctx, query_ws_bytes(n, ob->geom.sort_bits),
+        ctx, query_ws_bytes(n, ob->geom.sort_bits, ob->geom.H >> 1),
         [&](hipStream_t s, void *ws) { return enqueue_query(ctx, *ob, d_rays, n, d_out, nullptr, s, ws); }, out);
 }
 
@@ -97,7 +97,7 @@ lsnif_status lsnif_graph_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
     lsnif_status st = pairs_setup(ctx, ps);
     if (st) return st;
     return capture(
-        ctx, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs),
+        ctx, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs, ps.maxH >> 1),
         [&](hipStream_t s, void *ws) {
             return enqueue_pairs(ctx, ps, d_rays, n_rays, d_pair_ray, d_pair_inst, n_pairs, d_inst, n_inst, d_out,
                                  s, ws);

@@ -451,25 +451,28 @@ lsnif_status lsnif_profile_enable(lsnif_ctx *ctx, int32_t on)
     return LSNIF_OK;
 }
 
-lsnif_status lsnif_profile_read(lsnif_ctx *ctx, double *sort_ms, double *kernel_ms, uint64_t *launches)
+lsnif_status lsnif_profile_read(lsnif_ctx *ctx, double *sort_ms, double *walk_ms, double *kernel_ms,
+                                uint64_t *launches)
 {
     if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-    double so = 0.0, kq = 0.0;
+    double so = 0.0, wk = 0.0, kq = 0.0;
     const uint64_t k = ctx->pending.size();
     lsnif_status st = LSNIF_OK;
     for (auto &v : ctx->pending) {
-        float a = 0.0f, b = 0.0f;
+        float a = 0.0f, b = 0.0f, c = 0.0f;
         if (st == LSNIF_OK &&
-            (hipEventSynchronize(v[2]) != hipSuccess || hipEventElapsedTime(&a, v[0], v[1]) != hipSuccess ||
-             hipEventElapsedTime(&b, v[1], v[2]) != hipSuccess))
+            (hipEventSynchronize(v[3]) != hipSuccess || hipEventElapsedTime(&a, v[0], v[1]) != hipSuccess ||
+             hipEventElapsedTime(&b, v[1], v[2]) != hipSuccess || hipEventElapsedTime(&c, v[2], v[3]) != hipSuccess))
             st = fail(LSNIF_E_DEVICE, "reading query events failed");
         so += a;
-        kq += b;
+        wk += b;
+        kq += c;
         for (hipEvent_t e : v) ctx->spare.push_back(e);
     }
     ctx->pending.clear();
     if (sort_ms) *sort_ms = so;
+    if (walk_ms) *walk_ms = wk;
     if (kernel_ms) *kernel_ms = kq;
     if (launches) *launches = k;
     return st;
@@ -487,7 +490,7 @@ static lsnif_status run_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ra
     lsnif_status st = check_query(ctx, object_id, d_rays, n, d_out, ob);
     if (st || n == 0) return st;
     DeviceGuard guard(ctx->device);
-    if ((st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n, ob->geom.sort_bits)))) return st;
+    if ((st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n, ob->geom.sort_bits, ob->geom.H >> 1)))) return st;
     return enqueue_query(ctx, *ob, d_rays, n, d_out, dbg, static_cast<hipStream_t>(stream), ctx->ws);
 }
 
@@ -503,7 +506,8 @@ lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
     PairsSetup ps;
     lsnif_status st = pairs_setup(ctx, ps);
     if (st) return st;
-    if ((st = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs)))) return st;
+    if ((st = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs, ps.maxH >> 1))))
+        return st;
     return enqueue_pairs(ctx, ps, d_rays, n_rays, d_pair_ray, d_pair_inst, n_pairs, d_inst, n_inst, d_out,
                          static_cast<hipStream_t>(stream), ctx->pws);
 }
@@ -591,20 +595,32 @@ static hipEvent_t take_event(lsnif_ctx *ctx)
     return e;
 }
 
-size_t query_ws_bytes(uint32_t n, uint32_t sort_bits)
-{
-    if (n < kSortMin || sort_bits == 0) return 0;
-    return ((size_t)2 * n + sort_bins(sort_bits) + sort_scan_blocks(sort_bits)) * sizeof(uint32_t);
-}
-
 static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
-size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs)
+// Coherence-sort arrays (keys, order, bins, scan partials), when the batch is sorted.
+static size_t sort_ws_bytes(uint32_t n, uint32_t sort_bits)
+{
+    if (n < kSortMin || sort_bits == 0) return 0;
+    return al256(((size_t)2 * n + sort_bins(sort_bits) + sort_scan_blocks(sort_bits)) * sizeof(uint32_t));
+}
+
+// Voxel counts (one byte) and voxel lists (cap entries) of n_slots slots.
+static size_t list_ws_bytes(size_t n_slots, uint32_t cap)
+{
+    return al256(n_slots) + al256(n_slots * cap * sizeof(uint32_t));
+}
+
+size_t query_ws_bytes(uint32_t n, uint32_t sort_bits, uint32_t cap)
+{
+    return sort_ws_bytes(n, sort_bits) + list_ws_bytes(n, cap);
+}
+
+size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs, uint32_t cap)
 {
     const size_t n_slots = (size_t)(n_pairs + kBlock - 1) / kBlock * kBlock + (size_t)kBlock * n_objs;
     return al256((size_t)n_rays * 8) + al256((size_t)n_pairs * sizeof(PairRes)) + al256((size_t)n_pairs * 4) +
            al256(n_slots * 4) + al256(n_slots / kBlock * 4) + al256((size_t)n_objs * kPairBins * 4) +
-           2 * al256((size_t)n_objs * 4);
+           2 * al256((size_t)n_objs * 4) + list_ws_bytes(n_slots, cap);
 }
 
 lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
@@ -637,13 +653,14 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
         A.dbg.enc = dbg->enc;
         A.dbg.act_amax = dbg->act_amax;
     }
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (ctx->profiling) {
         for (auto &e : ev)
             if (!(e = take_event(ctx))) return fail(LSNIF_E_DEVICE, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(ev[0], s));
     }
-    if (n >= kSortMin && ob.geom.sort_bits) {
+    const size_t sort_bytes = sort_ws_bytes(n, ob.geom.sort_bits);
+    if (sort_bytes) {
         uint32_t *keys = static_cast<uint32_t *>(ws);
         uint32_t *order = keys + n;
         uint32_t *hist = order + n;
@@ -652,14 +669,19 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
     }
     if (ev[1]) HIP_TRY(hipEventRecord(ev[1], s));
     const uint32_t grid = (n + kBlock - 1) / kBlock;
+    char *wl = static_cast<char *>(ws) + sort_bytes;
+    A.nvox = reinterpret_cast<uint8_t *>(wl);
+    A.lists = reinterpret_cast<uint32_t *>(wl + al256(n));
+    HIP_TRY(launch_walk(A, false, grid, s));
+    if (ev[2]) HIP_TRY(hipEventRecord(ev[2], s));
     const int kbm = ob.mlp.kb_point;
     if (ob.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, ob.feat_dtype, ob.F, false, grid, s));
     else if (ob.mlp_dtype == LSNIF_FP16) HIP_TRY(launch_mma_f16(A, ob.feat_dtype, ob.F, kbm, false, grid, s));
     else if (ob.mlp_dtype == LSNIF_BF16) HIP_TRY(launch_mma_bf16(A, ob.feat_dtype, ob.F, kbm, false, grid, s));
     else HIP_TRY(launch_mma_fp8(A, ob.feat_dtype, ob.F, kbm, false, grid, s));
-    if (ev[2]) {
-        HIP_TRY(hipEventRecord(ev[2], s));
-        ctx->pending.push_back({ev[0], ev[1], ev[2]});
+    if (ev[3]) {
+        HIP_TRY(hipEventRecord(ev[3], s));
+        ctx->pending.push_back({ev[0], ev[1], ev[2], ev[3]});
     }
     return LSNIF_OK;
 }
@@ -750,9 +772,12 @@ lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray
     P.obj_total = reinterpret_cast<uint32_t *>(w);
     w += al256((size_t)n_objs * 4);
     P.obj_off = reinterpret_cast<uint32_t *>(w);
+    w += al256((size_t)n_objs * 4);
+    uint8_t *nvox = reinterpret_cast<uint8_t *>(w);
+    uint32_t *lists = reinterpret_cast<uint32_t *>(w + al256(n_slots));
     P.n_slots = n_slots;
     P.n_tiles = n_tiles;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (ctx->profiling) {
         for (auto &e : ev)
             if (!(e = take_event(ctx))) return fail(LSNIF_E_DEVICE, "hipEventCreate failed");
@@ -774,6 +799,10 @@ lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray
         A.pr.slot_pair = P.slot_pair;
         A.pr.minkey = P.minkey;
         A.pr.res = P.res;
+        A.nvox = nvox;
+        A.lists = lists;
+        HIP_TRY(launch_walk(A, true, n_tiles, s));
+        if (ev[2]) HIP_TRY(hipEventRecord(ev[2], s));
         const int kbm = ps.kbm;
         if (first.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, first.feat_dtype, first.F, true, n_tiles, s));
         else if (first.mlp_dtype == LSNIF_FP16)
@@ -782,9 +811,10 @@ lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray
             HIP_TRY(launch_mma_bf16(A, first.feat_dtype, first.F, kbm, true, n_tiles, s));
         else HIP_TRY(launch_mma_fp8(A, first.feat_dtype, first.F, kbm, true, n_tiles, s));
     }
-    if (ev[2]) {
-        HIP_TRY(hipEventRecord(ev[2], s));
-        ctx->pending.push_back({ev[0], ev[1], ev[2]});
+    if (ev[3]) {
+        if (!n_pairs) HIP_TRY(hipEventRecord(ev[2], s));
+        HIP_TRY(hipEventRecord(ev[3], s));
+        ctx->pending.push_back({ev[0], ev[1], ev[2], ev[3]});
     }
     HIP_TRY(launch_pairs_payload(P, s));
     return LSNIF_OK;

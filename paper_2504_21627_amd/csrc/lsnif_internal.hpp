@@ -62,9 +62,10 @@ void destroy_server(lsnif_ctx *ctx);   // stops a running serving loop
 // Batches below this size are processed in the order given (no coherence sort).
 constexpr uint32_t kSortMin = 8192;
 
-// Workspace bytes of one query of n rays, and of one pair query.
-size_t query_ws_bytes(uint32_t n, uint32_t sort_bits);
-size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs);
+// Workspace bytes of one query of n rays, and of one pair query; cap is the
+// longest voxel list (H / 2, the largest over the objects for pairs).
+size_t query_ws_bytes(uint32_t n, uint32_t sort_bits, uint32_t cap);
+size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs, uint32_t cap);
 
 }  // namespace lsnif
 

@@ -83,6 +83,8 @@ struct QueryArgs {
     lsnif_hit *hits;
     uint32_t n;               // rays (single object) or sorted pair slots (pairs)
     const uint32_t *order;    // processing order of the rays (coherence sort), or NULL
+    uint32_t *lists;          // voxel lists by slot: entry j of slot i at lists[j n + i]
+    uint8_t *nvox;            // listed voxels of each slot
     Dbg dbg;
     PairArgs pr;
     uint32_t hot_lds;         // dynamic LDS bytes after the voxel lists for hot levels
@@ -443,15 +445,15 @@ __device__ __forceinline__ void decode_store(const QueryArgs &A, const Mlp &mm, 
 
 // ------------------------------------------------------------- shared prologue
 //
-// Each lane walks the voxels of ray blockIdx.x * kBlock + threadIdx.x, then
-// the block's rays are ordered by voxel count (most first) so that each wave
+// The walk kernel lists the voxels of slot blockIdx-tile * kBlock + threadIdx.x
+// into the workspace; the query kernels then load each slot's list into LDS
+// and order the block's rays by voxel count (most first), so that each wave
 // encodes rays with similar numbers of boundary points.  After the prologue,
 // lane `tid` works on ray `src` of the block; its voxel list is at
 // s_list[j * kBlock + src] and its walk state has been reloaded from LDS.
 constexpr int kState = 15;          // words of walk state per ray kept in LDS
 
 struct Shared {
-    uint32_t coarse[kCoarseLdsWords];
     float state[kState * kBlock];
     uint32_t hist[kMaxList + 2];
     uint16_t perm[kBlock];
@@ -483,41 +485,82 @@ __device__ __forceinline__ uint32_t block_tile()
     return ((k / C) * 8u + x) * C + k % C;
 }
 
+// Ray (or pair) of slot `slot` and its object-space segment.
+template <bool PAIRS>
+__device__ __forceinline__ void slot_ray(const QueryArgs &A, const Geom &g, uint32_t slot, uint32_t &r,
+                                         uint32_t &pair, bool &live, VRay &w)
+{
+    r = 0u;
+    pair = 0xffffffffu;
+    if constexpr (PAIRS) {
+        pair = slot < A.n ? A.pr.slot_pair[slot] : 0xffffffffu;
+        live = pair != 0xffffffffu;
+        if (live) r = A.pr.pair_ray[pair];
+    } else {
+        live = slot < A.n;
+        if (live) r = A.order ? A.order[slot] : slot;
+    }
+    w.valid = w.cand = false;
+    w.ta = w.tb = w.tmax = w.tmin = 0.0f;
+    w.mov = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w.o[a] = w.d[a] = w.inv[a] = 0.0f;
+    if (live) {
+        float4 ra = A.rays[2 * r], rb = A.rays[2 * r + 1];
+        if constexpr (PAIRS) to_object_space(A.pr.inst[A.pr.pair_inst[pair]], ra, rb);
+        setup_ray(g, ra, rb, w);
+    }
+}
+
+// The voxel walk of every slot, in a kernel of its own: it needs few registers,
+// so many waves per SIMD hide the latency of its dependent brick-mask loads,
+// which the query kernels (two waves per SIMD) could not.
+template <bool PAIRS>
+__device__ __forceinline__ void walk_body(const QueryArgs &A, const Geom &g, uint32_t *coarse)
+{
+    const uint32_t tid = threadIdx.x;
+    const bool lds_coarse = g.coarse_words <= kCoarseLdsWords;
+    if (lds_coarse)
+        for (int i = tid; i < g.coarse_words; i += kBlock) coarse[i] = g.coarse[i];
+    __syncthreads();
+    const uint32_t slot = block_tile() * kBlock + tid;
+    uint32_t r, pair;
+    bool live;
+    VRay w;
+    slot_ray<PAIRS>(A, g, slot, r, pair, live, w);
+    int nvox = 0;
+    if (live) {
+        uint32_t *list = A.lists + slot;
+        nvox = lds_coarse ? walk_voxels(g, w, coarse, list, A.n, g.H >> 1)
+                          : walk_voxels(g, w, g.coarse, list, A.n, g.H >> 1);
+    }
+    if (slot < A.n) A.nvox[slot] = (uint8_t)nvox;
+}
+
 template <bool PAIRS>
 __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g, Shared &S, uint32_t *s_list,
                                               Lane &L)
 {
     const uint32_t tid = threadIdx.x;
     const int cap = g.H >> 1;
-    const bool lds_coarse = g.coarse_words <= kCoarseLdsWords;
-    if (lds_coarse)
-        for (int i = tid; i < g.coarse_words; i += kBlock) S.coarse[i] = g.coarse[i];
     if (tid <= (uint32_t)cap) S.hist[tid] = 0;
     __syncthreads();
     const uint32_t slot0 = block_tile() * kBlock + tid;
-    uint32_t r0 = 0u, pair0 = 0xffffffffu;
+    uint32_t r0, pair0;
     bool live0;
-    if constexpr (PAIRS) {
-        pair0 = slot0 < A.n ? A.pr.slot_pair[slot0] : 0xffffffffu;
-        live0 = pair0 != 0xffffffffu;
-        if (live0) r0 = A.pr.pair_ray[pair0];
-    } else {
-        live0 = slot0 < A.n;
-        if (live0) r0 = A.order ? A.order[slot0] : slot0;
-    }
     VRay w;
-    w.valid = w.cand = false;
-    w.ta = w.tb = w.tmax = w.tmin = 0.0f;
-    w.mov = 0;
+    slot_ray<PAIRS>(A, g, slot0, r0, pair0, live0, w);
+    // the slot's voxel list into LDS, eight loads in flight at a time
+    const int nvox = live0 ? (int)A.nvox[slot0] : 0;
+    const int nmax = __builtin_amdgcn_readfirstlane(wave_max(nvox));
+    for (int j0 = 0; j0 < nmax; j0 += 8) {
+        uint32_t v[8];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) w.o[a] = w.d[a] = w.inv[a] = 0.0f;
-    int nvox = 0;
-    if (live0) {
-        float4 ra = A.rays[2 * r0], rb = A.rays[2 * r0 + 1];
-        if constexpr (PAIRS) to_object_space(A.pr.inst[A.pr.pair_inst[pair0]], ra, rb);
-        setup_ray(g, ra, rb, w);
-        nvox = lds_coarse ? walk_voxels(g, w, S.coarse, s_list + tid, kBlock, cap)
-                          : walk_voxels(g, w, g.coarse, s_list + tid, kBlock, cap);
+        for (int q = 0; q < 8; ++q)
+            if (j0 + q < nvox) v[q] = A.lists[(size_t)(j0 + q) * A.n + slot0];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (j0 + q < nvox) s_list[(j0 + q) * kBlock + tid] = v[q];
     }
     float *st = S.state;
 #pragma unroll
@@ -1031,6 +1074,21 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
     } else {
         query_mma_body<TF, TM, F, WIDTH, KBM, false, HOT>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list,
                                                     S);
+    }
+}
+
+// ------------------------------------------------------------------ voxel walk
+template <bool PAIRS>
+__global__ __launch_bounds__(kBlock) void k_walk(QueryArgs A)
+{
+    __shared__ uint32_t coarse[kCoarseLdsWords];
+    if constexpr (PAIRS) {
+        const int o = tile_object(A.pr);
+        if (o < 0) return;   // the query kernel skips such a tile too
+        const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
+        walk_body<true>(A, O.g, coarse);
+    } else {
+        walk_body<false>(A, A.g, coarse);
     }
 }
 

@@ -258,24 +258,25 @@ private:
             if (r.n_pairs && (!r.d_pair_ray || !r.d_pair_inst || !r.d_inst))
                 return fail(LSNIF_E_INVALID, "pair buffers are NULL");
             if (dry_) {
-                need = pairs_ws_bytes(r.n_rays, r.n_pairs, r.n_inst + 1);
+                need = pairs_ws_bytes(r.n_rays, r.n_pairs, r.n_inst + 1, kMaxList);
                 return LSNIF_OK;
             }
             std::lock_guard<std::recursive_mutex> g(ctx_->mu);
             PairsSetup ps;
             lsnif_status st = pairs_setup(ctx_, ps);
             if (st) return st;
-            need = pairs_ws_bytes(r.n_rays, r.n_pairs, ps.n_objs);
+            need = pairs_ws_bytes(r.n_rays, r.n_pairs, ps.n_objs, ps.maxH >> 1);
             return LSNIF_OK;
         }
-        uint32_t bits = 5;   // dry runs: the default resolution
+        uint32_t bits = 5, cap = kMaxList;   // dry runs: the default resolution, the longest lists
         if (!dry_) {
             std::lock_guard<std::recursive_mutex> g(ctx_->mu);
             auto it = ctx_->objects.find(r.object_id);
             if (it == ctx_->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", r.object_id);
             bits = it->second.geom.sort_bits;
+            cap = (uint32_t)it->second.geom.H >> 1;
         }
-        need = query_ws_bytes(r.n_rays, bits);
+        need = query_ws_bytes(r.n_rays, bits, cap);
         return LSNIF_OK;
     }
 

@@ -121,7 +121,7 @@ lsnif_status lsnif_autotune(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray 
     if (n == 0) return fail(LSNIF_E_INVALID, "nothing to time (n = 0)");
     Object &ob = ctx->objects[object_id];
     DeviceGuard guard(ctx->device);
-    if ((st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n, 6)))) return st;   // the finest candidate
+    if ((st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n, 6, ob.geom.H >> 1)))) return st;   // the finest candidate
     HIP_TRY(hipDeviceSynchronize());
     const lsnif_tuning start = current(ob);
     lsnif_tuning win = start;
@@ -177,7 +177,8 @@ lsnif_status lsnif_autotune_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint3
                 PairsSetup ps;
                 lsnif_status e = pairs_setup(ctx, ps);   // uploads the changed object table
                 if (e) return e;
-                if ((e = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs)))) return e;
+                if ((e = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs, ps.maxH >> 1))))
+                    return e;
                 float ms = 0.0f;
                 e = time_ms(
                     [&](hipStream_t q) {

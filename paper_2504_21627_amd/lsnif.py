@@ -118,7 +118,7 @@ def load():
     lib.lsnif_serve_stop.argtypes = [C.c_void_p]
     lib.lsnif_profile_enable.argtypes = [C.c_void_p, C.c_int32]
     lib.lsnif_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                       C.POINTER(C.c_uint64)]
+                                       C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
     lib.lsnif_graph_query.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
                                       C.POINTER(C.c_void_p)]
     lib.lsnif_graph_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
@@ -387,10 +387,10 @@ def lsnif_profile_enable(ctx, on=True):
 
 
 def lsnif_profile_read(ctx):
-    """(sort_ms, kernel_ms, queries) summed over the queries since the last read."""
-    a, b, k = C.c_double(), C.c_double(), C.c_uint64()
-    _check(load().lsnif_profile_read(ctx, C.byref(a), C.byref(b), C.byref(k)))
-    return a.value, b.value, k.value
+    """(sort_ms, walk_ms, kernel_ms, queries) summed over the queries since the last read."""
+    a, b, c, k = C.c_double(), C.c_double(), C.c_double(), C.c_uint64()
+    _check(load().lsnif_profile_read(ctx, C.byref(a), C.byref(b), C.byref(c), C.byref(k)))
+    return a.value, b.value, c.value, k.value
 
 
 def hits_from(out):

@@ -63,9 +63,17 @@ def test_slots_limit_concurrency(L, ctx):
     L.lsnif_serve_stop(ctx)
 
 
+def dry_ws(n):
+    """Workspace of a dry-run query of n rays: the coherence sort at 32^3 cells (2n words,
+    262,145 bins, 257 scan partials) when n >= 8192, then a voxel count byte and a list of
+    up to 32 voxels per ray, each array 256-byte aligned."""
+    a = lambda x: (x + 255) // 256 * 256
+    sort = a((2 * n + 262_145 + 257) * 4) if n >= 8192 else 0
+    return sort + a(n) + a(n * 32 * 4)
+
+
 def test_budget_rejects_what_can_never_fit_and_queues_the_rest(L, ctx):
-    # a query of n >= 8192 rays needs (2n + 262401) * 4 bytes of workspace
-    one = (2 * 100_000 + 262_145 + 257) * 4
+    one = dry_ws(100_000)
     L.lsnif_serve_start(ctx, max_inflight=8, hbm_budget=one + 4096, dry_run_ns_per_ray=200)
     with pytest.raises(L.LsnifError) as e:
         L.lsnif_serve_submit(ctx, req(L, 4_000_000))
@@ -134,8 +142,8 @@ def test_wait_timeout_and_unknown_ticket(L, ctx):
 
 def test_no_overtaking(L, ctx):
     """A large waiting request is not overtaken by small ones that would fit."""
-    one = (2 * 100_000 + 262_145 + 257) * 4
-    L.lsnif_serve_start(ctx, max_inflight=8, hbm_budget=one + (2 * 9000 + 262_402) * 4 + 8192,
+    one = dry_ws(100_000)
+    L.lsnif_serve_start(ctx, max_inflight=8, hbm_budget=one + dry_ws(9000) + 8192,
                         dry_run_ns_per_ray=300)
     big1 = L.lsnif_serve_submit(ctx, req(L, 100_000))               # 30 ms
     big2 = L.lsnif_serve_submit(ctx, req(L, 100_000))               # must wait for big1
