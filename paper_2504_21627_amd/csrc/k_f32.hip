@@ -15,7 +15,7 @@ __global__ __launch_bounds__(kBlock) void k_debug(DebugArgs D)
     VRay w;
     setup_ray(g, D.rays[2 * r], D.rays[2 * r + 1], w);
     const int H = g.H, L = g.L;
-    const int nvox = walk_voxels(g, w, g.coarse, s_list + tid, kBlock, H >> 1);
+    const int nvox = walk_voxels<true>(g, w, g.coarse, s_list + tid, kBlock, H >> 1);
     const int count = 2 * nvox;
     if (D.b.count) D.b.count[r] = w.valid ? count : -1;
     if (D.b.tatb) {

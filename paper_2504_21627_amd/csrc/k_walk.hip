@@ -4,10 +4,15 @@
 
 namespace lsnif {
 
-hipError_t launch_walk(const QueryArgs &A, bool pairs, uint32_t grid, hipStream_t s)
+hipError_t launch_walk(const QueryArgs &A, bool pairs, bool recheck, uint32_t grid, hipStream_t s)
 {
-    if (pairs) hipLaunchKernelGGL(k_walk<true>, dim3(grid), dim3(kBlock), 0, s, A);
-    else hipLaunchKernelGGL(k_walk<false>, dim3(grid), dim3(kBlock), 0, s, A);
+    if (pairs) {
+        if (recheck) hipLaunchKernelGGL((k_walk<true, true>), dim3(grid), dim3(kBlock), 0, s, A);
+        else hipLaunchKernelGGL((k_walk<true, false>), dim3(grid), dim3(kBlock), 0, s, A);
+    } else {
+        if (recheck) hipLaunchKernelGGL((k_walk<false, true>), dim3(grid), dim3(kBlock), 0, s, A);
+        else hipLaunchKernelGGL((k_walk<false, false>), dim3(grid), dim3(kBlock), 0, s, A);
+    }
     return hipGetLastError();
 }
 

@@ -236,15 +236,19 @@ __device__ __forceinline__ bool keep_f64(const VRay &w, const int c[3], int V)
 // brick, its 64-bit mask, loaded once on entering the brick.  An empty brick
 // is crossed in one step that lands on the cell the cell-by-cell walk reaches
 // next; every decision still compares values of the same plane functions.
+template <bool RECHECK>
 __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, const uint32_t *coarse,
                                            uint32_t *list, uint32_t stride, int cap)
 {
     if (!w.cand) return 0;
-    int c[3];
+    int c[3], st[3], pk[3];
     float en[3], ex[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         c[a] = start_cell(g, w, a);
+        const bool up = w.d[a] > 0.0f;
+        st[a] = up ? 1 : -1;   // cell step along the ray
+        pk[a] = up ? 1 : 0;    // exit plane of cell k: k + pk
         if (w.mov & (1u << a)) {
             cell_span(w, a, c[a], en[a], ex[a]);
         } else {
@@ -304,36 +308,36 @@ __device__ __forceinline__ int walk_voxels(const Geom &g, const VRay &w, const u
                 if (w.mov & (1u << a)) cell_span(w, a, c[a], en[a], ex[a]);
             continue;
         }
-        float tin = -__builtin_inff(), tout = __builtin_inff();
-        int ia = -1, oa = -1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (w.mov & (1u << a)) {
-                if (ia < 0 || en[a] > tin) { tin = en[a]; ia = a; }
-                if (oa < 0 || ex[a] < tout) { tout = ex[a]; oa = a; }
-            }
-        }
+        // A still axis has en = -inf and ex = +inf, so it never decides the interval; the
+        // exit axis is the lowest one whose exit equals the earliest (the axis order of ties).
+        const float tin = __builtin_fmaxf(__builtin_fmaxf(en[0], en[1]), en[2]);
+        const float tout = __builtin_fminf(__builtin_fminf(ex[0], ex[1]), ex[2]);
+        const int oa = ex[0] == tout ? 0 : (ex[1] == tout ? 1 : 2);
         bool keep = fmin2(tout, w.tb) > fmax2(tin, w.ta);
-        if (g.recheck && grazing(tin, tout, w.ta, w.tb)) keep = keep_f64(w, c, V);
-        if (keep) {
-            if ((mask >> bit_in_brick(c)) & 1ull) {
-                list[(size_t)n * stride] = pack_ijk(c);
-                if (++n == cap) break;
-            }
+        if constexpr (RECHECK)
+            if (g.recheck && grazing(tin, tout, w.ta, w.tb)) keep = keep_f64(w, c, V);
+        if (keep && ((mask >> bit_in_brick(c)) & 1ull)) {
+            list[(size_t)n * stride] = pack_ijk(c);
+            if (++n == cap) break;
         }
         if (tout >= w.tb) break;
-        bool out = false;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            if (a == oa) {
-                const bool up = w.d[a] > 0.0f;
-                c[a] += up ? 1 : -1;
-                out = c[a] < 0 || c[a] >= V;
-                en[a] = ex[a];
-                ex[a] = plane_t((float)(up ? c[a] + 1 : c[a]), w.o[a], w.inv[a]);
-            }
-        }
-        if (out) break;
+        // step along the exit axis, as selects rather than a branch per axis
+        const bool s0 = oa == 0, s1 = oa == 1;
+        const bool s2 = !s0 && !s1;
+        c[0] += s0 ? st[0] : 0;
+        c[1] += s1 ? st[1] : 0;
+        c[2] += s2 ? st[2] : 0;
+        const int cn = s0 ? c[0] : (s1 ? c[1] : c[2]);
+        const int kp = cn + (s0 ? pk[0] : (s1 ? pk[1] : pk[2]));
+        const float xn = plane_t((float)kp, s0 ? w.o[0] : (s1 ? w.o[1] : w.o[2]),
+                                 s0 ? w.inv[0] : (s1 ? w.inv[1] : w.inv[2]));
+        en[0] = s0 ? ex[0] : en[0];
+        en[1] = s1 ? ex[1] : en[1];
+        en[2] = s2 ? ex[2] : en[2];
+        ex[0] = s0 ? xn : ex[0];
+        ex[1] = s1 ? xn : ex[1];
+        ex[2] = s2 ? xn : ex[2];
+        if (cn < 0 || cn >= V) break;
     }
     return n;
 }

@@ -672,7 +672,7 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
     char *wl = static_cast<char *>(ws) + sort_bytes;
     A.nvox = reinterpret_cast<uint8_t *>(wl);
     A.lists = reinterpret_cast<uint32_t *>(wl + al256(n));
-    HIP_TRY(launch_walk(A, false, grid, s));
+    HIP_TRY(launch_walk(A, false, ob.geom.recheck != 0, grid, s));
     if (ev[2]) HIP_TRY(hipEventRecord(ev[2], s));
     const int kbm = ob.mlp.kb_point;
     if (ob.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, ob.feat_dtype, ob.F, false, grid, s));
@@ -722,6 +722,7 @@ lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps)
     ps.kbm = 1;
     ps.maxH = 2;
     ps.hot_max = 0;
+    ps.recheck = false;
     for (auto &kv : ctx->objects) {
         if (!same_class(kv.second, *ps.first))
             return fail(LSNIF_E_INVALID, "pair queries need every object of the context in one kernel class "
@@ -729,6 +730,7 @@ lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps)
         ps.kbm = std::max(ps.kbm, kv.second.mlp.kb_point);
         ps.maxH = std::max(ps.maxH, kv.second.geom.H);
         ps.hot_max = std::max(ps.hot_max, kv.second.geom.hot_bytes);
+        ps.recheck = ps.recheck || kv.second.geom.recheck;
     }
     return upload_table(ctx, ps.n_objs);
 }
@@ -801,7 +803,7 @@ lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray
         A.pr.res = P.res;
         A.nvox = nvox;
         A.lists = lists;
-        HIP_TRY(launch_walk(A, true, n_tiles, s));
+        HIP_TRY(launch_walk(A, true, ps.recheck, n_tiles, s));
         if (ev[2]) HIP_TRY(hipEventRecord(ev[2], s));
         const int kbm = ps.kbm;
         if (first.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, first.feat_dtype, first.F, true, n_tiles, s));

@@ -102,6 +102,7 @@ struct PairsSetup {
     const Object *first = nullptr;
     int kbm = 1, maxH = 2;
     uint32_t hot_max = 0;   // largest hot-level LDS footprint of the objects
+    bool recheck = false;   // some object re-decides grazing voxels in float64
     uint32_t n_objs = 0;
 };
 lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps);

@@ -515,7 +515,7 @@ __device__ __forceinline__ void slot_ray(const QueryArgs &A, const Geom &g, uint
 // The voxel walk of every slot, in a kernel of its own: it needs few registers,
 // so many waves per SIMD hide the latency of its dependent brick-mask loads,
 // which the query kernels (two waves per SIMD) could not.
-template <bool PAIRS>
+template <bool PAIRS, bool RECHECK>
 __device__ __forceinline__ void walk_body(const QueryArgs &A, const Geom &g, uint32_t *coarse)
 {
     const uint32_t tid = threadIdx.x;
@@ -531,8 +531,8 @@ __device__ __forceinline__ void walk_body(const QueryArgs &A, const Geom &g, uin
     int nvox = 0;
     if (live) {
         uint32_t *list = A.lists + slot;
-        nvox = lds_coarse ? walk_voxels(g, w, coarse, list, A.n, g.H >> 1)
-                          : walk_voxels(g, w, g.coarse, list, A.n, g.H >> 1);
+        nvox = lds_coarse ? walk_voxels<RECHECK>(g, w, coarse, list, A.n, g.H >> 1)
+                          : walk_voxels<RECHECK>(g, w, g.coarse, list, A.n, g.H >> 1);
     }
     if (slot < A.n) A.nvox[slot] = (uint8_t)nvox;
 }
@@ -1078,7 +1078,8 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
 }
 
 // ------------------------------------------------------------------ voxel walk
-template <bool PAIRS>
+// RECHECK: some object of the launch asks for the float64 re-decision of grazing voxels.
+template <bool PAIRS, bool RECHECK>
 __global__ __launch_bounds__(kBlock) void k_walk(QueryArgs A)
 {
     __shared__ uint32_t coarse[kCoarseLdsWords];
@@ -1086,9 +1087,9 @@ __global__ __launch_bounds__(kBlock) void k_walk(QueryArgs A)
         const int o = tile_object(A.pr);
         if (o < 0) return;   // the query kernel skips such a tile too
         const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
-        walk_body<true>(A, O.g, coarse);
+        walk_body<true, RECHECK>(A, O.g, coarse);
     } else {
-        walk_body<false>(A, A.g, coarse);
+        walk_body<false, RECHECK>(A, A.g, coarse);
     }
 }
 

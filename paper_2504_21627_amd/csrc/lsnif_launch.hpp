@@ -20,8 +20,9 @@ hipError_t launch_mma_bf16(const QueryArgs &A, int feat_dtype, int F, int kbm, b
                            hipStream_t s);
 hipError_t launch_mma_fp8(const QueryArgs &A, int feat_dtype, int F, int kbm, bool pairs, uint32_t grid,
                           hipStream_t s);
-// Voxel walk of every slot into A.lists / A.nvox, before the query kernel of the same `grid`.
-hipError_t launch_walk(const QueryArgs &A, bool pairs, uint32_t grid, hipStream_t s);
+// Voxel walk of every slot into A.lists / A.nvox, before the query kernel of the same `grid`;
+// `recheck` when some object of the launch re-decides grazing voxels in float64.
+hipError_t launch_walk(const QueryArgs &A, bool pairs, bool recheck, uint32_t grid, hipStream_t s);
 hipError_t launch_debug(const DebugArgs &D, hipStream_t s);
 struct PairPlan;
 hipError_t launch_pairs_prepare(const PairPlan &P, hipStream_t s);
