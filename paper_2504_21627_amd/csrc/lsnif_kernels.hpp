@@ -200,9 +200,9 @@ __device__ __forceinline__ void level_cell_mm(const Geom &g, int l, const float 
 // boundary point p (voxel units) whose crossing axis is `face`; levels at or
 // beyond L give zeros.  All slots are formed first and all gathers issued
 // before any is consumed.  On a level aligned with the voxel faces the
-// crossing-axis weight is exactly 0 or 1; both of that axis' vertex terms are
-// set to the selected one, so the 4 zero-weight corners re-read the 4 face
-// corners instead of touching other table entries.
+// crossing-axis weight is exactly 0 or 1, and the 4 zero-weight corners do
+// not touch their own entries (the LDS variant re-reads the 4 face corners,
+// the other reads the level's first entry).
 template <typename TF, int F, int NL, bool HOT>
 __device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restrict__ tab, const uint32_t *hot, int l0,
                                               const float p[3], int face, float out[NL][F])
@@ -249,17 +249,6 @@ __device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restric
             const uint32_t my = g.my[l] << sh, mz = g.mz[l] << sh;
             const uint32_t x0 = i[0] << sh;
             uint32_t t[3][2] = {{x0, x0 + (1u << sh)}, {i[1] * my, i[1] * my + my}, {i[2] * mz, i[2] * mz + mz}};
-            if ((g.aligned_mask >> l) & 1u) {
-                // one value for the whole wave: only aligned levels pay for the collapse
-                const float wf = face == 0 ? wt[0] : (face == 1 ? wt[1] : wt[2]);
-                const bool up = wf != 0.0f;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const uint32_t sel = up ? t[a][1] : t[a][0];
-                    t[a][0] = a == face ? sel : t[a][0];
-                    t[a][1] = a == face ? sel : t[a][1];
-                }
-            }
             // vertex slot: x + y + z on a directly indexed level, (x ^ y ^ z) & (T - 1) on a
             // hashed one (y, z already times their multipliers); the level kind is wave-uniform
             constexpr uint32_t m = scaled ? 1u : esz;
@@ -276,6 +265,16 @@ __device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restric
                     off[lv][2 * q + 1] = ((t[0][1] ^ yz) & hm) * m;
                 }
             }
+            if ((g.aligned_mask >> l) & 1u) {
+                // On a face-aligned level the crossing axis' weight is exactly 0 or 1, so the 4
+                // corners on the other side weigh 0.  They read the level's first entry: one
+                // line for every lane, where their own slots would cost the addresser a line
+                // per lane.  Weight 0 times a finite entry adds nothing (the sum is never -0).
+                const float wf = face == 0 ? wt[0] : (face == 1 ? wt[1] : wt[2]);
+                const uint32_t fb = 1u << face, keep = wf != 0.0f ? fb : 0u;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) off[lv][c] = ((uint32_t)c & fb) == keep ? off[lv][c] : 0u;
+            }
         }
         wx[lv][0] = 1.0f - wt[0]; wx[lv][1] = wt[0];
         wy[lv][0] = 1.0f - wt[1]; wy[lv][1] = wt[1];
@@ -285,14 +284,28 @@ __device__ __forceinline__ void encode_levels(const Geom &g, const TF *__restric
         base[lv] = reinterpret_cast<const char *>(tab + ((size_t)l << g.log2_T) * F);
     }
     Entry<TF, F> e[NL][8];
+    typedef uint32_t u32x2a4 __attribute__((ext_vector_type(2), aligned(4)));
 #pragma unroll
-    for (int lv = 0; lv < NL; ++lv)
+    for (int lv = 0; lv < NL; ++lv) {
+        const int l = l0 + lv < g.L ? l0 + lv : g.L - 1;
+        const bool pairx = !HOT && F * sizeof(TF) == 4 && ((g.dense_mask & ~g.aligned_mask) >> l) & 1u;
+        if (pairx) {
+            // directly indexed level: the two x-vertices of an edge are adjacent entries
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            // a hot level is read from its LDS copy (the pointer stays in the LDS address space)
-            if (HOT && in_lds[lv]) e[lv][c].load(reinterpret_cast<const char *>(hot) + hoff[lv], off[lv][c]);
-            else e[lv][c].load(base[lv], off[lv][c]);
+            for (int q = 0; q < 4; ++q) {
+                const u32x2a4 v = *reinterpret_cast<const u32x2a4 *>(base[lv] + off[lv][2 * q]);
+                e[lv][2 * q].d[0] = v.x;
+                e[lv][2 * q + 1].d[0] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                // a hot level is read from its LDS copy (the pointer stays in the LDS address space)
+                if (HOT && in_lds[lv]) e[lv][c].load(reinterpret_cast<const char *>(hot) + hoff[lv], off[lv][c]);
+                else e[lv][c].load(base[lv], off[lv][c]);
+            }
         }
+    }
     // keep every gather of the batch in flight before the first is consumed
     asm volatile("" ::: "memory");
 #pragma unroll
