@@ -274,9 +274,20 @@ def bench_c2(L, args):
         print(f"[bench] timing the {name} path ({tuning}): {args.warmup} warmup + {args.steps} steps",
               file=sys.stderr, flush=True)
         wall, lat, sort_ms, walk_ms, kern_ms = time_path(L, ctx, oid, rays, out, args.steps, args.warmup)
+        iso = tuning
+        if tuning["walk_chunks"] > 1:
+            # with the walk running ahead on a side stream the kernels overlap; the roofline
+            # takes the query kernel alone, from steps that walk the whole batch first
+            iso = dict(tuning, walk_chunks=1)
+            L.lsnif_set_tuning(ctx, oid, *iso.values())
+            print(f"[bench] timing the {name} kernels one after another ({iso})", file=sys.stderr, flush=True)
+            _, _, sort_ms, walk_ms, kern_ms = time_path(L, ctx, oid, rays, out, max(args.steps // 4, 5),
+                                                        args.warmup)
+            L.lsnif_set_tuning(ctx, oid, *tuning.values())
         pts, cand = points_per_launch(L, ctx, oid, rays, out)
         paths[name] = {"wall": wall, "lat": lat, "points": pts, "cand": cand, "sort_ms": sort_ms,
-                       "walk_ms": walk_ms, "kern_ms": kern_ms, "feat_bytes": 2 if feat == "fp16" else 4, "tuning": tuning}
+                       "walk_ms": walk_ms, "kern_ms": kern_ms, "feat_bytes": 2 if feat == "fp16" else 4,
+                       "tuning": tuning, "tuning_isolated": iso}
         L.lsnif_release(ctx, oid)
     L.lsnif_destroy(ctx)
 
@@ -298,6 +309,7 @@ def bench_c2(L, args):
         "p99_ms": float(np.percentile(head["lat"], 99)),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "fp16" if "fp16" in paths else "fp32",
+        "tuning": head["tuning"],
         "data": "synthetic",
         "config": {"workload": "c2: 200k-triangle noise-displaced sphere, V=128, 16 levels x 2^19 "
                                "entries x 2 features, MLP 576-64-64-64-9, 1024x1024 pinhole primary "
@@ -310,7 +322,7 @@ def bench_c2(L, args):
                      "alg_bytes_per_launch": alg_bytes, "points_per_launch": head["points"],
                      "bytes_per_point": bpp, "mean_kernel_ms": mean_ms,
                      "mean_sort_ms": float(head["sort_ms"]), "mean_walk_ms": float(head["walk_ms"]),
-                     "tuning": head["tuning"],
+                     "tuning": head["tuning_isolated"],
                      "mfma_tflops": flops / (mean_ms * 1e-3) / 1e12,
                      "mfma_frac": flops / (mean_ms * 1e-3) / 1e12 / MFMA_FP16_PEAK_TFLOPS},
     }
@@ -338,8 +350,8 @@ def main():
     ap.add_argument("--c5-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="keep the default tuning (no autotuner)")
     ap.add_argument("--tuning", default=None,
-                    help="sort_bits,pair_bits,hot_lds_bytes for the c2 object instead of the autotuner "
-                         "(profiling runs repeat the tuning the autotuner chose)")
+                    help="sort_bits,pair_bits,hot_lds_bytes[,walk_chunks] for the c2 object instead of the "
+                         "autotuner (profiling runs repeat the tuning the autotuner chose)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first copy a device buffer of this size (MiB): the copy of known size "
                          "against which rocprofv3's FETCH_SIZE/WRITE_SIZE counters are scaled")

@@ -229,11 +229,19 @@ lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
  *  hot_lds_bytes  LDS per workgroup for the object's coarsest levels (0..40960):
  *                 those levels, all of whose used entries fit, are copied into
  *                 LDS by every workgroup and gathered from there.
+ *  walk_chunks    tile ranges (1..16) of a direct or captured query: the voxel
+ *                 walk of each range runs on a side stream of the context
+ *                 (default priority) ahead of the query kernel, which starts on
+ *                 range i as soon as its walk is done, so walk and query kernel
+ *                 share the GPU.  1 (the default) walks the whole batch first.
+ *                 Ranges hold at least 256 tiles; the serving loop always walks
+ *                 whole requests.
  * lsnif_autotune times each candidate (sort_bits 0, 4, 5, 6 x hot_lds_bytes 0,
- * 20480, 40960) on the caller's batch, a warm-up and three timed queries each
- * on a private stream, keeps the fastest for the object and returns it.
- * lsnif_autotune_pairs does the same for a pair query (pair_bits 2, 3, 4 x
- * hot_lds_bytes), applying one choice to every object of the context.  Both
+ * 20480, 40960, then walk_chunks 1, 2, 4, 8 for the best of those) on the
+ * caller's batch, a warm-up and three timed queries each on a private stream,
+ * keeps the fastest for the object and returns it.  lsnif_autotune_pairs does
+ * the same for a pair query (pair_bits 2, 3, 4 x hot_lds_bytes, then
+ * walk_chunks), applying one choice to every object of the context.  Both
  * overwrite d_out, synchronise the device and, like lsnif_set_tuning, make the
  * context's captured graphs stale.
  */
@@ -241,6 +249,7 @@ typedef struct {
     int32_t sort_bits;
     int32_t pair_bits;
     int32_t hot_lds_bytes;
+    int32_t walk_chunks;
 } lsnif_tuning;
 
 lsnif_status lsnif_get_tuning(lsnif_ctx *ctx, uint32_t object_id, lsnif_tuning *tuning);
@@ -352,7 +361,9 @@ lsnif_status lsnif_serve_stop(lsnif_ctx *ctx);
  * preparation), before the voxel-walk kernel, before the query kernel and
  * after it.  lsnif_profile_read waits for the recorded queries, returns the
  * summed milliseconds of the three phases and the number of queries since the
- * last read, and forgets them.  Any output pointer may be NULL. */
+ * last read, and forgets them.  Any output pointer may be NULL.  When the walk
+ * runs ahead in ranges (walk_chunks > 1), the walk phase ends once the query
+ * kernel may start on the first range and the query phase holds the rest. */
 lsnif_status lsnif_profile_enable(lsnif_ctx *ctx, int32_t on);
 lsnif_status lsnif_profile_read(lsnif_ctx *ctx, double *sort_ms, double *walk_ms, double *kernel_ms,
                                 uint64_t *launches);

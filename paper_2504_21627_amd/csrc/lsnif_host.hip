@@ -266,6 +266,8 @@ void lsnif_destroy(lsnif_ctx *ctx)
     for (auto &v : ctx->pending)
         for (hipEvent_t e : v) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ctx->order_events) (void)hipEventDestroy(e);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
 }
 
@@ -623,8 +625,54 @@ size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs, uint32
            2 * al256((size_t)n_objs * 4) + list_ws_bytes(n_slots, cap);
 }
 
+// The walk kernel, then the query kernel, over `ntiles` tiles.  With k > 1 tile
+// ranges the walk of every range runs on the context's side stream, in order,
+// and the query kernel of range i waits only for the walk of range i, so the
+// walk of the later ranges (vector-ALU bound) shares the GPU with the query
+// kernel (gather bound).  `ev_mid`, when timing, is recorded once the query
+// kernel may start.
+template <typename Query>
+static lsnif_status walk_then_query(lsnif_ctx *ctx, QueryArgs A, bool pairs, bool recheck, uint32_t ntiles,
+                                    uint32_t chunks, hipStream_t s, hipEvent_t ev_mid, Query &&query)
+{
+    const uint32_t k = std::max(1u, std::min(chunks, ntiles / kMinChunkTiles));
+    if (k == 1) {
+        A.tile0 = 0;
+        HIP_TRY(launch_walk(A, pairs, recheck, ntiles, s));
+        if (ev_mid) HIP_TRY(hipEventRecord(ev_mid, s));
+        HIP_TRY(query(A, ntiles));
+        return LSNIF_OK;
+    }
+    if (!ctx->side && hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) {
+        ctx->side = nullptr;
+        return fail(LSNIF_E_DEVICE, "hipStreamCreateWithFlags failed");
+    }
+    while (ctx->order_events.size() < k + 1) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return fail(LSNIF_E_DEVICE, "hipEventCreateWithFlags failed");
+        ctx->order_events.push_back(e);
+    }
+    hipEvent_t *ev = ctx->order_events.data();
+    auto first = [&](uint32_t i) { return (uint32_t)((uint64_t)ntiles * i / k); };
+    HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(hipStreamWaitEvent(ctx->side, ev[0], 0));
+    for (uint32_t i = 0; i < k; ++i) {
+        A.tile0 = first(i);
+        HIP_TRY(launch_walk(A, pairs, recheck, first(i + 1) - first(i), ctx->side));
+        HIP_TRY(hipEventRecord(ev[i + 1], ctx->side));
+    }
+    for (uint32_t i = 0; i < k; ++i) {
+        HIP_TRY(hipStreamWaitEvent(s, ev[i + 1], 0));
+        if (i == 0 && ev_mid) HIP_TRY(hipEventRecord(ev_mid, s));
+        A.tile0 = first(i);
+        HIP_TRY(query(A, first(i + 1) - first(i)));
+    }
+    return LSNIF_OK;
+}
+
 lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
-                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws)
+                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws, int chunks)
 {
     QueryArgs A{};
     A.g = ob.geom;
@@ -672,13 +720,16 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
     char *wl = static_cast<char *>(ws) + sort_bytes;
     A.nvox = reinterpret_cast<uint8_t *>(wl);
     A.lists = reinterpret_cast<uint32_t *>(wl + al256(n));
-    HIP_TRY(launch_walk(A, false, ob.geom.recheck != 0, grid, s));
-    if (ev[2]) HIP_TRY(hipEventRecord(ev[2], s));
     const int kbm = ob.mlp.kb_point;
-    if (ob.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, ob.feat_dtype, ob.F, false, grid, s));
-    else if (ob.mlp_dtype == LSNIF_FP16) HIP_TRY(launch_mma_f16(A, ob.feat_dtype, ob.F, kbm, false, grid, s));
-    else if (ob.mlp_dtype == LSNIF_BF16) HIP_TRY(launch_mma_bf16(A, ob.feat_dtype, ob.F, kbm, false, grid, s));
-    else HIP_TRY(launch_mma_fp8(A, ob.feat_dtype, ob.F, kbm, false, grid, s));
+    const uint32_t k = dbg ? 1u : (chunks > 0 ? (uint32_t)chunks : ob.walk_chunks);
+    lsnif_status st = walk_then_query(ctx, A, false, ob.geom.recheck != 0, grid, k, s, ev[2],
+                                      [&](const QueryArgs &a, uint32_t g) -> hipError_t {
+        if (ob.mlp_dtype == LSNIF_FP32) return launch_f32(a, ob.feat_dtype, ob.F, false, g, s);
+        if (ob.mlp_dtype == LSNIF_FP16) return launch_mma_f16(a, ob.feat_dtype, ob.F, kbm, false, g, s);
+        if (ob.mlp_dtype == LSNIF_BF16) return launch_mma_bf16(a, ob.feat_dtype, ob.F, kbm, false, g, s);
+        return launch_mma_fp8(a, ob.feat_dtype, ob.F, kbm, false, g, s);
+    });
+    if (st) return st;
     if (ev[3]) {
         HIP_TRY(hipEventRecord(ev[3], s));
         ctx->pending.push_back({ev[0], ev[1], ev[2], ev[3]});
@@ -723,6 +774,7 @@ lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps)
     ps.maxH = 2;
     ps.hot_max = 0;
     ps.recheck = false;
+    ps.walk_chunks = 1;
     for (auto &kv : ctx->objects) {
         if (!same_class(kv.second, *ps.first))
             return fail(LSNIF_E_INVALID, "pair queries need every object of the context in one kernel class "
@@ -731,13 +783,15 @@ lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps)
         ps.maxH = std::max(ps.maxH, kv.second.geom.H);
         ps.hot_max = std::max(ps.hot_max, kv.second.geom.hot_bytes);
         ps.recheck = ps.recheck || kv.second.geom.recheck;
+        ps.walk_chunks = std::max(ps.walk_chunks, kv.second.walk_chunks);
     }
     return upload_table(ctx, ps.n_objs);
 }
 
 lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray *d_rays, uint32_t n_rays,
                            const uint32_t *d_pair_ray, const uint32_t *d_pair_inst, uint32_t n_pairs,
-                           const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out, hipStream_t s, void *ws)
+                           const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out, hipStream_t s, void *ws,
+                           int chunks)
 {
     if (!d_rays || !d_out || (n_pairs && (!d_pair_ray || !d_pair_inst || !d_inst)))
         return fail(LSNIF_E_INVALID, "NULL buffer");
@@ -803,15 +857,16 @@ lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray
         A.pr.res = P.res;
         A.nvox = nvox;
         A.lists = lists;
-        HIP_TRY(launch_walk(A, true, ps.recheck, n_tiles, s));
-        if (ev[2]) HIP_TRY(hipEventRecord(ev[2], s));
         const int kbm = ps.kbm;
-        if (first.mlp_dtype == LSNIF_FP32) HIP_TRY(launch_f32(A, first.feat_dtype, first.F, true, n_tiles, s));
-        else if (first.mlp_dtype == LSNIF_FP16)
-            HIP_TRY(launch_mma_f16(A, first.feat_dtype, first.F, kbm, true, n_tiles, s));
-        else if (first.mlp_dtype == LSNIF_BF16)
-            HIP_TRY(launch_mma_bf16(A, first.feat_dtype, first.F, kbm, true, n_tiles, s));
-        else HIP_TRY(launch_mma_fp8(A, first.feat_dtype, first.F, kbm, true, n_tiles, s));
+        const uint32_t k = chunks > 0 ? (uint32_t)chunks : ps.walk_chunks;
+        lsnif_status st = walk_then_query(ctx, A, true, ps.recheck, n_tiles, k, s, ev[2],
+                                          [&](const QueryArgs &a, uint32_t g) -> hipError_t {
+            if (first.mlp_dtype == LSNIF_FP32) return launch_f32(a, first.feat_dtype, first.F, true, g, s);
+            if (first.mlp_dtype == LSNIF_FP16) return launch_mma_f16(a, first.feat_dtype, first.F, kbm, true, g, s);
+            if (first.mlp_dtype == LSNIF_BF16) return launch_mma_bf16(a, first.feat_dtype, first.F, kbm, true, g, s);
+            return launch_mma_fp8(a, first.feat_dtype, first.F, kbm, true, g, s);
+        });
+        if (st) return st;
     }
     if (ev[3]) {
         if (!n_pairs) HIP_TRY(hipEventRecord(ev[2], s));

@@ -26,6 +26,11 @@ lsnif_status fail(lsnif_status st, const char *fmt, ...);
             return ::lsnif::fail(LSNIF_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+// Default tile ranges of a query whose walk runs ahead of the query kernel (1:
+// the walk of the whole batch first), and the fewest tiles a range may hold.
+constexpr uint32_t kWalkChunks = 1;
+constexpr uint32_t kMinChunkTiles = 256;
+
 struct Object {
     Geom geom{};
     Mlp mlp{};
@@ -33,6 +38,7 @@ struct Object {
     int feat_dtype = 0, mlp_dtype = 0, F = 0, width = 0;
     uint32_t esz = 0;             // bytes of one table entry on the device
     uint32_t hot_budget = kHotLdsBudget;   // LDS budget the hot levels were planned for
+    uint32_t walk_chunks = kWalkChunks;    // tile ranges of a query whose walk runs ahead
     uint64_t bytes = 0;
 };
 
@@ -90,6 +96,10 @@ struct lsnif_ctx {
     bool profiling = false;
     std::vector<std::vector<hipEvent_t>> pending;
     std::vector<hipEvent_t> spare;
+    // walk of the next tile range while the query kernel works on the current one: a side
+    // stream (default priority) and the events that order the two
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> order_events;
     // serving loop, when started; `mu` orders the direct calls against it
     lsnif::Server *server = nullptr;
     std::recursive_mutex mu;
@@ -103,6 +113,7 @@ struct PairsSetup {
     int kbm = 1, maxH = 2;
     uint32_t hot_max = 0;   // largest hot-level LDS footprint of the objects
     bool recheck = false;   // some object re-decides grazing voxels in float64
+    uint32_t walk_chunks = 1;   // largest walk_chunks of the objects
     uint32_t n_objs = 0;
 };
 lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps);
@@ -116,10 +127,13 @@ lsnif_status check_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_
 
 // Enqueue one query on `s`.  `ws` must hold query_ws_bytes(n) (pairs_ws_bytes for
 // pairs) bytes and stay untouched until the stream has run the query.
+// `chunks`: tile ranges whose walk runs ahead of the query kernel on the side stream
+// (<= 0: the object's tuning; 1: the walk of the whole batch first).
 lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
-                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws);
+                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws, int chunks = 0);
 lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray *d_rays, uint32_t n_rays,
                            const uint32_t *d_pair_ray, const uint32_t *d_pair_inst, uint32_t n_pairs,
-                           const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out, hipStream_t s, void *ws);
+                           const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out, hipStream_t s, void *ws,
+                           int chunks = 0);
 
 }  // namespace lsnif

@@ -85,6 +85,7 @@ struct QueryArgs {
     const uint32_t *order;    // processing order of the rays (coherence sort), or NULL
     uint32_t *lists;          // voxel lists by slot: entry j of slot i at lists[j n + i]
     uint8_t *nvox;            // listed voxels of each slot
+    uint32_t tile0;           // first tile of the launch (a launch may cover a range of the tiles)
     Dbg dbg;
     PairArgs pr;
     uint32_t hot_lds;         // dynamic LDS bytes after the voxel lists for hot levels
@@ -487,18 +488,18 @@ struct Lane {
 // C consecutive tiles go to one XCD, so the rays an XCD has in flight lie in
 // fewer regions of the object and share more of its L2; short runs keep the
 // work of the XCDs even where the cost per tile drifts along the order.  Any
-// grid size maps one to one (the last partial round keeps b itself).
-__device__ __forceinline__ uint32_t block_tile()
+// grid size maps one to one (the last partial round keeps b itself).  A launch
+// covers tiles tile0 .. tile0 + gridDim.x - 1.
+__device__ __forceinline__ uint32_t block_tile(uint32_t tile0)
 {
     constexpr uint32_t C = 8;
     const uint32_t b = blockIdx.x, nb = gridDim.x;
     const uint32_t full = nb / (8u * C) * (8u * C);
-    if (b >= full) return b;
+    if (b >= full) return tile0 + b;
     const uint32_t x = b & 7u, k = b >> 3;
-    return ((k / C) * 8u + x) * C + k % C;
+    return tile0 + ((k / C) * 8u + x) * C + k % C;
 }
 
-// Ray (or pair) of slot `slot` and its object-space segment.
 template <bool PAIRS>
 __device__ __forceinline__ void slot_ray(const QueryArgs &A, const Geom &g, uint32_t slot, uint32_t &r,
                                          uint32_t &pair, bool &live, VRay &w)
@@ -536,7 +537,7 @@ __device__ __forceinline__ void walk_body(const QueryArgs &A, const Geom &g, uin
     if (lds_coarse)
         for (int i = tid; i < g.coarse_words; i += kBlock) coarse[i] = g.coarse[i];
     __syncthreads();
-    const uint32_t slot = block_tile() * kBlock + tid;
+    const uint32_t slot = block_tile(A.tile0) * kBlock + tid;
     uint32_t r, pair;
     bool live;
     VRay w;
@@ -558,7 +559,7 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g,
     const int cap = g.H >> 1;
     if (tid <= (uint32_t)cap) S.hist[tid] = 0;
     __syncthreads();
-    const uint32_t slot0 = block_tile() * kBlock + tid;
+    const uint32_t slot0 = block_tile(A.tile0) * kBlock + tid;
     uint32_t r0, pair0;
     bool live0;
     VRay w;
@@ -619,7 +620,7 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g,
     L.src = src;
     L.r = __float_as_uint(st[13 * kBlock + src]);
     L.pair = __float_as_uint(st[14 * kBlock + src]);
-    L.live = PAIRS ? L.pair != 0xffffffffu : block_tile() * kBlock + src < A.n;
+    L.live = PAIRS ? L.pair != 0xffffffffu : block_tile(A.tile0) * kBlock + src < A.n;
 }
 
 // ---------------------------------------------------------------- float32 path
@@ -629,10 +630,10 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g,
 // contiguous and every lane reads the same address.
 // Object of this block's tile: one value for the whole block, read through the
 // scalar path so that everything derived from it (tables, weights) stays uniform.
-__device__ __forceinline__ int tile_object(const PairArgs &P)
+__device__ __forceinline__ int tile_object(const PairArgs &P, uint32_t tile0)
 {
     typedef const __attribute__((address_space(4))) int32_t cint;
-    return __builtin_amdgcn_readfirstlane(((cint *)P.tile_obj)[block_tile()]);
+    return __builtin_amdgcn_readfirstlane(((cint *)P.tile_obj)[block_tile(tile0)]);
 }
 // The object table, read through the constant address space in the device pass (the
 // host pass only type-checks kernel bodies and has no such address space).
@@ -747,7 +748,7 @@ __global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
     extern __shared__ uint32_t s_list[];
     __shared__ Shared S;
     if constexpr (PAIRS) {
-        const int o = tile_object(A.pr);
+        const int o = tile_object(A.pr, A.tile0);
         if (o < 0) return;
         const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
         query_f32_body<TF, F, WIDTH, true, HOT>(A, O.g, O.m, (const TF *)O.tables, s_list, S);
@@ -1080,7 +1081,7 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
     extern __shared__ uint32_t s_list[];
     __shared__ Shared S;
     if constexpr (PAIRS) {
-        const int o = tile_object(A.pr);
+        const int o = tile_object(A.pr, A.tile0);
         if (o < 0) return;
         const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
         query_mma_body<TF, TM, F, WIDTH, KBM, true, HOT>(A, O.g, O.m, (const TF *)O.tables, s_list, S);
@@ -1097,7 +1098,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(QueryArgs A)
 {
     __shared__ uint32_t coarse[kCoarseLdsWords];
     if constexpr (PAIRS) {
-        const int o = tile_object(A.pr);
+        const int o = tile_object(A.pr, A.tile0);
         if (o < 0) return;   // the query kernel skips such a tile too
         const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
         walk_body<true, RECHECK>(A, O.g, coarse);

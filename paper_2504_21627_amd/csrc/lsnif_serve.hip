@@ -306,12 +306,12 @@ private:
                 st = pairs_setup(ctx_, ps);
                 if (!st)
                     st = enqueue_pairs(ctx_, ps, q.r.d_rays, q.r.n_rays, q.r.d_pair_ray, q.r.d_pair_inst, q.r.n_pairs,
-                                       q.r.d_inst, q.r.n_inst, q.r.d_out, s, ws);
+                                       q.r.d_inst, q.r.n_inst, q.r.d_out, s, ws, 1);   // streams overlap requests
             } else {
                 auto it = ctx_->objects.find(q.r.object_id);
                 st = it == ctx_->objects.end()
                          ? fail(LSNIF_E_NOTFOUND, "no object %u", q.r.object_id)
-                         : enqueue_query(ctx_, it->second, q.r.d_rays, q.r.n_rays, q.r.d_out, nullptr, s, ws);
+                         : enqueue_query(ctx_, it->second, q.r.d_rays, q.r.n_rays, q.r.d_out, nullptr, s, ws, 1);
             }
         }
         if (st) return st;

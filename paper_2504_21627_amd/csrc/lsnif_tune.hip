@@ -24,6 +24,7 @@ lsnif_status check_tuning(const lsnif_tuning *t)
     if (t->pair_bits < 1 || t->pair_bits > 4) return fail(LSNIF_E_INVALID, "pair_bits must be 1..4");
     if (t->hot_lds_bytes < 0 || t->hot_lds_bytes > (int32_t)kHotLdsBudget)
         return fail(LSNIF_E_INVALID, "hot_lds_bytes must be 0..%u", kHotLdsBudget);
+    if (t->walk_chunks < 1 || t->walk_chunks > 16) return fail(LSNIF_E_INVALID, "walk_chunks must be 1..16");
     return LSNIF_OK;
 }
 
@@ -32,6 +33,7 @@ void apply(lsnif_ctx *ctx, Object &ob, const lsnif_tuning &t)
     ob.geom.sort_bits = (uint32_t)t.sort_bits;
     ob.geom.pair_bits = (uint32_t)t.pair_bits;
     ob.hot_budget = (uint32_t)t.hot_lds_bytes;
+    ob.walk_chunks = (uint32_t)t.walk_chunks;
     plan_hot_levels(ob.geom, ob.esz, ob.hot_budget);
     ctx->table_dirty = true;
     ++ctx->generation;
@@ -39,7 +41,8 @@ void apply(lsnif_ctx *ctx, Object &ob, const lsnif_tuning &t)
 
 lsnif_tuning current(const Object &ob)
 {
-    return lsnif_tuning{(int32_t)ob.geom.sort_bits, (int32_t)ob.geom.pair_bits, (int32_t)ob.hot_budget};
+    return lsnif_tuning{(int32_t)ob.geom.sort_bits, (int32_t)ob.geom.pair_bits, (int32_t)ob.hot_budget,
+                        (int32_t)ob.walk_chunks};
 }
 
 // Milliseconds per call of `enqueue(stream)`, averaged over kTimedReps after a warm-up.
@@ -78,6 +81,7 @@ template <typename Fn> lsnif_status with_stream(Fn &&fn)
 }
 
 const int32_t kHotCandidates[] = {0, 20 << 10, 40 << 10};
+const int32_t kChunkCandidates[] = {1, 2, 4, 8};
 
 }  // namespace
 
@@ -127,20 +131,26 @@ lsnif_status lsnif_autotune(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray 
     lsnif_tuning win = start;
     float win_ms = -1.0f;
     st = with_stream([&](hipStream_t s, hipEvent_t e0, hipEvent_t e1) -> lsnif_status {
-        for (int sb : {0, 4, 5, 6})
-            for (int32_t hot : kHotCandidates) {
-                const lsnif_tuning t{sb, start.pair_bits, hot};
-                apply(ctx, ob, t);
-                float ms = 0.0f;
-                lsnif_status e = time_ms(
-                    [&](hipStream_t q) { return enqueue_query(ctx, ob, d_rays, n, d_out, nullptr, q, ctx->ws); }, s,
-                    e0, e1, ms);
-                if (e) return e;
-                if (win_ms < 0.0f || ms < win_ms) {
-                    win_ms = ms;
-                    win = t;
-                }
+        auto run = [&](const lsnif_tuning &t) -> lsnif_status {
+            apply(ctx, ob, t);
+            float ms = 0.0f;
+            lsnif_status e = time_ms(
+                [&](hipStream_t q) { return enqueue_query(ctx, ob, d_rays, n, d_out, nullptr, q, ctx->ws); }, s, e0,
+                e1, ms);
+            if (e) return e;
+            if (win_ms < 0.0f || ms < win_ms) {
+                win_ms = ms;
+                win = t;
             }
+            return LSNIF_OK;
+        };
+        for (int sb : {0, 4, 5, 6})
+            for (int32_t hot : kHotCandidates)
+                if (lsnif_status e = run(lsnif_tuning{sb, start.pair_bits, hot, start.walk_chunks})) return e;
+        const lsnif_tuning best = win;
+        for (int32_t ch : kChunkCandidates)
+            if (ch != best.walk_chunks)
+                if (lsnif_status e = run(lsnif_tuning{best.sort_bits, best.pair_bits, best.hot_lds_bytes, ch})) return e;
         return LSNIF_OK;
     });
     apply(ctx, ob, st ? start : win);
@@ -165,33 +175,42 @@ lsnif_status lsnif_autotune_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint3
     for (auto &kv : ctx->objects) start.push_back({kv.first, current(kv.second)});
     auto apply_all = [&](const lsnif_tuning &t) {
         for (auto &kv : ctx->objects)
-            apply(ctx, kv.second, lsnif_tuning{(int32_t)kv.second.geom.sort_bits, t.pair_bits, t.hot_lds_bytes});
+            apply(ctx, kv.second,
+                  lsnif_tuning{(int32_t)kv.second.geom.sort_bits, t.pair_bits, t.hot_lds_bytes, t.walk_chunks});
     };
     lsnif_tuning win{};
     float win_ms = -1.0f;
+    const uint32_t start_chunks = ctx->objects.begin()->second.walk_chunks;
     lsnif_status st = with_stream([&](hipStream_t s, hipEvent_t e0, hipEvent_t e1) -> lsnif_status {
-        for (int pb : {2, 3, 4})
-            for (int32_t hot : kHotCandidates) {
-                const lsnif_tuning t{0, pb, hot};
-                apply_all(t);
-                PairsSetup ps;
-                lsnif_status e = pairs_setup(ctx, ps);   // uploads the changed object table
-                if (e) return e;
-                if ((e = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs, ps.maxH >> 1))))
-                    return e;
-                float ms = 0.0f;
-                e = time_ms(
-                    [&](hipStream_t q) {
-                        return enqueue_pairs(ctx, ps, d_rays, n_rays, d_pair_ray, d_pair_inst, n_pairs, d_inst, n_inst,
-                                             d_out, q, ctx->pws);
-                    },
-                    s, e0, e1, ms);
-                if (e) return e;
-                if (win_ms < 0.0f || ms < win_ms) {
-                    win_ms = ms;
-                    win = t;
-                }
+        auto run = [&](const lsnif_tuning &t) -> lsnif_status {
+            apply_all(t);
+            PairsSetup ps;
+            lsnif_status e = pairs_setup(ctx, ps);   // uploads the changed object table
+            if (e) return e;
+            if ((e = grow_workspace(ctx->pws, ctx->pws_bytes,
+                                    pairs_ws_bytes(n_rays, n_pairs, ps.n_objs, ps.maxH >> 1))))
+                return e;
+            float ms = 0.0f;
+            e = time_ms(
+                [&](hipStream_t q) {
+                    return enqueue_pairs(ctx, ps, d_rays, n_rays, d_pair_ray, d_pair_inst, n_pairs, d_inst, n_inst,
+                                         d_out, q, ctx->pws);
+                },
+                s, e0, e1, ms);
+            if (e) return e;
+            if (win_ms < 0.0f || ms < win_ms) {
+                win_ms = ms;
+                win = t;
             }
+            return LSNIF_OK;
+        };
+        for (int pb : {2, 3, 4})
+            for (int32_t hot : kHotCandidates)
+                if (lsnif_status e = run(lsnif_tuning{0, pb, hot, (int32_t)start_chunks})) return e;
+        const lsnif_tuning best = win;
+        for (int32_t ch : kChunkCandidates)
+            if (ch != best.walk_chunks)
+                if (lsnif_status e = run(lsnif_tuning{0, best.pair_bits, best.hot_lds_bytes, ch})) return e;
         return LSNIF_OK;
     });
     if (st) {

@@ -46,7 +46,8 @@ class lsnif_object_desc(C.Structure):
 
 
 class lsnif_tuning(C.Structure):
-    _fields_ = [("sort_bits", C.c_int32), ("pair_bits", C.c_int32), ("hot_lds_bytes", C.c_int32)]
+    _fields_ = [("sort_bits", C.c_int32), ("pair_bits", C.c_int32), ("hot_lds_bytes", C.c_int32),
+                ("walk_chunks", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -272,8 +273,8 @@ def lsnif_get_tuning(ctx, object_id):
     return t.as_dict()
 
 
-def lsnif_set_tuning(ctx, object_id, sort_bits, pair_bits, hot_lds_bytes):
-    t = lsnif_tuning(sort_bits, pair_bits, hot_lds_bytes)
+def lsnif_set_tuning(ctx, object_id, sort_bits, pair_bits, hot_lds_bytes, walk_chunks=1):
+    t = lsnif_tuning(sort_bits, pair_bits, hot_lds_bytes, walk_chunks)
     _check(load().lsnif_set_tuning(ctx, object_id, C.byref(t)))
 
 

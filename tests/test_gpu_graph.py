@@ -28,10 +28,13 @@ def bits(t):
 def test_graph_query_replays(L):
     import torch
     obj = W.configs.c2_object()
-    rays_np = W.configs.subsample(W.configs.c2_rays(), 40000, seed=3)   # above the sort threshold
+    # above the sort threshold, and 782 tiles: with walk_chunks 4, 3 walk ranges of at least 256
+    # tiles run ahead on the context's side stream, and the capture records that fork and join
+    rays_np = W.configs.subsample(W.configs.c2_rays(), 200000, seed=3)
     ctx = L.lsnif_create(0)
     try:
         oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp16", "fp16"))
+        L.lsnif_set_tuning(ctx, oid, 5, 4, 0, 4)
         rays = torch.from_numpy(rays_np).cuda()
         ref = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
         L.lsnif_query(ctx, oid, rays, ref)
@@ -62,6 +65,8 @@ def test_graph_pairs_replays_and_goes_stale(L):
     ctx = L.lsnif_create(0)
     try:
         ids = [L.lsnif_build(ctx, L.ObjectDesc(o, "fp16", "fp16")) for o in objs]
+        for i in ids:
+            L.lsnif_set_tuning(ctx, i, 5, 4, 0, 4)   # the walk runs ahead in 4 ranges
         eye = np.concatenate([np.eye(3), np.zeros((3, 1))], 1).astype(np.float32)
         inst = torch.from_numpy(L.instances_array([(i, eye) for i in ids])).cuda()
         rays = torch.from_numpy(rays_np).cuda()

@@ -23,33 +23,38 @@ def bits(t):
 def test_single_object_tunings_agree(L):
     import torch
     obj = W.configs.c2_object()
-    rays_np = W.configs.subsample(W.configs.c2_rays(), 60000, seed=8)
+    # 300,000 rays = 1,172 tiles: up to 4 walk ranges of at least 256 tiles each
+    rays_np = W.configs.subsample(W.configs.c2_rays(), 300000, seed=8)
     ctx = L.lsnif_create(0)
     try:
         rays = torch.from_numpy(rays_np).cuda()
         for feat, mlp in (("fp16", "fp16"), ("fp32", "fp32")):
             oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
             ref = None
-            for sb, hot in ((5, 40960), (0, 0), (3, 20480), (4, 0), (6, 0)):
-                L.lsnif_set_tuning(ctx, oid, sb, 4, hot)
-                assert L.lsnif_get_tuning(ctx, oid) == {"sort_bits": sb, "pair_bits": 4, "hot_lds_bytes": hot}
+            for sb, hot, ch in ((5, 40960, 1), (0, 0, 4), (3, 20480, 2), (4, 0, 16), (6, 0, 3)):
+                L.lsnif_set_tuning(ctx, oid, sb, 4, hot, ch)
+                assert L.lsnif_get_tuning(ctx, oid) == {"sort_bits": sb, "pair_bits": 4, "hot_lds_bytes": hot,
+                                                        "walk_chunks": ch}
                 out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
                 L.lsnif_query(ctx, oid, rays, out)
                 torch.cuda.synchronize()
                 if ref is None:
                     ref = bits(out)
                 else:
-                    assert np.array_equal(bits(out), ref), (feat, sb, hot)
+                    assert np.array_equal(bits(out), ref), (feat, sb, hot, ch)
             out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
             best = L.lsnif_autotune(ctx, oid, rays, out)
             print(feat, "autotuned", best, flush=True)
             assert best["sort_bits"] in (0, 4, 5, 6) and best["hot_lds_bytes"] in (0, 20480, 40960)
+            assert best["walk_chunks"] in (1, 2, 4, 8)
             assert L.lsnif_get_tuning(ctx, oid) == best
             L.lsnif_query(ctx, oid, rays, out)
             torch.cuda.synchronize()
             assert np.array_equal(bits(out), ref)
             with pytest.raises(L.LsnifError):
                 L.lsnif_set_tuning(ctx, oid, 7, 4, 0)
+            with pytest.raises(L.LsnifError):
+                L.lsnif_set_tuning(ctx, oid, 5, 4, 0, 17)
             L.lsnif_release(ctx, oid)
     finally:
         L.lsnif_destroy(ctx)
@@ -68,9 +73,9 @@ def test_pair_tunings_agree(L):
         pr = torch.arange(len(rays_np), dtype=torch.int32, device="cuda")
         pi = torch.from_numpy(owner.astype(np.int32)).cuda()
         ref = None
-        for pb, hot in ((4, 40960), (2, 0), (3, 20480)):
+        for pb, hot, ch in ((4, 40960, 1), (2, 0, 4), (3, 20480, 16)):
             for i in ids:
-                L.lsnif_set_tuning(ctx, i, 5, pb, hot)
+                L.lsnif_set_tuning(ctx, i, 5, pb, hot, ch)
             out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
             L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out)
             torch.cuda.synchronize()
@@ -78,11 +83,11 @@ def test_pair_tunings_agree(L):
                 ref = bits(out)
                 assert (ref[:, 0] == 1).sum() > 100
             else:
-                assert np.array_equal(bits(out), ref), (pb, hot)
+                assert np.array_equal(bits(out), ref), (pb, hot, ch)
         out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
         best = L.lsnif_autotune_pairs(ctx, rays, pr, pi, inst, out)
         print("pairs autotuned", best, flush=True)
-        assert best["pair_bits"] in (2, 3, 4)
+        assert best["pair_bits"] in (2, 3, 4) and best["walk_chunks"] in (1, 2, 4, 8)
         L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out)
         torch.cuda.synchronize()
         assert np.array_equal(bits(out), ref)
