@@ -251,6 +251,39 @@ def bench_c5(L, n_requests, seed=7):
     }
 
 
+def bench_p1(L, steps, warmup, tune):
+    """The paper's default object shape (width-128 leaky-ReLU MLP, albedo head, F = 3, two
+    face-aligned levels) and its low-quality variant (width 64, H = 10), FP16 features and
+    MLP, 1M rays from the enclosing sphere."""
+    import torch
+    import workloads as W
+    rays_np = W.configs.p1_rays()
+    n = len(rays_np)
+    rays = torch.from_numpy(rays_np).cuda()
+    out = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+    res = {"workload": "p1: c1's icosphere as the paper's default object shape (V=32, levels R=64,128 "
+                       "face-aligned, 2^17 entries x 3 fp16 features, H=18, MLP 108-128-128-12 leaky ReLU, "
+                       "albedo head, 4 materials) and its low-quality variant (width 64, H=10); 1,048,576 "
+                       "rays from the enclosing sphere", "rays": n}
+    ctx = L.lsnif_create(0)
+    try:
+        for name, width, H in (("default", 128, 18), ("low_quality", 64, 10)):
+            obj = W.configs.paper_object(width=width, H=H)
+            oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp16", "fp16"))
+            tuning = L.lsnif_autotune(ctx, oid, rays, out) if tune else L.lsnif_get_tuning(ctx, oid)
+            print(f"[bench] timing p1 {name} ({tuning}): {warmup} warmup + {steps} steps", file=sys.stderr,
+                  flush=True)
+            wall, lat, sort_ms, walk_ms, kern_ms = time_path(L, ctx, oid, rays, out, steps, warmup)
+            res[name] = {"width": width, "H": H, "value": n / (wall / steps) / 1e6, "unit": "Mrays/s",
+                         "ms_per_step": wall * 1e3 / steps, "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)), "sort_ms": sort_ms, "walk_ms": walk_ms,
+                         "kernel_ms": kern_ms, "tuning": tuning}
+            L.lsnif_release(ctx, oid)
+    finally:
+        L.lsnif_destroy(ctx)
+    return res
+
+
 def bench_c2(L, args):
     """The headline: the c2 batch through the FP16 matrix-core path and the plain FP32 path."""
     import torch
@@ -345,8 +378,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--only", choices=["fp16", "fp32"], default=None,
                     help="time one path only (for profiling)")
-    ap.add_argument("--legs", default="c2,c4,c5",
-                    help="comma list: c2 (headline), c4 (batched objects), c5 (serving)")
+    ap.add_argument("--legs", default="c2,c4,c5,p1",
+                    help="comma list: c2 (headline), c4 (batched objects), c5 (serving), "
+                         "p1 (the paper's default object shape)")
     ap.add_argument("--c5-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="keep the default tuning (no autotuner)")
     ap.add_argument("--tuning", default=None,
@@ -381,6 +415,8 @@ def main():
         rec["batched_c4"] = bench_c4(L, max(args.steps // 10, 5), min(args.warmup, 3), not args.no_tune)
     if "c5" in legs:
         rec["serving_c5"] = bench_c5(L, args.c5_requests)
+    if "p1" in legs:
+        rec["paper_default_p1"] = bench_p1(L, max(args.steps // 4, 5), min(args.warmup, 3), not args.no_tune)
     if not args.no_cpu and "c2" in legs:
         print("[bench] timing the oracle on a CPU sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(obj, rays_np, args.cpu_sample)

@@ -8,7 +8,15 @@ template <typename TF, int F, int KBM>
 static void go(const QueryArgs &A, bool pairs, uint32_t grid, hipStream_t s)
 {
     // voxel lists of H/2 entries per lane (for pairs, H is the largest over the objects)
-    const size_t lds = (size_t)(A.g.H >> 1) * kBlock * sizeof(uint32_t) + A.hot_lds;
+    const size_t lists = (size_t)(A.g.H >> 1) * kBlock * sizeof(uint32_t);
+    if constexpr (KBM <= 2) {
+        if (A.width == 128) {   // the paper's default width: no hot-level variant (hot levels change no result)
+            if (pairs) hipLaunchKernelGGL((k_query_mma<TF, fp8e4m3, F, 128, KBM, true, false>), dim3(grid), dim3(kBlock), lists, s, A);
+            else hipLaunchKernelGGL((k_query_mma<TF, fp8e4m3, F, 128, KBM, false, false>), dim3(grid), dim3(kBlock), lists, s, A);
+            return;
+        }
+    }
+    const size_t lds = lists + A.hot_lds;
     // objects with hot levels take the variant that reads them from LDS
     if constexpr (hot_entries<TF, F>()) {
         if (A.hot_lds) {

@@ -123,7 +123,15 @@ lsnif_status validate(const lsnif_object_desc *d)
 lsnif_status supported(const lsnif_object_desc *d)
 {
     if (d->F != 2 && d->F != 3) return fail(LSNIF_E_INVALID, "kernels support F = 2 or 3 (got %d)", d->F);
-    if (d->width != 64) return fail(LSNIF_E_INVALID, "kernels support width 64 (got %d)", d->width);
+    if (d->width != 64 && d->width != 128)
+        return fail(LSNIF_E_INVALID, "kernels support width 64 or 128 (got %d)", d->width);
+    if (d->width == 128 && d->mlp_dtype != LSNIF_FP32) {
+        // the matrix-core kernels of width 128 hold at most 2 K blocks (32 inputs) per point
+        const int fp = d->F == 3 ? 4 : d->F;
+        if (d->L * fp > 32)
+            return fail(LSNIF_E_INVALID, "width 128 on matrix cores needs L x %d <= 32 inputs per point (L = %d)",
+                        fp, d->L);
+    }
     // the gathers address a level with 32-bit byte offsets
     const uint64_t level_bytes = ((uint64_t)1 << d->log2_T) * d->F * dtype_size(d->feat_dtype);
     if (level_bytes > ((uint64_t)1 << 32))
@@ -677,6 +685,7 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
     QueryArgs A{};
     A.g = ob.geom;
     A.hot_lds = ob.geom.hot_bytes;
+    A.width = (uint32_t)ob.width;
     A.m = ob.mlp;
     A.tables = ob.d_tab;
     A.rays = reinterpret_cast<const float4 *>(d_rays);
@@ -845,6 +854,7 @@ lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray
         QueryArgs A{};
         A.g.H = ps.maxH;
         A.hot_lds = ps.hot_max;   // every object's hot levels fit
+        A.width = (uint32_t)first.width;   // one kernel class: every object has this width
         A.rays = P.rays;
         A.n = n_slots;
         A.pr.pair_ray = d_pair_ray;

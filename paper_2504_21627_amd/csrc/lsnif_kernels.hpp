@@ -86,6 +86,7 @@ struct QueryArgs {
     uint32_t *lists;          // voxel lists by slot: entry j of slot i at lists[j n + i]
     uint8_t *nvox;            // listed voxels of each slot
     uint32_t tile0;           // first tile of the launch (a launch may cover a range of the tiles)
+    uint32_t width;           // hidden width of the launch's objects (64 or 128), picks the kernel
     Dbg dbg;
     PairArgs pr;
     uint32_t hot_lds;         // dynamic LDS bytes after the voxel lists for hot levels

@@ -70,6 +70,15 @@ def test_footprint_matches_paper(L):
     assert abs(b / 2 ** 20 - 1.56) < 0.01
 
 
+def test_paper_object_workload_footprint(L):
+    """The p1 workload object has the paper's default shape, hence its 1.56 MB (Sec. 5.1);
+    the low-quality variant (width 64, H = 10) is smaller only in its network."""
+    b = L.lsnif_desc_bytes(L.ObjectDesc(W.configs.paper_object(), "fp16", "fp16"))
+    assert b == 4 * 1024 + 1536 * 1024 + 62 * 1024
+    lq = L.lsnif_desc_bytes(L.ObjectDesc(W.configs.paper_object(width=64, H=10), "fp16", "fp16"))
+    assert lq == 4 * 1024 + 1536 * 1024 + 2 * (60 * 64 + 64 * 64 + 64 * 12)
+
+
 @pytest.mark.parametrize("M,kb", [(2 ** 8, 3), (2 ** 11, 24), (2 ** 14, 192), (2 ** 17, 1536)])
 def test_grid_bytes_vs_hash_map_size(L, M, kb):
     """Grid bytes for the hash-map sizes of the paper's parameter study (2 levels x 3 FP16)."""

@@ -4,6 +4,10 @@
 * ``c2``: 200k-triangle noise-displaced sphere at V = 128, 16 levels of 2**19
   entries, 1024 x 1024 pinhole primary rays plus 1M shadow rays.
 * ``c3``: c2's object and weights, 4M cosine-distributed bounce rays.
+* ``p1``: the paper's default object shape (Sec. 5.1) on c1's icosphere: V = 32,
+  two face-aligned levels (R = 64, 128) of 2**17 entries x 3 features, a
+  2 x 128 leaky-ReLU MLP with the albedo head and 4 materials, H = 18; and its
+  low-quality variant (width 64, H = 10); 1M rays from the enclosing sphere.
 
 The paper's own scenes are not available; these procedural objects and ray
 distributions stand in for them (primary, shadow and diffuse-bounce rays,
@@ -16,7 +20,7 @@ import os
 import numpy as np
 
 from .meshes import icosphere, displaced_sphere
-from .objects import make_object, level_resolutions
+from .objects import make_object, level_resolutions, LEAKY_RELU
 from .rays import sphere_to_box_rays, pinhole_rays, shadow_rays, diffuse_rays
 from .rng import streams, RAYS, GEOMETRY
 from .voxelize import voxelize
@@ -54,6 +58,20 @@ def c1(seed=0, n_rays=4096):
     obj = c1_object(seed)
     rays = sphere_to_box_rays(streams(seed)[RAYS], n_rays)
     return {"name": "c1", "objects": [obj], "rays": rays}
+
+
+def paper_object(seed=0, width=128, H=18):
+    """The paper's default object shape (width 128, H = 18) or its low-quality variant
+    (width 64, H = 10), with seeded features and weights on c1's icosphere."""
+    verts, tris = icosphere(3)
+    return make_object(verts, tris, V=32, bmin=[-1.1] * 3, bmax=[1.1] * 3, L=2, F=3, log2_T=17,
+                       R=[64, 128], H=H, n_hidden=2, width=width, n_mat=4, has_albedo=1,
+                       act=LEAKY_RELU, leaky_slope=0.01, seed=seed,
+                       name=f"p1-icosphere-w{width}-h{H}")
+
+
+def p1_rays(seed=0, n_rays=1 << 20):
+    return sphere_to_box_rays(streams(seed)[RAYS], n_rays)
 
 
 def c2_mesh(seed=1):
