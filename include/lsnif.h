@@ -213,6 +213,36 @@ lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
                                const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out,
                                void *stream);
 
+/* Broad phase (Sec. 4, the step that lists which instances a ray may hit).
+ * Pair (r, i) is listed when ray r, mapped into instance i's object space as
+ * the pair query maps it, meets the object's voxel grid on [max(ta, tmin), tb]
+ * with positive length (the slab test the pair query's narrow phase starts
+ * with) and that segment starts no later than tmax (a hit's t lies in
+ * [ta, tb] and must not exceed tmax), so every pair that can hit is listed.
+ * Pairs come sorted by ray, then instance index; instances naming no built
+ * object give none.
+ *
+ *  d_rays / d_inst  as for lsnif_query_pairs (device pointers).
+ *  d_pair_ray, d_pair_inst  device buffers of `cap` entries each.
+ *  n_pairs          host: receives the number of pairs.
+ *
+ * The pairs are counted on `stream`, which the call then synchronises once to
+ * read the count; the writing pass is enqueued after it and returns without
+ * waiting.  If the count exceeds cap, nothing is written and LSNIF_E_NOMEM is
+ * returned with *n_pairs set.  n_rays x n_inst must be below 2^32 (else
+ * LSNIF_E_INVALID).  Uses a workspace of the context (4 bytes per ray). */
+lsnif_status lsnif_broad_phase(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t n_rays,
+                               const lsnif_instance *d_inst, uint32_t n_inst, uint32_t *d_pair_ray,
+                               uint32_t *d_pair_inst, uint32_t cap, uint32_t *n_pairs, void *stream);
+
+/* World rays against instances: the broad phase above into the context's
+ * workspace, then lsnif_query_pairs over its pairs; d_out[r] is ray r's
+ * nearest hit (the same answer as lsnif_query_pairs given every pair that can
+ * hit).  Synchronises `stream` once, after counting the pairs; the rest is
+ * asynchronous.  Not for graph capture (the pair count is read on the host). */
+lsnif_status lsnif_query_scene(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t n_rays,
+                               const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out, void *stream);
+
 /* ------------------------------------------------------------------ tuning
  *
  * Launch parameters of an object that change speed but never a result (a

@@ -65,6 +65,9 @@ def _load():
                                            C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         lib.oracle_query_pairs.restype = C.c_int
+        lib.oracle_broad_phase.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
+                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+        lib.oracle_broad_phase.restype = C.c_int64
         lib.oracle_num_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -145,6 +148,37 @@ def query(obj, rays, debug=False, outputs=True):
     return r
 
 
+def _instances(instances):
+    inst = (_Instance * max(len(instances), 1))()
+    for i, (oi, m) in enumerate(instances):
+        inst[i].object = int(oi)
+        inst[i].m[:] = [float(x) for x in np.asarray(m, np.float32).reshape(12)]
+    return inst
+
+
+def broad_phase(objects, instances, rays):
+    """The (ray, instance) pairs whose ray, in the instance's object space, the narrow
+    phase's slab test makes a candidate (Sec. 4): ``(pair_ray, pair_inst)`` uint32 arrays
+    listed by ray, then instance.  ``instances`` as for ``query_pairs``."""
+    lib = _load()
+    bound = [_Bound(o) for o in objects]
+    objs = (_Object * len(bound))(*[b.s for b in bound])
+    inst = _instances(instances)
+    rays = np.ascontiguousarray(rays, dtype=np.float32)
+    n = len(rays)
+    counts = np.empty(max(n, 1), np.uint32)
+    total = lib.oracle_broad_phase(C.cast(objs, C.c_void_p), C.cast(inst, C.c_void_p), len(instances),
+                                   _ptr(rays), n, _ptr(counts), None, None, 0)
+    if total < 0:
+        raise RuntimeError(f"oracle_broad_phase failed ({total})")
+    pr, pi = np.empty(max(total, 1), np.uint32), np.empty(max(total, 1), np.uint32)
+    got = lib.oracle_broad_phase(C.cast(objs, C.c_void_p), C.cast(inst, C.c_void_p), len(instances),
+                                 _ptr(rays), n, _ptr(counts), _ptr(pr), _ptr(pi), total)
+    if got != total:
+        raise RuntimeError(f"oracle_broad_phase failed ({got})")
+    return pr[:total], pi[:total]
+
+
 def query_pairs(objects, instances, rays, pair_ray, pair_inst):
     """Nearest hit per ray over (ray, instance) pairs.
 
@@ -155,10 +189,7 @@ def query_pairs(objects, instances, rays, pair_ray, pair_inst):
     lib = _load()
     bound = [_Bound(o) for o in objects]
     objs = (_Object * len(bound))(*[b.s for b in bound])
-    inst = (_Instance * len(instances))()
-    for i, (oi, m) in enumerate(instances):
-        inst[i].object = int(oi)
-        inst[i].m[:] = [float(x) for x in np.asarray(m, np.float32).reshape(12)]
+    inst = _instances(instances)
     rays = np.ascontiguousarray(rays, dtype=np.float32)
     pr = np.ascontiguousarray(pair_ray, dtype=np.uint32)
     pi = np.ascontiguousarray(pair_inst, dtype=np.uint32)

@@ -152,14 +152,16 @@ static int keep_f64(const walk_t *w, const int moving[3], const int c[3], int V,
  * per-axis plane function, so the emitted list equals the list obtained by
  * slab-testing every voxel on its own.
  */
-static void walk(const oracle_object *ob, const float *ray, walk_t *w)
+/* Validity rules and the ray/AABB slab test in voxel space: fills valid, o, d,
+ * ta, tb and candidate (ta < tb), and each axis' reciprocal and moving flag. */
+static void segment(const oracle_object *ob, const float *ray, walk_t *w, float inv[3], int moving[3])
 {
     memset(w, 0, sizeof(*w));
+    moving[0] = moving[1] = moving[2] = 0;
+    inv[0] = inv[1] = inv[2] = 0.0f;
     if (!ray_valid(ray)) return;
     w->valid = 1;
     const int V = ob->V;
-    float inv[3];
-    int moving[3];
     for (int a = 0; a < 3; ++a) {
         float s = (float)V / (ob->bmax[a] - ob->bmin[a]);
         w->o[a] = (ray[a] - ob->bmin[a]) * s;
@@ -184,12 +186,19 @@ static void walk(const oracle_object *ob, const float *ray, walk_t *w)
         }
     }
     if (!moving[0] && !moving[1] && !moving[2]) return;
-    float ta = fmax2(t0, ray[6]);
-    float tb = t1;
-    w->ta = ta;
-    w->tb = tb;
-    if (!(ta < tb)) return;
-    w->candidate = 1;
+    w->ta = fmax2(t0, ray[6]);
+    w->tb = t1;
+    w->candidate = w->ta < w->tb;
+}
+
+static void walk(const oracle_object *ob, const float *ray, walk_t *w)
+{
+    float inv[3];
+    int moving[3];
+    segment(ob, ray, w, inv, moving);
+    if (!w->candidate) return;
+    const int V = ob->V;
+    const float ta = w->ta, tb = w->tb;
 
     /* start cell: on a moving axis the unique cell whose [entry, exit)
      * contains ta (found by scanning every cell: slow and plain); on a still
@@ -475,6 +484,20 @@ typedef struct {
     float m[12];
 } oracle_instance;
 
+/* World ray rw mapped into an instance's object space: x_obj = A x + b, d_obj = A d, each
+ * row evaluated as ((m0 x + m1 y) + m2 z) + m3; an invalid world ray stays invalid. */
+static void to_object(const oracle_instance *I, const float *rw, float ro[8])
+{
+    for (int a = 0; a < 3; ++a) {
+        const float *m = I->m + 4 * a;
+        ro[a] = ((m[0] * rw[0] + m[1] * rw[1]) + m[2] * rw[2]) + m[3];
+        ro[3 + a] = (m[0] * rw[3] + m[1] * rw[4]) + m[2] * rw[5];
+    }
+    ro[6] = rw[6];
+    ro[7] = rw[7];
+    if (!ray_valid(rw)) ro[0] = NAN;
+}
+
 int oracle_query_pairs(const oracle_object *objs, const oracle_instance *inst, int32_t n_inst,
                        const float *rays, int64_t n_rays, const uint32_t *pair_ray,
                        const uint32_t *pair_inst, int64_t n_pairs,
@@ -511,16 +534,8 @@ int oracle_query_pairs(const oracle_object *objs, const oracle_instance *inst, i
 #pragma omp for schedule(dynamic, 64)
                 for (int64_t p = 0; p < n_pairs; ++p) {
                     const oracle_instance *I = &inst[pair_inst[p]];
-                    const float *rw = rays + 8 * (int64_t)pair_ray[p];
                     float ro[8];
-                    for (int a = 0; a < 3; ++a) {
-                        const float *m = I->m + 4 * a;
-                        ro[a] = ((m[0] * rw[0] + m[1] * rw[1]) + m[2] * rw[2]) + m[3];
-                        ro[3 + a] = (m[0] * rw[3] + m[1] * rw[4]) + m[2] * rw[5];
-                    }
-                    ro[6] = rw[6];
-                    ro[7] = rw[7];
-                    if (!ray_valid(rw)) ro[0] = NAN;
+                    to_object(I, rays + 8 * (int64_t)pair_ray[p], ro);
                     query_one(&objs[I->object], ro, p, &o, w, enc, out, ba, bb);
                 }
             }
@@ -552,4 +567,57 @@ int oracle_query_pairs(const oracle_object *objs, const oracle_instance *inst, i
     }
     free(ph); free(pt); free(pn); free(pm); free(best);
     return err;
+}
+
+/* Broad phase (Sec. 4, the step that finds which instances a ray may hit):
+ * pair (r, i) exists when ray r, mapped into instance i's object space as
+ * above, meets the object's voxel grid on [max(ta, tmin), tb] with positive
+ * length (the narrow phase's slab test makes it a candidate) and that
+ * segment starts no later than tmax; no other pair can hit, since a hit's t
+ * lies in [ta, tb] and must not exceed tmax.  counts[r] receives ray r's
+ * number of pairs.  Pairs are listed by ray, then instance; at most cap are
+ * written.  Returns the total. */
+int64_t oracle_broad_phase(const oracle_object *objs, const oracle_instance *inst, int32_t n_inst,
+                           const float *rays, int64_t n_rays, uint32_t *counts, uint32_t *pair_ray,
+                           uint32_t *pair_inst, int64_t cap)
+{
+#pragma omp parallel
+    {
+        walk_t *w = (walk_t *)malloc(sizeof(walk_t));
+        float inv[3], ro[8];
+        int moving[3];
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t r = 0; r < n_rays; ++r) {
+            uint32_t c = 0;
+            for (int32_t i = 0; w && i < n_inst; ++i) {
+                to_object(&inst[i], rays + 8 * r, ro);
+                segment(&objs[inst[i].object], ro, w, inv, moving);
+                c += w->candidate && w->ta <= ro[7] ? 1u : 0u;
+            }
+            counts[r] = c;
+        }
+        free(w);
+    }
+    int64_t total = 0;
+    for (int64_t r = 0; r < n_rays; ++r) total += counts[r];
+    if (total > cap) return total;
+    int64_t off = 0;
+    walk_t *w = (walk_t *)malloc(sizeof(walk_t));
+    if (!w) return -2;
+    for (int64_t r = 0; r < n_rays; ++r) {
+        if (!counts[r]) continue;
+        float inv[3], ro[8];
+        int moving[3];
+        for (int32_t i = 0; i < n_inst; ++i) {
+            to_object(&inst[i], rays + 8 * r, ro);
+            segment(&objs[inst[i].object], ro, w, inv, moving);
+            if (w->candidate && w->ta <= ro[7]) {
+                pair_ray[off] = (uint32_t)r;
+                pair_inst[off] = (uint32_t)i;
+                ++off;
+            }
+        }
+    }
+    free(w);
+    return total;
 }

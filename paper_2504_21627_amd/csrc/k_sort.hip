@@ -133,6 +133,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint32_t *keys, u
     if (live) order[pos] = i;
 }
 
+hipError_t launch_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *part, hipStream_t s)
+{
+    const uint32_t nblocks = (n + kScanChunk - 1) / kScanChunk;
+    if (!nblocks) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_partial, dim3(nblocks), dim3(kBlock), 0, s, v, n, part);
+    hipLaunchKernelGGL(k_scan_final, dim3(nblocks), dim3(kBlock), 0, s, v, n, part);
+    return hipGetLastError();
+}
+
 hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *keys, uint32_t *hist,
                                  uint32_t *order, hipStream_t s)
 {

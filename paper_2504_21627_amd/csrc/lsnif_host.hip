@@ -271,6 +271,8 @@ void lsnif_destroy(lsnif_ctx *ctx)
     (void)hipFree(ctx->ws);
     (void)hipFree(ctx->d_table);
     (void)hipFree(ctx->pws);
+    (void)hipFree(ctx->bws);
+    (void)hipFree(ctx->sws);
     for (auto &v : ctx->pending)
         for (hipEvent_t e : v) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
@@ -746,7 +748,7 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
     return LSNIF_OK;
 }
 
-static lsnif_status upload_table(lsnif_ctx *ctx, uint32_t &n_objs)
+lsnif_status upload_table(lsnif_ctx *ctx, uint32_t &n_objs)
 {
     n_objs = ctx->objects.empty() ? 1u : ctx->objects.rbegin()->first + 1u;
     if (!ctx->table_dirty && ctx->d_table) return LSNIF_OK;

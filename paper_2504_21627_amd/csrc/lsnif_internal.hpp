@@ -86,6 +86,11 @@ struct lsnif_ctx {
     size_t ws_bytes = 0;
     void *pws = nullptr;
     size_t pws_bytes = 0;
+    // broad phase: per-ray counts and their scan; the pairs of lsnif_query_scene
+    void *bws = nullptr;
+    size_t bws_bytes = 0;
+    void *sws = nullptr;
+    size_t sws_bytes = 0;
     // device copy of the object table for pair queries, indexed by object id
     void *d_table = nullptr;
     size_t table_cap = 0;
@@ -117,6 +122,8 @@ struct PairsSetup {
     uint32_t n_objs = 0;
 };
 lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps);
+// Upload the object table (by object id) if objects changed; n_objs = largest id + 1.
+lsnif_status upload_table(lsnif_ctx *ctx, uint32_t &n_objs);
 // Grow a device workspace to `need` bytes (frees the old one, which waits for its users).
 lsnif_status grow_workspace(void *&buf, size_t &have, size_t need);
 // Choose an object's hot levels for an LDS budget (bytes).

@@ -1092,6 +1092,18 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
     }
 }
 
+// ------------------------------------------------------------------ broad phase
+struct BroadArgs {
+    const float4 *rays;
+    uint32_t n_rays;
+    const lsnif_instance *inst;
+    uint32_t n_inst;
+    const ObjDev *objs;       // object table by id
+    uint32_t n_objs;
+    uint32_t *offsets;        // [n_rays + 1]: pairs per ray, then their exclusive scan
+    uint32_t *pair_ray, *pair_inst;
+};
+
 // ------------------------------------------------------------------ voxel walk
 // RECHECK: some object of the launch asks for the float64 re-decision of grazing voxels.
 template <bool PAIRS, bool RECHECK>

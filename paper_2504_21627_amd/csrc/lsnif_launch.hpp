@@ -24,6 +24,13 @@ hipError_t launch_mma_fp8(const QueryArgs &A, int feat_dtype, int F, int kbm, bo
 // `recheck` when some object of the launch re-decides grazing voxels in float64.
 hipError_t launch_walk(const QueryArgs &A, bool pairs, bool recheck, uint32_t grid, hipStream_t s);
 hipError_t launch_debug(const DebugArgs &D, hipStream_t s);
+// Broad phase: pairs per ray into B.offsets (and 0 at offsets[n_rays]), then, after an
+// exclusive scan of the n_rays + 1 counters, the pairs themselves.
+struct BroadArgs;
+hipError_t launch_broad_count(const BroadArgs &B, hipStream_t s);
+hipError_t launch_broad_write(const BroadArgs &B, hipStream_t s);
+// In-place exclusive scan of n counters; `part` holds (n + 1023) / 1024 partial sums.
+hipError_t launch_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *part, hipStream_t s);
 struct PairPlan;
 hipError_t launch_pairs_prepare(const PairPlan &P, hipStream_t s);
 hipError_t launch_pairs_payload(const PairPlan &P, hipStream_t s);

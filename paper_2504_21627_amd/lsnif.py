@@ -110,6 +110,10 @@ def load():
                                       C.POINTER(lsnif_debug_bufs), C.c_void_p]
     lib.lsnif_query_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
                                       C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
+    lib.lsnif_broad_phase.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
+                                      C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32), C.c_void_p]
+    lib.lsnif_query_scene.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
+                                      C.c_void_p]
     lib.lsnif_serve_start.argtypes = [C.c_void_p, C.POINTER(lsnif_serve_cfg)]
     lib.lsnif_serve_submit.argtypes = [C.c_void_p, C.POINTER(lsnif_request), C.POINTER(C.c_uint64)]
     lib.lsnif_serve_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)]
@@ -139,7 +143,8 @@ def load():
                  "lsnif_profile_read", "lsnif_query_pairs", "lsnif_serve_start", "lsnif_serve_submit",
                  "lsnif_serve_poll", "lsnif_serve_wait", "lsnif_serve_cancel", "lsnif_serve_stats_get",
                  "lsnif_serve_stop", "lsnif_graph_query", "lsnif_graph_pairs", "lsnif_graph_launch",
-                 "lsnif_get_tuning", "lsnif_set_tuning", "lsnif_autotune", "lsnif_autotune_pairs"):
+                 "lsnif_get_tuning", "lsnif_set_tuning", "lsnif_autotune", "lsnif_autotune_pairs",
+                 "lsnif_broad_phase", "lsnif_query_scene"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -265,6 +270,37 @@ def lsnif_query_pairs(ctx, rays, pair_ray, pair_inst, inst, out, stream=None):
                                     C.c_void_p(pair_inst.data_ptr() if m else 0), m,
                                     C.c_void_p(inst.data_ptr() if k else 0), k,
                                     C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+
+
+def lsnif_broad_phase(ctx, rays, inst, pair_ray, pair_inst, stream=None):
+    """Device broad phase: fills ``pair_ray`` / ``pair_inst`` (int32 device tensors, their
+    length is the capacity) and returns the number of pairs; raises with status
+    LSNIF_E_NOMEM when they do not fit (``lsnif_last_pair_count`` then has the count)."""
+    n, k = rays.shape[0], inst.shape[0]
+    cnt = C.c_uint32()
+    cap = pair_ray.shape[0]
+    assert pair_inst.shape[0] == cap
+    st = load().lsnif_broad_phase(ctx, C.c_void_p(rays.data_ptr() if n else 0), n,
+                                  C.c_void_p(inst.data_ptr() if k else 0), k,
+                                  C.c_void_p(pair_ray.data_ptr() if cap else 0),
+                                  C.c_void_p(pair_inst.data_ptr() if cap else 0), cap, C.byref(cnt),
+                                  _stream_handle(stream))
+    global lsnif_last_pair_count
+    lsnif_last_pair_count = cnt.value
+    _check(st)
+    return cnt.value
+
+
+lsnif_last_pair_count = 0
+
+
+def lsnif_query_scene(ctx, rays, inst, out, stream=None):
+    """World rays against instances: device broad phase, then the pair query."""
+    n, k = rays.shape[0], inst.shape[0]
+    assert out.shape[0] >= n
+    _check(load().lsnif_query_scene(ctx, C.c_void_p(rays.data_ptr() if n else 0), n,
+                                    C.c_void_p(inst.data_ptr() if k else 0), k, C.c_void_p(out.data_ptr()),
+                                    _stream_handle(stream)))
 
 
 def lsnif_get_tuning(ctx, object_id):

@@ -1,0 +1,100 @@
+"""The device broad phase and the scene query (Sec. 4) against the oracle's broad phase
+and against the pair query given the host's world-box pairs."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.scene import small_scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_2504_21627_amd import lsnif
+    return lsnif
+
+
+@pytest.fixture(scope="module")
+def scene():
+    return small_scene()
+
+
+def bits(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def setup(L, ctx, objs, insts, rays):
+    import torch
+    ids = [L.lsnif_build(ctx, L.ObjectDesc(o, "fp16", "fp16")) for o in objs]
+    inst = torch.from_numpy(L.instances_array([(ids[k], m) for k, m in insts])).cuda()
+    return ids, inst, torch.from_numpy(rays).cuda()
+
+
+def test_broad_phase_matches_oracle(L, scene):
+    import torch
+    objs, insts, boxes, rays_np = scene
+    want_r, want_i = oracle.broad_phase(objs, insts, rays_np)
+    ctx = L.lsnif_create(0)
+    try:
+        ids, inst, rays = setup(L, ctx, objs, insts, rays_np)
+        cap = len(want_r) + 100
+        pr = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+        pi = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+        n = L.lsnif_broad_phase(ctx, rays, inst, pr, pi)
+        torch.cuda.synchronize()
+        assert n == len(want_r)
+        assert np.array_equal(pr[:n].cpu().numpy().astype(np.uint32), want_r)
+        assert np.array_equal(pi[:n].cpu().numpy().astype(np.uint32), want_i)
+        assert (pr[n:] == -1).all()
+        # too small a buffer: nothing written, the count reported
+        small = torch.full((10,), -1, dtype=torch.int32, device="cuda")
+        with pytest.raises(L.LsnifError) as e:
+            L.lsnif_broad_phase(ctx, rays, inst, small, small.clone())
+        assert e.value.status == L.LSNIF_E_NOMEM and L.lsnif_last_pair_count == n
+        assert (small == -1).all()
+        # no instances; an instance naming no built object; no rays
+        none = torch.empty((0, 13), dtype=torch.int32, device="cuda")
+        assert L.lsnif_broad_phase(ctx, rays, none, pr, pi) == 0
+        ghost = inst[:2].clone()
+        ghost[1, 0] = 999
+        got = L.lsnif_broad_phase(ctx, rays, ghost, pr, pi)
+        torch.cuda.synchronize()
+        assert got == int((want_i == 0).sum()) and (pi[:got] == 0).all()
+        assert L.lsnif_broad_phase(ctx, rays[:0], inst, pr, pi) == 0
+    finally:
+        L.lsnif_destroy(ctx)
+
+
+def test_scene_query_equals_pairs_query(L, scene):
+    """lsnif_query_scene answers every ray as the pair query does given the host's (looser)
+    world-box pairs, bit for bit, and agrees with the oracle's pair query."""
+    import torch
+    objs, insts, boxes, rays_np = scene
+    ctx = L.lsnif_create(0)
+    try:
+        ids, inst, rays = setup(L, ctx, objs, insts, rays_np)
+        n = len(rays_np)
+        got = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+        L.lsnif_query_scene(ctx, rays, inst, got)
+        hr, hi = W.configs.ray_box_pairs(rays_np, boxes)
+        ref = torch.empty_like(got)
+        L.lsnif_query_pairs(ctx, rays, torch.from_numpy(hr.astype(np.int32)).cuda(),
+                            torch.from_numpy(hi.astype(np.int32)).cuda(), inst, ref)
+        torch.cuda.synchronize()
+        g, r = bits(got), bits(ref)
+        assert np.array_equal(g, r)
+        assert (g[:, 0] == 1).sum() > 100
+        pr, pi = oracle.broad_phase(objs, insts, rays_np)
+        o = oracle.query_pairs(objs, insts, rays_np, pr, pi)
+        agree = (g[:, 0] == o["hit"]).mean()
+        assert agree >= 0.99, agree
+        both = (g[:, 0] == 1) & (o["hit"] == 1)
+        t = got.cpu().numpy()[:, 1]
+        assert np.all(np.abs(t[both] - o["t"][both]) <= 1e-3 * np.maximum(np.abs(o["t"][both]), 1.0))
+    finally:
+        L.lsnif_destroy(ctx)
