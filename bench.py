@@ -356,8 +356,18 @@ def bench_c2(L, args):
             _, _, sort_ms, walk_ms, kern_ms = time_path(L, ctx, oid, rays, out, max(args.steps // 4, 5),
                                                         args.warmup)
             L.lsnif_set_tuning(ctx, oid, *tuning.values())
+        ub_ms = None
+        if name == "fp16":
+            # the gather ceiling: the same batch through the kernel that only gathers (SURVEY's
+            # ub_gather), with the walk of the whole batch first as for the roofline's kernel time
+            L.lsnif_set_tuning(ctx, oid, *iso.values())
+            sums = torch.empty(n, dtype=torch.float32, device="cuda")
+            _, _, _, _, ub_ms = time_calls(L, ctx, lambda st: L.lsnif_gather_ceiling(ctx, oid, rays, sums, st),
+                                           max(args.steps // 4, 5), args.warmup)
+            L.lsnif_set_tuning(ctx, oid, *tuning.values())
+            del sums
         pts, cand = points_per_launch(L, ctx, oid, rays, out)
-        paths[name] = {"wall": wall, "lat": lat, "points": pts, "cand": cand, "sort_ms": sort_ms,
+        paths[name] = {"wall": wall, "lat": lat, "points": pts, "cand": cand, "sort_ms": sort_ms, "ub_ms": ub_ms,
                        "walk_ms": walk_ms, "kern_ms": kern_ms, "feat_bytes": 2 if feat == "fp16" else 4,
                        "tuning": tuning, "tuning_isolated": iso}
         L.lsnif_release(ctx, oid)
@@ -395,6 +405,9 @@ def bench_c2(L, args):
                      "bytes_per_point": bpp, "mean_kernel_ms": mean_ms,
                      "mean_sort_ms": float(head["sort_ms"]), "mean_walk_ms": float(head["walk_ms"]),
                      "tuning": head["tuning_isolated"],
+                     "ub_gather_ms": head["ub_ms"],
+                     "ub_gather_gbs": alg_bytes / (head["ub_ms"] * 1e-3) / 1e9 if head["ub_ms"] else None,
+                     "frac_of_ub_gather": head["ub_ms"] / mean_ms if head["ub_ms"] else None,
                      "mfma_tflops": flops / (mean_ms * 1e-3) / 1e12,
                      "mfma_frac": flops / (mean_ms * 1e-3) / 1e12 / MFMA_FP16_PEAK_TFLOPS},
     }

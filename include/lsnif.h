@@ -192,6 +192,16 @@ lsnif_status lsnif_query_debug(lsnif_ctx *ctx, uint32_t object_id, const lsnif_r
                                uint32_t n, lsnif_hit *d_out, const lsnif_debug_bufs *dbg,
                                void *stream);
 
+/* Measurement aid: the gathers of lsnif_query alone.  Runs the same sort,
+ * walk, boundary points and hash-grid encoding (Sec. 3.2) as the query, but
+ * instead of the MLP writes d_sums[i] = the sum over ray i's boundary points,
+ * levels and features of the interpolated features (0 for a ray with no
+ * point).  Its kernel holds no MLP accumulators, so its time is a ceiling for
+ * what the query kernel's gathers can take on the same batch.  d_sums: [n]
+ * floats on the device; asynchronous on `stream`; timed by lsnif_profile_*. */
+lsnif_status lsnif_gather_ceiling(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
+                                  float *d_sums, void *stream);
+
 /* Nearest hit over (ray, instance) pairs (Sec. 4: the broad phase lists the
  * pairs, the narrow phase queries each LSNIF object, and a ray's hit
  * information is updated with the nearest hit).

@@ -537,6 +537,20 @@ lsnif_status lsnif_query_debug(lsnif_ctx *ctx, uint32_t object_id, const lsnif_r
     return run_query(ctx, object_id, d_rays, n, d_out, dbg, stream);
 }
 
+lsnif_status lsnif_gather_ceiling(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays, uint32_t n,
+                                  float *d_sums, void *stream)
+{
+    if (!ctx) return fail(LSNIF_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->device < 0) return fail(LSNIF_E_DEVICE, "host-only context");
+    const Object *ob = nullptr;
+    lsnif_status st = check_query(ctx, object_id, d_rays, n, reinterpret_cast<lsnif_hit *>(d_sums), ob);
+    if (st || n == 0) return st;
+    DeviceGuard guard(ctx->device);
+    if ((st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n, ob->geom.sort_bits, ob->geom.H >> 1)))) return st;
+    return enqueue_query(ctx, *ob, d_rays, n, nullptr, nullptr, static_cast<hipStream_t>(stream), ctx->ws, 1, d_sums);
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ enqueue
@@ -682,7 +696,7 @@ static lsnif_status walk_then_query(lsnif_ctx *ctx, QueryArgs A, bool pairs, boo
 }
 
 lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
-                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws, int chunks)
+                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws, int chunks, float *gather_sums)
 {
     QueryArgs A{};
     A.g = ob.geom;
@@ -735,6 +749,7 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
     const uint32_t k = dbg ? 1u : (chunks > 0 ? (uint32_t)chunks : ob.walk_chunks);
     lsnif_status st = walk_then_query(ctx, A, false, ob.geom.recheck != 0, grid, k, s, ev[2],
                                       [&](const QueryArgs &a, uint32_t g) -> hipError_t {
+        if (gather_sums) return launch_gather_only(a, ob.feat_dtype, ob.F, gather_sums, g, s);
         if (ob.mlp_dtype == LSNIF_FP32) return launch_f32(a, ob.feat_dtype, ob.F, false, g, s);
         if (ob.mlp_dtype == LSNIF_FP16) return launch_mma_f16(a, ob.feat_dtype, ob.F, kbm, false, g, s);
         if (ob.mlp_dtype == LSNIF_BF16) return launch_mma_bf16(a, ob.feat_dtype, ob.F, kbm, false, g, s);

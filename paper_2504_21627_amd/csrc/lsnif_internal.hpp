@@ -137,7 +137,8 @@ lsnif_status check_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_
 // `chunks`: tile ranges whose walk runs ahead of the query kernel on the side stream
 // (<= 0: the object's tuning; 1: the walk of the whole batch first).
 lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
-                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws, int chunks = 0);
+                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws, int chunks = 0,
+                           float *gather_sums = nullptr);
 lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray *d_rays, uint32_t n_rays,
                            const uint32_t *d_pair_ray, const uint32_t *d_pair_inst, uint32_t n_pairs,
                            const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out, hipStream_t s, void *ws,

@@ -1105,6 +1105,66 @@ __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
     }
 }
 
+// ------------------------------------------------------------- gather ceiling
+//
+// The query kernel's gathers alone, for measurement: the same prologue (voxel
+// lists from the walk, count sort), the same boundary points, repeated-point
+// reuse and encode_levels batches, but each ray's interpolated features are
+// summed into sums[r] instead of feeding the MLP.  Without the accumulators
+// it runs at the occupancy its gathers and address arithmetic allow, so its
+// time bounds what the query kernel's gathers can take.
+template <typename TF, int F>
+__device__ __forceinline__ void gather_only_body(const QueryArgs &A, float *sums, uint32_t *s_list, Shared &S)
+{
+    constexpr int FP = F == 3 ? 4 : F;
+    constexpr int LPB = 16 / FP;
+    constexpr int NL = (F * sizeof(TF) <= 4 && LPB >= 8) ? 8 : (LPB < 4 ? LPB : 4);
+    const Geom &g = A.g;
+    const TF *__restrict__ tab = reinterpret_cast<const TF *>(A.tables);
+    Lane ln;
+    walk_and_sort<false>(A, g, S, s_list, ln);
+    const int count = 2 * ln.nvox;
+    const int wmax = __builtin_amdgcn_readfirstlane(wave_max(count));
+    float total = 0.0f, prev = 0.0f;
+    uint32_t pp[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu};
+    int pface = -1;
+    for (int h = 0; h < wmax; ++h) {
+        float p[3] = {0.0f, 0.0f, 0.0f};
+        int face = 0;
+        const bool has = h < count;
+        if (has) face = boundary_point(ln.w, s_list[(h >> 1) * kBlock + ln.src], h & 1, p);
+        const bool dup = has && (h & 1) == 0 && face == pface && __float_as_uint(p[0]) == pp[0] &&
+                         __float_as_uint(p[1]) == pp[1] && __float_as_uint(p[2]) == pp[2];
+        float here = 0.0f;
+        if (has && !dup) {
+            for (int l0 = 0; l0 < g.L; l0 += NL) {
+                float v[NL][F];
+                encode_levels<TF, F, NL, false>(g, tab, nullptr, l0, p, face, v);
+#pragma unroll
+                for (int lv = 0; lv < NL; ++lv)
+#pragma unroll
+                    for (int f = 0; f < F; ++f) here += v[lv][f];
+            }
+        } else if (dup) {
+            here = prev;
+        }
+        total += here;
+        prev = here;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) pp[b] = __float_as_uint(p[b]);
+        pface = has ? face : -1;
+    }
+    if (ln.live) sums[ln.r] = total;
+}
+
+template <typename TF, int F>
+__global__ __launch_bounds__(kBlock) void k_gather_only(QueryArgs A, float *sums)
+{
+    extern __shared__ uint32_t s_list[];
+    __shared__ Shared S;
+    gather_only_body<TF, F>(A, sums, s_list, S);
+}
+
 // ------------------------------------------------------------------ broad phase
 struct BroadArgs {
     const float4 *rays;

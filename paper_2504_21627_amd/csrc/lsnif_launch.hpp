@@ -24,6 +24,8 @@ hipError_t launch_mma_fp8(const QueryArgs &A, int feat_dtype, int F, int kbm, bo
 // `recheck` when some object of the launch re-decides grazing voxels in float64.
 hipError_t launch_walk(const QueryArgs &A, bool pairs, bool recheck, uint32_t grid, hipStream_t s);
 hipError_t launch_debug(const DebugArgs &D, hipStream_t s);
+// Gather ceiling: the query's gathers alone, each ray's feature sum into sums[r].
+hipError_t launch_gather_only(const QueryArgs &A, int feat_dtype, int F, float *sums, uint32_t grid, hipStream_t s);
 // Broad phase: pairs per ray into B.offsets (and 0 at offsets[n_rays]), then, after an
 // exclusive scan of the n_rays + 1 counters, the pairs themselves.
 struct BroadArgs;

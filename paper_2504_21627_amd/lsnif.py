@@ -110,6 +110,7 @@ def load():
                                       C.POINTER(lsnif_debug_bufs), C.c_void_p]
     lib.lsnif_query_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
                                       C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
+    lib.lsnif_gather_ceiling.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
     lib.lsnif_broad_phase.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
                                       C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32), C.c_void_p]
     lib.lsnif_query_scene.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
@@ -144,7 +145,7 @@ def load():
                  "lsnif_serve_poll", "lsnif_serve_wait", "lsnif_serve_cancel", "lsnif_serve_stats_get",
                  "lsnif_serve_stop", "lsnif_graph_query", "lsnif_graph_pairs", "lsnif_graph_launch",
                  "lsnif_get_tuning", "lsnif_set_tuning", "lsnif_autotune", "lsnif_autotune_pairs",
-                 "lsnif_broad_phase", "lsnif_query_scene"):
+                 "lsnif_broad_phase", "lsnif_query_scene", "lsnif_gather_ceiling"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -270,6 +271,14 @@ def lsnif_query_pairs(ctx, rays, pair_ray, pair_inst, inst, out, stream=None):
                                     C.c_void_p(pair_inst.data_ptr() if m else 0), m,
                                     C.c_void_p(inst.data_ptr() if k else 0), k,
                                     C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+
+
+def lsnif_gather_ceiling(ctx, object_id, rays, sums, stream=None):
+    """The query's gathers alone: sums[i] = ray i's summed interpolated features."""
+    n = rays.shape[0]
+    assert sums.shape[0] >= n
+    _check(load().lsnif_gather_ceiling(ctx, object_id, C.c_void_p(rays.data_ptr()), n,
+                                       C.c_void_p(sums.data_ptr()), _stream_handle(stream)))
 
 
 def lsnif_broad_phase(ctx, rays, inst, pair_ray, pair_inst, stream=None):

@@ -190,6 +190,28 @@ def test_edge_cases(L, ctx, c1, mlp):
         L.lsnif_release(ctx, oid)
 
 
+@pytest.mark.parametrize("feat,mlp", [("fp32", "fp32"), ("fp16", "fp16")])
+def test_gather_ceiling_sums(L, ctx, c1, c2_small, feat, mlp):
+    """The gather-ceiling kernel runs the query's walk and encoding: each ray's summed
+    features equal the sum of the oracle's encoding row, within the feature type's rounding."""
+    import torch
+    for obj, rays in ((c1["objects"][0], c1["rays"]), (c2_small["objects"][0], c2_small["rays"][:6000])):
+        oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
+        try:
+            sums = torch.full((len(rays),), float("nan"), dtype=torch.float32, device="cuda")
+            L.lsnif_gather_ceiling(ctx, oid, torch.from_numpy(rays).cuda(), sums)
+            torch.cuda.synchronize()
+            o = oracle.query(obj, rays, debug=True)
+            want, scale = o["enc"].sum(1), np.abs(o["enc"]).sum(1)
+            got = sums.cpu().numpy().astype(np.float64)
+            tol = (1e-5 if feat == "fp32" else 4 * U[feat]) * scale + 1e-30
+            bad = np.abs(got - want) > tol
+            assert not bad.any(), (int(bad.sum()), float(np.abs(got - want)[bad].max()))
+            assert (np.abs(want) > 0).sum() > 100
+        finally:
+            L.lsnif_release(ctx, oid)
+
+
 def test_width_limits_rejected(L, ctx):
     """Width 128 runs on the matrix cores for at most 32 inputs per point (2 K blocks);
     widths other than 64 and 128 have no kernel."""
