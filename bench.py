@@ -231,7 +231,35 @@ def bench_c5(L, n_requests, seed=7):
             L.lsnif_query_scene(ctx, rays_d, inst_d, out_d)
             torch.cuda.synchronize()
             sc_ms.append((time.perf_counter() - t0) * 1e3)
-        del out_d, pr_d, pi_d
+        # a wavefront path tracer over the same scene: the primary image, then depth - 1 diffuse
+        # bounces, each one lsnif_query_scene of the previous hits' bounce rays (lsnif_bounce)
+        depth = 4
+        prim = rays_d[:pool["n_primary"]]
+        nxt = torch.empty((len(prim), 8), dtype=torch.float32, device="cuda")
+        par = torch.empty(len(prim), dtype=torch.int32, device="cuda")
+        hits = torch.empty((len(prim), 6), dtype=torch.float32, device="cuda")
+        bufs = [torch.empty_like(nxt), torch.empty_like(nxt)]
+
+        def trace():
+            cur, counts = prim, []
+            for b in range(depth):
+                m = cur.shape[0]
+                counts.append(m)
+                if m == 0:
+                    break
+                L.lsnif_query_scene(ctx, cur, inst_d, hits[:m])
+                if b + 1 < depth:
+                    k = L.lsnif_bounce(ctx, cur, hits[:m], 17, b + 1, 1e-4, bufs[b % 2], par)
+                    cur = bufs[b % 2][:k]
+            return counts
+        tr_ms = []
+        for _ in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            counts = trace()
+            torch.cuda.synchronize()
+            tr_ms.append((time.perf_counter() - t0) * 1e3)
+        del out_d, pr_d, pi_d, nxt, hits, bufs
         rs = RequestSet(L, rays, pr, pi, insts, windows)
         torch.cuda.synchronize()
         cfg = dict(max_inflight=8, hbm_budget=4 << 30, n_streams=4)
@@ -278,6 +306,10 @@ def bench_c5(L, n_requests, seed=7):
         "broad_phase": {"where": "device (lsnif_broad_phase)", "pool_rays": len(rays), "pairs": int(n_pairs),
                         "ms": float(np.median(bp_ms[1:])),
                         "mrays_s": len(rays) / float(np.median(bp_ms[1:])) / 1e3},
+        "wavefront": {"what": f"1024x1024 primary rays, then {depth - 1} diffuse bounces from the hits: "
+                              "one lsnif_query_scene per depth, lsnif_bounce between",
+                      "rays_per_depth": counts, "ms": float(np.median(tr_ms[1:])),
+                      "value": sum(counts) / float(np.median(tr_ms[1:])) / 1e3, "unit": "Mrays/s"},
         "scene_query": {"what": "the whole pool in one lsnif_query_scene (broad phase + pair query)",
                         "value": len(rays) / float(np.median(sc_ms[1:])) / 1e3, "unit": "Mrays/s",
                         "ms": float(np.median(sc_ms[1:]))},

@@ -253,6 +253,26 @@ lsnif_status lsnif_broad_phase(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
 lsnif_status lsnif_query_scene(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t n_rays,
                                const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out, void *stream);
 
+/* The consumer side of a wavefront path tracer (the paper renders with one,
+ * Sec. 7): every ray i with a hit spawns one diffuse bounce ray, compacted in
+ * the order of i, for the next lsnif_query_scene.  New origin x + eps n, with
+ * x = o + t d evaluated per axis as o + (t d) and n the hit normal, negated
+ * if it faces along d (the paper offsets new rays by a small epsilon along
+ * the normal); direction (lx tx + ly bx) + lz n, cosine-distributed about n
+ * (Malley's method: r = sqrt(u1), phi = 2 pi u2, lx = r cos phi,
+ * ly = r sin phi, lz = sqrt(max(0, 1 - u1))) in the orthonormal basis of Duff
+ * et al. 2017 (s = copysign(1, nz), a = -1 / (s + nz), b = nx ny a,
+ * tx = (1 + s nx nx a, s b, -s nx), bx = (b, s + ny ny a, -ny)); tmin 0,
+ * tmax +inf.  u1 = (h1 >> 8) 2^-24 and u2 = (h2 >> 8) 2^-24 with
+ * h1 = pcg(i ^ pcg(seed ^ pcg(bounce))) and h2 = pcg(h1), pcg the PCG hash
+ * of Jarzynski and Olano 2020.  d_parent[j] = the index of new ray j's
+ * parent.  Counts on `stream`, synchronises it once to read the count into
+ * *n_next, then writes asynchronously; LSNIF_E_NOMEM (nothing written) when
+ * the count exceeds cap. */
+lsnif_status lsnif_bounce(lsnif_ctx *ctx, const lsnif_ray *d_rays, const lsnif_hit *d_hits, uint32_t n, uint32_t seed,
+                          uint32_t bounce, float eps, lsnif_ray *d_next, uint32_t *d_parent, uint32_t cap,
+                          uint32_t *n_next, void *stream);
+
 /* ------------------------------------------------------------------ tuning
  *
  * Launch parameters of an object that change speed but never a result (a

@@ -68,6 +68,9 @@ def _load():
         lib.oracle_broad_phase.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64,
                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
         lib.oracle_broad_phase.restype = C.c_int64
+        lib.oracle_bounce.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_uint32,
+                                      C.c_uint32, C.c_float, C.c_void_p, C.c_void_p]
+        lib.oracle_bounce.restype = C.c_int64
         lib.oracle_num_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -177,6 +180,24 @@ def broad_phase(objects, instances, rays):
     if got != total:
         raise RuntimeError(f"oracle_broad_phase failed ({got})")
     return pr[:total], pi[:total]
+
+
+def bounce(rays, hit, t, normal, seed, bounce_index, eps):
+    """Diffuse bounce rays of the rays with a hit, in order: ``(next_rays (m, 8) float32,
+    parent (m,) uint32)``.  ``hit``, ``t`` and ``normal`` as returned by ``query_pairs``."""
+    lib = _load()
+    rays = np.ascontiguousarray(rays, dtype=np.float32)
+    hit = np.ascontiguousarray(hit, dtype=np.uint32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    normal = np.ascontiguousarray(normal, dtype=np.float32)
+    n = len(rays)
+    m = int(hit[:n].astype(bool).sum())
+    nxt, par = np.empty((max(m, 1), 8), np.float32), np.empty(max(m, 1), np.uint32)
+    got = lib.oracle_bounce(_ptr(rays), _ptr(hit), _ptr(t), _ptr(normal), n, seed, bounce_index,
+                            float(eps), _ptr(nxt), _ptr(par))
+    if got != m:
+        raise RuntimeError(f"oracle_bounce returned {got}, expected {m}")
+    return nxt[:m], par[:m]
 
 
 def query_pairs(objects, instances, rays, pair_ray, pair_inst):

@@ -621,3 +621,50 @@ int64_t oracle_broad_phase(const oracle_object *objs, const oracle_instance *ins
     free(w);
     return total;
 }
+
+/* PCG hash (Jarzynski and Olano 2020, "Hash Functions for GPU Rendering"). */
+static uint32_t pcg_hash(uint32_t v)
+{
+    uint32_t state = v * 747796405u + 2891336453u;
+    uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+/* Diffuse bounce rays of a wavefront path tracer (the paper renders with one,
+ * Sec. 7).  For every ray i with a hit, in order of i: the hit point
+ * x = o + t d, the hit normal turned to face the incoming ray, the new origin
+ * x + eps n, and a direction cosine-distributed about n by Malley's method
+ * (a uniform point of the unit disk, r = sqrt(u1), phi = 2 pi u2, lifted to the
+ * hemisphere) expressed in the orthonormal basis of Duff et al. 2017; the
+ * uniforms come from the PCG hash of (seed, bounce, i).  Writes the new rays
+ * (tmin 0, tmax +inf) and their parents; returns their number. */
+int64_t oracle_bounce(const float *rays, const uint32_t *hit, const float *t, const float *nrm, int64_t n,
+                      uint32_t seed, uint32_t bounce, float eps, float *next, uint32_t *parent)
+{
+    const uint32_t k = pcg_hash(seed ^ pcg_hash(bounce));
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!hit[i]) continue;
+        const float *r = rays + 8 * i;
+        float nv[3] = {nrm[3 * i], nrm[3 * i + 1], nrm[3 * i + 2]};
+        if ((nv[0] * r[3] + nv[1] * r[4]) + nv[2] * r[5] > 0.0f)
+            for (int a = 0; a < 3; ++a) nv[a] = -nv[a];
+        float *q = next + 8 * m;
+        for (int a = 0; a < 3; ++a) q[a] = (r[a] + t[i] * r[3 + a]) + eps * nv[a];
+        const uint32_t h1 = pcg_hash((uint32_t)i ^ k), h2 = pcg_hash(h1);
+        const float u1 = (float)(h1 >> 8) * 5.9604644775390625e-8f, u2 = (float)(h2 >> 8) * 5.9604644775390625e-8f;
+        const float rr = sqrtf(u1), phi = 6.2831855f * u2;
+        const float lx = rr * cosf(phi), ly = rr * sinf(phi), lz = sqrtf(fmaxf(0.0f, 1.0f - u1));
+        const float s = copysignf(1.0f, nv[2]);
+        const float a = -1.0f / (s + nv[2]);
+        const float b = nv[0] * nv[1] * a;
+        const float tx[3] = {1.0f + s * nv[0] * nv[0] * a, s * b, -s * nv[0]};
+        const float bx[3] = {b, s + nv[1] * nv[1] * a, -nv[1]};
+        for (int c = 0; c < 3; ++c) q[3 + c] = (lx * tx[c] + ly * bx[c]) + lz * nv[c];
+        q[6] = 0.0f;
+        q[7] = INFINITY;
+        parent[m] = (uint32_t)i;
+        ++m;
+    }
+    return m;
+}

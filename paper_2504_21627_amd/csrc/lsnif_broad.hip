@@ -2,6 +2,8 @@
 // query: world rays and instances in, the nearest hit per ray out (Sec. 4).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "lsnif_internal.hpp"
 #include "lsnif_kernels.hpp"
 #include "lsnif_launch.hpp"
@@ -103,6 +105,46 @@ lsnif_status lsnif_query_scene(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
     if ((st = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, total, ps.n_objs, ps.maxH >> 1))))
         return st;
     return enqueue_pairs(ctx, ps, d_rays, n_rays, B.pair_ray, B.pair_inst, total, d_inst, n_inst, d_out, s, ctx->pws);
+}
+
+lsnif_status lsnif_bounce(lsnif_ctx *ctx, const lsnif_ray *d_rays, const lsnif_hit *d_hits, uint32_t n, uint32_t seed,
+                          uint32_t bounce, float eps, lsnif_ray *d_next, uint32_t *d_parent, uint32_t cap,
+                          uint32_t *n_next, void *stream)
+{
+    if (!ctx || !n_next) return fail(LSNIF_E_INVALID, "ctx or n_next is NULL");
+    *n_next = 0;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    if (ctx->device < 0) return fail(LSNIF_E_DEVICE, "host-only context");
+    if (n && (!d_rays || !d_hits)) return fail(LSNIF_E_INVALID, "rays or hits is NULL");
+    if (cap && (!d_next || !d_parent)) return fail(LSNIF_E_INVALID, "output buffers are NULL");
+    if (reinterpret_cast<uintptr_t>(d_rays) % 16 || reinterpret_cast<uintptr_t>(d_next) % 16)
+        return fail(LSNIF_E_INVALID, "rays must be 16-byte aligned");
+    if (!(eps >= 0.0f) || !std::isfinite(eps)) return fail(LSNIF_E_INVALID, "eps must be finite and >= 0");
+    DeviceGuard guard(ctx->device);
+    const size_t n1 = (size_t)n + 1, parts = (n1 + 1023) / 1024;
+    lsnif_status st = grow_workspace(ctx->bws, ctx->bws_bytes, al256(n1 * 4) + al256(parts * 4));
+    if (st) return st;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    BounceArgs B{};
+    B.rays = reinterpret_cast<const float4 *>(d_rays);
+    B.hits = d_hits;
+    B.n = n;
+    B.seed = seed;
+    B.bounce = bounce;
+    B.eps = eps;
+    B.offsets = static_cast<uint32_t *>(ctx->bws);
+    B.next = reinterpret_cast<float4 *>(d_next);
+    B.parent = d_parent;
+    uint32_t *part = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->bws) + al256(n1 * 4));
+    HIP_TRY(launch_bounce_mark(B, s));
+    HIP_TRY(launch_exclusive_scan(B.offsets, (uint32_t)n1, part, s));
+    uint32_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, B.offsets + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_next = total;
+    if (total > cap) return fail(LSNIF_E_NOMEM, "%u bounce rays do not fit a buffer of %u", total, cap);
+    HIP_TRY(launch_bounce_write(B, s));
+    return LSNIF_OK;
 }
 
 }  // extern "C"

@@ -1177,6 +1177,27 @@ struct BroadArgs {
     uint32_t *pair_ray, *pair_inst;
 };
 
+// ------------------------------------------------------------------ bounce rays
+struct BounceArgs {
+    const float4 *rays;       // the rays just answered (world space)
+    const lsnif_hit *hits;    // their nearest hits
+    uint32_t n;
+    uint32_t seed, bounce;
+    float eps;                // offset of the new origin along the facing normal
+    uint32_t *offsets;        // [n + 1]: 1 per hit, then their exclusive scan
+    float4 *next;             // new rays, compacted in the order of their parents
+    uint32_t *parent;         // index of each new ray's parent
+};
+
+// PCG hash (Jarzynski and Olano 2020, "Hash Functions for GPU Rendering"): a
+// 32-bit counter-based generator, one permuted congruential step of the input.
+__device__ __forceinline__ uint32_t pcg_hash(uint32_t v)
+{
+    const uint32_t state = v * 747796405u + 2891336453u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
 // ------------------------------------------------------------------ voxel walk
 // RECHECK: some object of the launch asks for the float64 re-decision of grazing voxels.
 template <bool PAIRS, bool RECHECK>

@@ -31,6 +31,11 @@ hipError_t launch_gather_only(const QueryArgs &A, int feat_dtype, int F, float *
 struct BroadArgs;
 hipError_t launch_broad_count(const BroadArgs &B, hipStream_t s);
 hipError_t launch_broad_write(const BroadArgs &B, hipStream_t s);
+// Bounce rays: 1 per hit into B.offsets (and 0 at offsets[n]); after their exclusive scan,
+// the new rays and their parents.
+struct BounceArgs;
+hipError_t launch_bounce_mark(const BounceArgs &B, hipStream_t s);
+hipError_t launch_bounce_write(const BounceArgs &B, hipStream_t s);
 // In-place exclusive scan of n counters; `part` holds (n + 1023) / 1024 partial sums.
 hipError_t launch_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *part, hipStream_t s);
 struct PairPlan;

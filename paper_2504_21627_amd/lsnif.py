@@ -110,6 +110,8 @@ def load():
                                       C.POINTER(lsnif_debug_bufs), C.c_void_p]
     lib.lsnif_query_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
                                       C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
+    lib.lsnif_bounce.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_float,
+                                 C.c_void_p, C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32), C.c_void_p]
     lib.lsnif_gather_ceiling.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
     lib.lsnif_broad_phase.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
                                       C.c_void_p, C.c_uint32, C.POINTER(C.c_uint32), C.c_void_p]
@@ -145,7 +147,7 @@ def load():
                  "lsnif_serve_poll", "lsnif_serve_wait", "lsnif_serve_cancel", "lsnif_serve_stats_get",
                  "lsnif_serve_stop", "lsnif_graph_query", "lsnif_graph_pairs", "lsnif_graph_launch",
                  "lsnif_get_tuning", "lsnif_set_tuning", "lsnif_autotune", "lsnif_autotune_pairs",
-                 "lsnif_broad_phase", "lsnif_query_scene", "lsnif_gather_ceiling"):
+                 "lsnif_broad_phase", "lsnif_query_scene", "lsnif_gather_ceiling", "lsnif_bounce"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -271,6 +273,21 @@ def lsnif_query_pairs(ctx, rays, pair_ray, pair_inst, inst, out, stream=None):
                                     C.c_void_p(pair_inst.data_ptr() if m else 0), m,
                                     C.c_void_p(inst.data_ptr() if k else 0), k,
                                     C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+
+
+def lsnif_bounce(ctx, rays, hits, seed, bounce, eps, next_rays, parent, stream=None):
+    """Diffuse bounce rays of the rays with a hit, compacted into ``next_rays`` (m, 8) float32
+    and ``parent`` (m,) int32 (device tensors, m = capacity); returns their number."""
+    n, cap = rays.shape[0], next_rays.shape[0]
+    assert hits.shape[0] >= n and parent.shape[0] == cap
+    cnt = C.c_uint32()
+    st = load().lsnif_bounce(ctx, C.c_void_p(rays.data_ptr() if n else 0), C.c_void_p(hits.data_ptr() if n else 0),
+                             n, seed, bounce, eps, C.c_void_p(next_rays.data_ptr() if cap else 0),
+                             C.c_void_p(parent.data_ptr() if cap else 0), cap, C.byref(cnt), _stream_handle(stream))
+    global lsnif_last_pair_count
+    lsnif_last_pair_count = cnt.value
+    _check(st)
+    return cnt.value
 
 
 def lsnif_gather_ceiling(ctx, object_id, rays, sums, stream=None):

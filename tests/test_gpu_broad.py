@@ -98,3 +98,42 @@ def test_scene_query_equals_pairs_query(L, scene):
         assert np.all(np.abs(t[both] - o["t"][both]) <= 1e-3 * np.maximum(np.abs(o["t"][both]), 1.0))
     finally:
         L.lsnif_destroy(ctx)
+
+
+def test_bounce_matches_oracle(L, scene):
+    """Bounce rays from the scene query's hits: the same parents, bit-identical origins and
+    directions within a few float32 ulps of the oracle's (the device's and libm's cos and sin
+    differ in the last bits)."""
+    import torch
+    objs, insts, boxes, rays_np = scene
+    ctx = L.lsnif_create(0)
+    try:
+        ids, inst, rays = setup(L, ctx, objs, insts, rays_np)
+        n = len(rays_np)
+        hits = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+        L.lsnif_query_scene(ctx, rays, inst, hits)
+        torch.cuda.synchronize()
+        h = hits.cpu().numpy()
+        hit = h[:, 0].view(np.uint32).copy()
+        assert hit.sum() > 100
+        nxt = torch.full((n, 8), float("nan"), dtype=torch.float32, device="cuda")
+        par = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        m = L.lsnif_bounce(ctx, rays, hits, 3, 1, 1e-4, nxt, par)
+        torch.cuda.synchronize()
+        want, wpar = oracle.bounce(rays_np, hit, h[:, 1], h[:, 2:5], 3, 1, 1e-4)
+        assert m == len(want)
+        assert np.array_equal(par[:m].cpu().numpy().astype(np.uint32), wpar)
+        g = nxt[:m].cpu().numpy()
+        assert np.array_equal(g[:, :3].view(np.uint32), want[:, :3].view(np.uint32))
+        # |lx|, |ly| <= 1 carry the two libraries' cos/sin differences (a few ulps, ~2.4e-7
+        # each), and the basis products and the two sums of each component add four
+        # roundings of values <= 1: 8e-7 bounds the component difference
+        assert np.abs(g[:, 3:6] - want[:, 3:6]).max() <= 8e-7
+        assert np.array_equal(g[:, 6:].view(np.uint32), want[:, 6:].view(np.uint32))
+        assert torch.isnan(nxt[m:]).all()
+        small = torch.zeros((4, 8), dtype=torch.float32, device="cuda")
+        with pytest.raises(L.LsnifError) as e:
+            L.lsnif_bounce(ctx, rays, hits, 3, 1, 1e-4, small, par[:4].clone())
+        assert e.value.status == L.LSNIF_E_NOMEM and L.lsnif_last_pair_count == m
+    finally:
+        L.lsnif_destroy(ctx)
