@@ -102,8 +102,10 @@ typedef struct {
  *  H              cap on boundary points per ray (even, 2..64); a ray uses
  *                 the entry and exit point of its first H/2 occupied voxels.
  *  n_hidden,width hidden layers and their width; the query kernels are built
- *                 for width 64 (lsnif_build returns LSNIF_E_INVALID for other widths;
- *                 lsnif_desc_bytes accounts any width).
+ *                 for widths 64 and 128 (the paper's), the matrix-core ones of
+ *                 width 128 for at most 32 inputs per point (L x F, F = 3
+ *                 counted as 4); lsnif_build returns LSNIF_E_INVALID otherwise,
+ *                 lsnif_desc_bytes accounts any width.
  *  act, leaky_slope  hidden activation.
  *  n_mat, has_albedo output heads: [occlusion, t, normal x3, (albedo x3),
  *                 material x n_mat], so 5 + 3*has_albedo + n_mat outputs.
@@ -180,6 +182,13 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *desc, uint32_t
 lsnif_status lsnif_release(lsnif_ctx *ctx, uint32_t object_id);
 /* Device bytes held by a built object (including layout padding). */
 lsnif_status lsnif_object_bytes(lsnif_ctx *ctx, uint32_t object_id, uint64_t *bytes);
+
+/* Direct calls (lsnif_query, _query_debug, _query_pairs, _query_scene,
+ * _broad_phase, _bounce, _gather_ceiling) keep their scratch arrays in
+ * workspaces of the context, grown on demand and reused by the next call: two
+ * such calls enqueued on different streams must not overlap on the device
+ * (order them, or use graphs or the serving loop, which own their
+ * workspaces).  Calls on one stream are ordered by the stream. */
 
 /* Query n rays (object space) against one object: out[i] answers rays[i]. */
 lsnif_status lsnif_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays,
