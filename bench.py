@@ -322,6 +322,29 @@ def bench_c5(L, n_requests, seed=7):
     }
 
 
+def bench_small(L, reps=200):
+    """Per-call latency of small batches on the c2 object (FP16): a consumer that queries a
+    few rays at a time, like an intersection shader calling one LSNIF per ray, against the
+    batched path.  Each size is queried `reps` times on one stream; HIP events per call."""
+    import torch
+    import workloads as W
+    obj = W.configs.c2_object()
+    rays_all = W.configs.subsample(W.configs.c2_rays(), 1 << 16, seed=77)
+    rays = torch.from_numpy(rays_all).cuda()
+    out = torch.empty((len(rays_all), 6), dtype=torch.float32, device="cuda")
+    ctx = L.lsnif_create(0)
+    res = {"workload": "c2's object (FP16), batches of 1..65,536 rays drawn from c2's ray mix"}
+    try:
+        oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp16", "fp16"))
+        for n in (1, 32, 256, 4096, 65536):
+            wall, lat, _, _, _ = time_calls(L, ctx, lambda st: L.lsnif_query(ctx, oid, rays[:n], out, st), reps, 10)
+            res[str(n)] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                           "mrays_s": n * reps / wall / 1e6}
+    finally:
+        L.lsnif_destroy(ctx)
+    return res
+
+
 def bench_p1(L, steps, warmup, tune):
     """The paper's default object shape (width-128 leaky-ReLU MLP, albedo head, F = 3, two
     face-aligned levels) and its low-quality variant (width 64, H = 10), FP16 features and
@@ -462,9 +485,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--only", choices=["fp16", "fp32"], default=None,
                     help="time one path only (for profiling)")
-    ap.add_argument("--legs", default="c2,c4,c5,p1",
+    ap.add_argument("--legs", default="c2,c4,c5,p1,small",
                     help="comma list: c2 (headline), c4 (batched objects), c5 (serving), "
-                         "p1 (the paper's default object shape)")
+                         "p1 (the paper's default object shape), small (latency of small batches)")
     ap.add_argument("--c5-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="keep the default tuning (no autotuner)")
     ap.add_argument("--tuning", default=None,
@@ -499,6 +522,8 @@ def main():
         rec["batched_c4"] = bench_c4(L, max(args.steps // 10, 5), min(args.warmup, 3), not args.no_tune)
     if "c5" in legs:
         rec["serving_c5"] = bench_c5(L, args.c5_requests)
+    if "small" in legs:
+        rec["small_batches"] = bench_small(L)
     if "p1" in legs:
         rec["paper_default_p1"] = bench_p1(L, max(args.steps // 4, 5), min(args.warmup, 3), not args.no_tune)
     if not args.no_cpu and "c2" in legs:
