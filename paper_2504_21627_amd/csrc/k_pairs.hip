@@ -2,8 +2,8 @@
 //
 // Before the query kernel, the (ray, instance) pairs are grouped by object
 // and, within an object, by direction octant and the cell (2^b per axis,
-// b <= 4 chosen per object) of the segment start in that object's voxel grid (a counting sort with wave-aggregated
-// atomics).  Each object's run is padded to whole 256-slot tiles, so every
+// b <= 5 chosen per object) of the segment start in that object's voxel grid
+// (a counting sort with wave-aggregated atomics).  Each object's run is padded to whole 256-slot tiles, so every
 // workgroup of the query kernel serves one object with one set of weights.
 // Pairs whose ray misses the object's box, or that name a ray, instance or
 // object that does not exist, are dropped here.
@@ -34,15 +34,16 @@ __global__ __launch_bounds__(kBlock) void k_pairs_init(PairPlan P)
 __global__ __launch_bounds__(kBlock) void k_pairs_fill(PairPlan P)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < P.n_objs * kPairBins) P.hist[i] = 0u;
+    if (i < P.n_objs * P.bins) P.hist[i] = 0u;
     if (i < P.n_slots) P.slot_pair[i] = 0xffffffffu;
     if (i < P.n_tiles) P.tile_obj[i] = -1;
 }
 
-__device__ __forceinline__ uint32_t spread4(uint32_t x)
+// The low 5 bits of x spread to every third bit (one axis of a Morton code).
+__device__ __forceinline__ uint32_t spread5(uint32_t x)
 {
-    x &= 15u;
-    return (x & 1u) | ((x & 2u) << 2) | ((x & 4u) << 4) | ((x & 8u) << 6);
+    x &= 31u;
+    return (x & 1u) | ((x & 2u) << 2) | ((x & 4u) << 4) | ((x & 8u) << 6) | ((x & 16u) << 8);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pairs_keys(PairPlan P)
@@ -71,7 +72,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs_keys(PairPlan P)
                     }
                     const uint32_t oct = (w.d[0] < 0.0f ? 1u : 0u) | (w.d[1] < 0.0f ? 2u : 0u) |
                                          (w.d[2] < 0.0f ? 4u : 0u);
-                    bin = o * kPairBins + ((oct << 12) | spread4(c[0]) | (spread4(c[1]) << 1) | (spread4(c[2]) << 2));
+                    bin = o * P.bins +
+                          ((oct << (3u * P.bits)) | spread5(c[0]) | (spread5(c[1]) << 1) | (spread5(c[2]) << 2));
                 }
             }
         }
@@ -80,34 +82,52 @@ __global__ __launch_bounds__(kBlock) void k_pairs_keys(PairPlan P)
     (void)wave_aggregated_add(P.hist, bin, bin != 0xffffffffu);
 }
 
-// Block o: exclusive scan of object o's kPairBins counters in place; total to obj_total[o].
+// Block o: exclusive scan of object o's P.bins counters in place, total to
+// obj_total[o].  The counters go in chunks of kScanChunk (each thread 8
+// consecutive, two 16-byte loads): per-thread sums, a wave scan with lane
+// shuffles, the four wave totals through LDS, and a carry between chunks.
+constexpr uint32_t kScanPer = 8, kScanChunk = kScanPer * kBlock;
+
 __global__ __launch_bounds__(kBlock) void k_pairs_scan_obj(PairPlan P)
 {
-    __shared__ uint32_t tmp[kBlock];
-    constexpr uint32_t per = kPairBins / kBlock;
-    uint32_t *h = P.hist + (size_t)blockIdx.x * kPairBins;
-    const uint32_t t = threadIdx.x;
-    uint32_t v[per], sum = 0;
+    __shared__ uint32_t wsum[kBlock / 64];
+    uint32_t *h = P.hist + (size_t)blockIdx.x * P.bins;
+    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < P.bins; base += kScanChunk) {
+        uint4 *p = reinterpret_cast<uint4 *>(h + base + t * kScanPer);
+        const uint4 a = p[0], b = p[1];
+        const uint32_t v[kScanPer] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+        uint32_t s = 0;
 #pragma unroll
-    for (uint32_t q = 0; q < per; ++q) {
-        v[q] = h[t * per + q];
-        sum += v[q];
-    }
-    tmp[t] = sum;
-    __syncthreads();
-    for (uint32_t off = 1; off < kBlock; off <<= 1) {
-        const uint32_t u = t >= off ? tmp[t - off] : 0u;
-        __syncthreads();
-        tmp[t] += u;
-        __syncthreads();
-    }
-    uint32_t run = tmp[t] - sum;
-    if (t == kBlock - 1) P.obj_total[blockIdx.x] = tmp[t];
+        for (uint32_t q = 0; q < kScanPer; ++q) s += v[q];
+        uint32_t inc = s;
 #pragma unroll
-    for (uint32_t q = 0; q < per; ++q) {
-        h[t * per + q] = run;
-        run += v[q];
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o, 64);
+            if (lane >= (uint32_t)o) inc += u;
+        }
+        if (lane == 63) wsum[wv] = inc;
+        __syncthreads();
+        uint32_t run = carry + inc - s, chunk = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kBlock / 64; ++k) {
+            const uint32_t x = wsum[k];
+            run += k < wv ? x : 0u;
+            chunk += x;
+        }
+        __syncthreads();   // wsum is rewritten by the next chunk
+        uint32_t out[kScanPer];
+#pragma unroll
+        for (uint32_t q = 0; q < kScanPer; ++q) {
+            out[q] = run;
+            run += v[q];
+        }
+        p[0] = make_uint4(out[0], out[1], out[2], out[3]);
+        p[1] = make_uint4(out[4], out[5], out[6], out[7]);
+        carry += chunk;
     }
+    if (t == 0) P.obj_total[blockIdx.x] = carry;
 }
 
 // One block: object runs padded to whole tiles, their offsets, and each tile's object.
@@ -133,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs_scatter(PairPlan P)
     const uint32_t bin = p < P.n_pairs ? P.keys[p] : 0xffffffffu;
     const bool live = bin != 0xffffffffu;
     const uint32_t within = wave_aggregated_add(P.hist, bin, live);
-    if (live) P.slot_pair[P.obj_off[bin / kPairBins] + within] = p;
+    if (live) P.slot_pair[P.obj_off[bin / P.bins] + within] = p;
 }
 
 __global__ __launch_bounds__(kBlock) void k_pairs_payload(PairPlan P)
@@ -162,7 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs_payload(PairPlan P)
 
 hipError_t launch_pairs_prepare(const PairPlan &P, hipStream_t s)
 {
-    const uint32_t nfill = P.n_objs * kPairBins > P.n_slots ? P.n_objs * kPairBins : P.n_slots;
+    const uint32_t nfill = P.n_objs * P.bins > P.n_slots ? P.n_objs * P.bins : P.n_slots;
     hipLaunchKernelGGL(k_pairs_init, dim3((P.n_rays + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P);
     hipLaunchKernelGGL(k_pairs_fill, dim3((nfill + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P);
     if (P.n_pairs == 0) return hipGetLastError();

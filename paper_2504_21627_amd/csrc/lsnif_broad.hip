@@ -102,7 +102,7 @@ lsnif_status lsnif_query_scene(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
     B.pair_ray = static_cast<uint32_t *>(ctx->sws);
     B.pair_inst = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->sws) + al256((size_t)total * 4));
     HIP_TRY(launch_broad_write(B, s));
-    if ((st = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, total, ps.n_objs, ps.maxH >> 1))))
+    if ((st = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, total, ps.n_objs, ps.maxH >> 1, ps.pair_bits))))
         return st;
     return enqueue_pairs(ctx, ps, d_rays, n_rays, B.pair_ray, B.pair_inst, total, d_inst, n_inst, d_out, s, ctx->pws);
 }

@@ -44,7 +44,7 @@ struct Geom {
     uint32_t aligned_mask;    // bit l: R % V == 0, the crossing-axis weight is 0 or 1
     uint32_t recheck;         // 1: grazing voxels of the walk are re-decided in float64
     uint32_t sort_bits;       // coherence sort of single-object batches: 2^bits cells per axis (0 = no sort, <= 6)
-    uint32_t pair_bits;       // grouping of pairs within an object: 2^bits cells per axis (<= 4)
+    uint32_t pair_bits;       // grouping of pairs within an object: 2^bits cells per axis (<= 5)
     uint32_t hot_mask;        // bit l: level l is copied into LDS for the launch (hot level)
     uint32_t hot_bytes;       // LDS bytes of the hot levels
     uint32_t hot_off[kMaxLevels], hot_len[kMaxLevels];   // LDS byte offset, bytes copied (multiples of 16)

@@ -97,7 +97,7 @@ lsnif_status lsnif_graph_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
     lsnif_status st = pairs_setup(ctx, ps);
     if (st) return st;
     return capture(
-        ctx, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs, ps.maxH >> 1),
+        ctx, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs, ps.maxH >> 1, ps.pair_bits),
         [&](hipStream_t s, void *ws) {
             return enqueue_pairs(ctx, ps, d_rays, n_rays, d_pair_ray, d_pair_inst, n_pairs, d_inst, n_inst, d_out,
                                  s, ws);

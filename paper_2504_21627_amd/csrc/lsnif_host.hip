@@ -518,7 +518,7 @@ lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
     PairsSetup ps;
     lsnif_status st = pairs_setup(ctx, ps);
     if (st) return st;
-    if ((st = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs, ps.maxH >> 1))))
+    if ((st = grow_workspace(ctx->pws, ctx->pws_bytes, pairs_ws_bytes(n_rays, n_pairs, ps.n_objs, ps.maxH >> 1, ps.pair_bits))))
         return st;
     return enqueue_pairs(ctx, ps, d_rays, n_rays, d_pair_ray, d_pair_inst, n_pairs, d_inst, n_inst, d_out,
                          static_cast<hipStream_t>(stream), ctx->pws);
@@ -641,11 +641,11 @@ size_t query_ws_bytes(uint32_t n, uint32_t sort_bits, uint32_t cap)
     return sort_ws_bytes(n, sort_bits) + list_ws_bytes(n, cap);
 }
 
-size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs, uint32_t cap)
+size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs, uint32_t cap, uint32_t pair_bits)
 {
     const size_t n_slots = (size_t)(n_pairs + kBlock - 1) / kBlock * kBlock + (size_t)kBlock * n_objs;
     return al256((size_t)n_rays * 8) + al256((size_t)n_pairs * sizeof(PairRes)) + al256((size_t)n_pairs * 4) +
-           al256(n_slots * 4) + al256(n_slots / kBlock * 4) + al256((size_t)n_objs * kPairBins * 4) +
+           al256(n_slots * 4) + al256(n_slots / kBlock * 4) + al256((size_t)n_objs * pair_bins(pair_bits) * 4) +
            2 * al256((size_t)n_objs * 4) + list_ws_bytes(n_slots, cap);
 }
 
@@ -801,6 +801,7 @@ lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps)
     ps.hot_max = 0;
     ps.recheck = false;
     ps.walk_chunks = 1;
+    ps.pair_bits = 1;
     for (auto &kv : ctx->objects) {
         if (!same_class(kv.second, *ps.first))
             return fail(LSNIF_E_INVALID, "pair queries need every object of the context in one kernel class "
@@ -810,8 +811,13 @@ lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps)
         ps.hot_max = std::max(ps.hot_max, kv.second.geom.hot_bytes);
         ps.recheck = ps.recheck || kv.second.geom.recheck;
         ps.walk_chunks = std::max(ps.walk_chunks, kv.second.walk_chunks);
+        ps.pair_bits = std::max(ps.pair_bits, kv.second.geom.pair_bits);
     }
-    return upload_table(ctx, ps.n_objs);
+    lsnif_status st = upload_table(ctx, ps.n_objs);
+    if (st) return st;
+    if ((uint64_t)ps.n_objs * pair_bins(ps.pair_bits) >= 0xffffffffull)   // pair keys are 32-bit, ~0 means dropped
+        return fail(LSNIF_E_INVALID, "object ids up to %u need pair_bits below %u", ps.n_objs - 1, ps.pair_bits);
+    return LSNIF_OK;
 }
 
 lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray *d_rays, uint32_t n_rays,
@@ -850,7 +856,9 @@ lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray
     P.tile_obj = reinterpret_cast<int32_t *>(w);
     w += al256((size_t)n_tiles * 4);
     P.hist = reinterpret_cast<uint32_t *>(w);
-    w += al256((size_t)n_objs * kPairBins * 4);
+    P.bits = ps.pair_bits;
+    P.bins = pair_bins(ps.pair_bits);
+    w += al256((size_t)n_objs * P.bins * 4);
     P.obj_total = reinterpret_cast<uint32_t *>(w);
     w += al256((size_t)n_objs * 4);
     P.obj_off = reinterpret_cast<uint32_t *>(w);

@@ -71,7 +71,7 @@ constexpr uint32_t kSortMin = 8192;
 // Workspace bytes of one query of n rays, and of one pair query; cap is the
 // longest voxel list (H / 2, the largest over the objects for pairs).
 size_t query_ws_bytes(uint32_t n, uint32_t sort_bits, uint32_t cap);
-size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs, uint32_t cap);
+size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs, uint32_t cap, uint32_t pair_bits);
 
 }  // namespace lsnif
 
@@ -119,6 +119,7 @@ struct PairsSetup {
     uint32_t hot_max = 0;   // largest hot-level LDS footprint of the objects
     bool recheck = false;   // some object re-decides grazing voxels in float64
     uint32_t walk_chunks = 1;   // largest walk_chunks of the objects
+    uint32_t pair_bits = 1;     // finest pair grouping of the objects
     uint32_t n_objs = 0;
 };
 lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps);

@@ -4,7 +4,11 @@
 
 namespace lsnif {
 
-constexpr uint32_t kPairBins = 32768;  // per object: 8 octants x 16^3 cells (coarser grids use a subset)
+// Counters per object of the pair grouping at 2^bits cells per axis: 8 octants x cells^3,
+// at least 4096 (the per-object scan works in chunks of 2048).  A query uses the finest
+// pair_bits of its objects (coarser objects use a subset of their bins).
+constexpr uint32_t kMaxPairBits = 5;
+__host__ __device__ inline uint32_t pair_bins(uint32_t bits) { return 8u << (3u * (bits < 3u ? 3u : bits)); }
 
 struct PairPlan {
     const float4 *rays;
@@ -22,7 +26,8 @@ struct PairPlan {
     uint32_t *keys;                  // [n_pairs] bin of each pair, or 0xffffffff if dropped
     uint32_t *slot_pair;             // [n_slots]
     int32_t *tile_obj;               // [n_tiles]
-    uint32_t *hist;                  // [n_objs * kPairBins]
+    uint32_t *hist;                  // [n_objs * bins]
+    uint32_t bins, bits;             // pair_bins(bits) counters per object; bits = the finest pair_bits
     uint32_t *obj_total, *obj_off;   // [n_objs]
     uint32_t n_slots, n_tiles;       // n_tiles * 256 == n_slots
 };

@@ -258,14 +258,14 @@ private:
             if (r.n_pairs && (!r.d_pair_ray || !r.d_pair_inst || !r.d_inst))
                 return fail(LSNIF_E_INVALID, "pair buffers are NULL");
             if (dry_) {
-                need = pairs_ws_bytes(r.n_rays, r.n_pairs, r.n_inst + 1, kMaxList);
+                need = pairs_ws_bytes(r.n_rays, r.n_pairs, r.n_inst + 1, kMaxList, 4);   // the default grouping
                 return LSNIF_OK;
             }
             std::lock_guard<std::recursive_mutex> g(ctx_->mu);
             PairsSetup ps;
             lsnif_status st = pairs_setup(ctx_, ps);
             if (st) return st;
-            need = pairs_ws_bytes(r.n_rays, r.n_pairs, ps.n_objs, ps.maxH >> 1);
+            need = pairs_ws_bytes(r.n_rays, r.n_pairs, ps.n_objs, ps.maxH >> 1, ps.pair_bits);
             return LSNIF_OK;
         }
         uint32_t bits = 5, cap = kMaxList;   // dry runs: the default resolution, the longest lists

@@ -55,6 +55,8 @@ def test_single_object_tunings_agree(L):
                 L.lsnif_set_tuning(ctx, oid, 7, 4, 0)
             with pytest.raises(L.LsnifError):
                 L.lsnif_set_tuning(ctx, oid, 5, 4, 0, 17)
+            with pytest.raises(L.LsnifError):
+                L.lsnif_set_tuning(ctx, oid, 5, 6, 0)
             L.lsnif_release(ctx, oid)
     finally:
         L.lsnif_destroy(ctx)
@@ -73,9 +75,10 @@ def test_pair_tunings_agree(L):
         pr = torch.arange(len(rays_np), dtype=torch.int32, device="cuda")
         pi = torch.from_numpy(owner.astype(np.int32)).cuda()
         ref = None
-        for pb, hot, ch in ((4, 40960, 1), (2, 0, 4), (3, 20480, 16)):
-            for i in ids:
-                L.lsnif_set_tuning(ctx, i, 5, pb, hot, ch)
+        # pb None: the objects alternate between the finest and a coarse grouping
+        for pb, hot, ch in ((4, 40960, 1), (2, 0, 4), (3, 20480, 16), (5, 0, 1), (1, 0, 2), (None, 0, 1)):
+            for k, i in enumerate(ids):
+                L.lsnif_set_tuning(ctx, i, 5, pb if pb is not None else (5 if k % 2 else 2), hot, ch)
             out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
             L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out)
             torch.cuda.synchronize()
@@ -87,7 +90,7 @@ def test_pair_tunings_agree(L):
         out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
         best = L.lsnif_autotune_pairs(ctx, rays, pr, pi, inst, out)
         print("pairs autotuned", best, flush=True)
-        assert best["pair_bits"] in (2, 3, 4) and best["walk_chunks"] in (1, 2, 4, 8)
+        assert best["pair_bits"] in (2, 3, 4, 5) and best["walk_chunks"] in (1, 2, 4, 8)
         L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out)
         torch.cuda.synchronize()
         assert np.array_equal(bits(out), ref)
