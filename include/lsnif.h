@@ -425,6 +425,78 @@ lsnif_status lsnif_serve_stats_get(lsnif_ctx *ctx, lsnif_serve_stats *stats);
 /* Waits for admitted requests, cancels waiting ones, stops the loop. */
 lsnif_status lsnif_serve_stop(lsnif_ctx *ctx);
 
+/* ------------------------------------------------------------------ training
+ * Joint optimisation of an object's hash-grid tables and MLP weights with
+ * Adam (Sec. 5.2) under the per-signal activations and losses of Sec. 5.3.
+ *
+ * A trainer works on an object of the context built with FP32 features and an
+ * FP32 MLP, in place: the object's device tables and weights ARE the trained
+ * parameters, so the object answers lsnif_query with the current parameters
+ * between steps (a query and a step in flight at once race).  The trainer
+ * adds, on the device, one gradient, one first-moment and one second-moment
+ * buffer per parameter (3 x the object's table and weight bytes) and a
+ * per-step workspace that grows with the batch (about 4 (in_dim + 4 width +
+ * 2 outputs) + 4 H/2 + 1 bytes per ray).
+ *
+ * Loss of one training batch of n rays: (1/n) sum over the rays of
+ *   softplus(z0) - y.hit z0                                  occlusion: sigmoid + binary cross-entropy
+ *   + y.hit * ( |sigmoid(z1) - tau|                          local hit distance: sigmoid + mean absolute error
+ *             + 1 - <zn, y.n> / max(|zn|, 1e-8)              normal: identity + cosine similarity
+ *             + mean_c (a_c - y.albedo_c)^2 / (a'_c + 0.01)^2   albedo (objects with the head):
+ *                                                            a = sigmoid(z_a), a' = a held constant
+ *                                                            (relative L2 of Lehtinen et al. 2018)
+ *             + logsumexp(zm) - zm[y.material] )             material: softmax + categorical cross-entropy
+ * where z are the object's raw network outputs for the ray (zn = z2..z4,
+ * z_a the albedo outputs, zm the material logits), tau = (y.t - ta) /
+ * (tb - ta) clamped to [0, 1] over the ray's AABB interval [ta, tb], and a
+ * ray with no listed voxel adds nothing (its network input is zero and a query
+ * calls it a miss without running the network).  The non-occlusion terms are
+ * zero when the reference says miss, as the paper prescribes.  |x| at 0 and
+ * the activation at 0 take derivative 0; the leaky slope applies below 0.
+ *
+ * Adam (Kingma and Ba 2015), per parameter, step t = 1, 2, ...:
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+ * over every table entry and weight (dense), moments starting at 0.  The
+ * paper's setting is lr 0.01 with batches of 2^18 rays. */
+typedef struct lsnif_trainer lsnif_trainer;
+
+/* Reference signals of one training ray (from ray casting the true geometry). */
+typedef struct {
+    uint32_t hit;        /* 1: the ray hits the object, at parameter t of the ray */
+    float t;
+    float n[3];          /* unit shading normal at the hit */
+    float albedo[3];     /* read when the object has an albedo head */
+    int32_t material;    /* 0 .. n_mat - 1 */
+} lsnif_train_target;    /* 36 bytes */
+
+typedef struct {
+    float lr, beta1, beta2, eps;
+} lsnif_adam_cfg;
+
+/* Creates a trainer for object_id (FP32 features and MLP, else
+ * LSNIF_E_INVALID); cfg NULL means lr 0.01, b1 0.9, b2 0.999, eps 1e-8.  The
+ * object must outlive the trainer. */
+lsnif_status lsnif_trainer_create(lsnif_ctx *ctx, uint32_t object_id, const lsnif_adam_cfg *cfg, lsnif_trainer **out);
+/* Waits for the device and frees the trainer's buffers; the object keeps its
+ * trained parameters. */
+void lsnif_trainer_destroy(lsnif_trainer *tr);
+/* Forward pass, loss and backward pass of one batch (device buffers, n >= 1):
+ * the gradients of the batch loss replace the trainer's gradients and the loss
+ * goes to d_loss[0] (device float).  Asynchronous on `stream`. */
+lsnif_status lsnif_train_grads(lsnif_trainer *tr, const lsnif_ray *d_rays, const lsnif_train_target *d_gt,
+                               uint32_t n, float *d_loss, void *stream);
+/* One Adam step with the trainer's current gradients.  Asynchronous. */
+lsnif_status lsnif_train_apply(lsnif_trainer *tr, void *stream);
+/* lsnif_train_grads then lsnif_train_apply: one training step. */
+lsnif_status lsnif_train_step(lsnif_trainer *tr, const lsnif_ray *d_rays, const lsnif_train_target *d_gt,
+                              uint32_t n, float *d_loss, void *stream);
+/* Host copies of the parameters and gradients (synchronises the device; any
+ * pointer may be NULL): tables as [L][2^log2_T][F], weights per layer
+ * row-major [out][in] as in lsnif_object_desc; *steps = Adam steps taken. */
+lsnif_status lsnif_trainer_read(lsnif_trainer *tr, float *tables, float *const *W, float *grad_tables,
+                                float *const *grad_W, uint64_t *steps);
+
 /* Kernel timing.  While enabled, every query on the context records HIP
  * events on its stream before the coherence sort (pair queries: the pair
  * preparation), before the voxel-walk kernel, before the query kernel and

@@ -1,0 +1,281 @@
+// Training step kernels: the encoding and its transpose, the layer products of
+// the forward and backward passes, the per-signal losses and Adam.
+//
+// Everything is float32 (the FP32 object's own tables and weights are the
+// parameters).  The voxel lists come from the query path's walk kernel, and
+// the boundary points, cells and table slots from the same device functions,
+// so a training ray sees exactly the encoding inputs a query sees.
+#include "lsnif_kernels.hpp"
+#include "lsnif_launch.hpp"
+#include "lsnif_train.hpp"
+
+namespace lsnif {
+
+__global__ __launch_bounds__(kBlock) void k_train_fill(float *a, uint64_t na, float *b, uint64_t nb, double *acc)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < na + nb; i += stride) {
+        if (i < na) a[i] = 0.0f;
+        else b[i - na] = 0.0f;
+    }
+    if (acc && blockIdx.x == 0 && threadIdx.x == 0) *acc = 0.0;
+}
+
+// Thread = (ray r, boundary point h).  Forward: the point's L x F features,
+// trilinear over the 8 corners of its cell on every level (corners of weight
+// 0 included), into x[r][(h L + l) F + f]; points past the ray's list get 0.
+// Backward: d loss / d table entry += corner weight x dx for every corner of
+// non-zero weight (float atomics; the order of the additions is not fixed).
+template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainEncArgs A)
+{
+    const Geom &g = A.g;
+    const uint32_t H = (uint32_t)g.H, L = (uint32_t)g.L, F = (uint32_t)g.F, LF = L * F;
+    const uint64_t idx = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t r = idx / H;
+    const uint32_t h = (uint32_t)(idx - r * H);
+    if (r >= A.n) return;
+    float *x = A.x + (size_t)r * H * LF + (size_t)h * LF;
+    const uint32_t nv = A.nvox[r];
+    if (h >= 2u * nv) {
+        if constexpr (!BWD)
+            for (uint32_t q = 0; q < LF; ++q) x[q] = 0.0f;
+        return;
+    }
+    VRay w;
+    setup_ray(g, A.rays[2 * r], A.rays[2 * r + 1], w);
+    const uint32_t packed = A.lists[(size_t)(h >> 1) * A.n + r];
+    float p[3];
+    (void)boundary_point(w, packed, (h & 1u) != 0u, p);
+    const size_t T = (size_t)1 << g.log2_T;
+    for (uint32_t l = 0; l < L; ++l) {
+        uint32_t i[3];
+        float wt[3];
+        level_cell(g, (int)l, p, i, wt);
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dx[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if constexpr (BWD)
+            for (uint32_t f = 0; f < F; ++f) dx[f] = x[l * F + f];
+#pragma unroll
+        for (uint32_t c = 0; c < 8; ++c) {
+            const uint32_t bx = c & 1u, by = (c >> 1) & 1u, bz = (c >> 2) & 1u;
+            const float wx = bx ? wt[0] : 1.0f - wt[0];
+            const float wy = by ? wt[1] : 1.0f - wt[1];
+            const float wz = bz ? wt[2] : 1.0f - wt[2];
+            const float wc = (wx * wy) * wz;
+            const size_t e = ((size_t)l * T + vertex_slot(g, (int)l, i[0] + bx, i[1] + by, i[2] + bz)) * F;
+            if constexpr (!BWD) {
+                for (uint32_t f = 0; f < F; ++f) acc[f] = __builtin_fmaf(wc, A.tab[e + f], acc[f]);
+            } else {
+                if (wc != 0.0f)
+                    for (uint32_t f = 0; f < F; ++f)
+                        if (dx[f] != 0.0f) unsafeAtomicAdd(&A.gtab[e + f], wc * dx[f]);
+            }
+        }
+        if constexpr (!BWD)
+            for (uint32_t f = 0; f < F; ++f) x[l * F + f] = acc[f];
+    }
+}
+
+// Tiled float32 product, 64 x 64 outputs per 256-thread block (4 x 4 per
+// thread), K in slices of 16 staged through LDS.  Block x = row tile, y =
+// column tile, z = K chunk.  Operand tiles are loaded along whichever index
+// has unit stride, so both plain and transposed operands read contiguously.
+constexpr uint32_t kGM = 64, kGN = 64, kGK = 16;
+
+template <int EPI> __global__ __launch_bounds__(kBlock) void k_train_gemm(GemmArgs G)
+{
+    __shared__ float As[kGK][kGM + 4];
+    __shared__ float Bs[kGK][kGN + 4];
+    const uint32_t tid = threadIdx.x, tx = tid & 15u, ty = tid >> 4;
+    const uint64_t i0 = (uint64_t)blockIdx.x * kGM;
+    const uint32_t j0 = blockIdx.y * kGN;
+    const uint64_t kb = (uint64_t)blockIdx.z * G.kchunk;
+    const uint64_t ke = kb + G.kchunk < G.K ? kb + G.kchunk : G.K;
+    const bool a_k_unit = G.sak == 1, b_j_unit = G.sbj == 1;
+    float acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0f;
+    for (uint64_t k0 = kb; k0 < ke; k0 += kGK) {
+#pragma unroll
+        for (uint32_t q = 0; q < 4; ++q) {
+            const uint32_t e = tid + q * kBlock;
+            const uint32_t ai = a_k_unit ? e >> 4 : e & 63u, ak = a_k_unit ? e & 15u : e >> 6;
+            const uint64_t gi = i0 + ai, gk = k0 + ak;
+            As[ak][ai] = (gi < G.M && gk < ke) ? G.A[gi * G.sai + gk * G.sak] : 0.0f;
+            const uint32_t bj = b_j_unit ? e & 63u : e >> 4, bk = b_j_unit ? e >> 6 : e & 15u;
+            const uint64_t gj = j0 + bj, gk2 = k0 + bk;
+            Bs[bk][bj] = (gj < G.N && gk2 < ke) ? G.B[gk2 * G.sbk + gj * G.sbj] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < kGK; ++k) {
+            float a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[k][ty * 4 + r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[k][tx * 4 + c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_fmaf(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t gi = i0 + ty * 4 + r;
+        if (gi >= G.M) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t gj = j0 + tx * 4 + c;
+            if (gj >= G.N) continue;
+            float *dst = G.C + gi * G.ldc + gj;
+            float v = acc[r][c];
+            if constexpr (EPI == kEpiAct) v = v > 0.0f ? v : v * G.slope;
+            if constexpr (EPI == kEpiActGrad) v = G.aux[gi * G.ldc + gj] > 0.0f ? v : v * G.slope;
+            if constexpr (EPI == kEpiAtomic) unsafeAtomicAdd(dst, v);
+            else *dst = v;
+        }
+    }
+}
+
+__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// Thread = ray: its loss (float64 sum over the batch) and d loss / d z.
+__global__ __launch_bounds__(kBlock) void k_train_loss(TrainLossArgs A)
+{
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    double lsum = 0.0;
+    if (r < A.n) {
+        const float *z = A.z + (size_t)r * A.ldz;
+        float *dz = A.dz + (size_t)r * A.ldz;
+        float d[kMaxOut];
+#pragma unroll
+        for (int k = 0; k < kMaxOut; ++k) d[k] = 0.0f;
+        if (A.nvox[r] > 0) {
+            VRay w;
+            setup_ray(A.g, A.rays[2 * r], A.rays[2 * r + 1], w);
+            const lsnif_train_target y = A.gt[r];
+            const float inv_n = 1.0f / (float)A.n;
+            const float yh = y.hit ? 1.0f : 0.0f;
+            // occlusion: softplus(z0) - y z0, the stable form
+            const float z0 = z[0];
+            float l = (fmaxf(z0, 0.0f) + log1pf(expf(-fabsf(z0)))) - yh * z0;
+            d[0] = sigmoidf(z0) - yh;
+            if (y.hit) {
+                // local hit distance
+                float tau = (y.t - w.ta) / (w.tb - w.ta);
+                tau = fminf(fmaxf(tau, 0.0f), 1.0f);
+                const float s1 = sigmoidf(z[1]), e1 = s1 - tau;
+                l += fabsf(e1);
+                d[1] = (e1 > 0.0f ? 1.0f : (e1 < 0.0f ? -1.0f : 0.0f)) * (s1 * (1.0f - s1));
+                // normal: 1 - cosine similarity
+                const float nn = sqrtf((z[2] * z[2] + z[3] * z[3]) + z[4] * z[4]);
+                const float dot = (z[2] * y.n[0] + z[3] * y.n[1]) + z[4] * y.n[2];
+                const float den = fmaxf(nn, 1e-8f);
+                const float cs = dot / den;
+                l += 1.0f - cs;
+                for (int b = 0; b < 3; ++b)
+                    d[2 + b] = nn > 1e-8f ? -(y.n[b] / nn - cs * (z[2 + b] / nn) / nn) : -(y.n[b] / 1e-8f);
+                uint32_t m0 = 5;
+                if (A.has_albedo) {
+                    for (int c = 0; c < 3; ++c) {
+                        const float a = sigmoidf(z[5 + c]), e = a - y.albedo[c];
+                        const float q = (a + 0.01f) * (a + 0.01f);
+                        l += (e * e / q) / 3.0f;
+                        d[5 + c] = ((2.0f * e / q) / 3.0f) * (a * (1.0f - a));
+                    }
+                    m0 = 8;
+                }
+                if (y.material >= 0 && (uint32_t)y.material < A.n_mat) {
+                    float mx = z[m0];
+                    for (uint32_t k = 1; k < A.n_mat; ++k) mx = fmaxf(mx, z[m0 + k]);
+                    float sum = 0.0f;
+                    for (uint32_t k = 0; k < A.n_mat; ++k) sum += expf(z[m0 + k] - mx);
+                    l += (mx + logf(sum)) - z[m0 + y.material];
+                    for (uint32_t k = 0; k < A.n_mat; ++k)
+                        d[m0 + k] = expf(z[m0 + k] - mx) / sum - ((int32_t)k == y.material ? 1.0f : 0.0f);
+                }
+            }
+            lsum = (double)l;
+#pragma unroll
+            for (int k = 0; k < kMaxOut; ++k) d[k] *= inv_n;
+        }
+        for (uint32_t k = 0; k < A.out_dim; ++k) dz[k] = d[k];
+    }
+    for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+    if ((threadIdx.x & 63u) == 0 && lsum != 0.0) unsafeAtomicAdd(A.loss_acc, lsum);
+}
+
+__global__ void k_train_loss_final(const double *acc, uint32_t n, float *loss)
+{
+    if (threadIdx.x == 0) loss[0] = (float)(acc[0] / (double)n);
+}
+
+__global__ __launch_bounds__(kBlock) void k_adam(AdamArgs A)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < A.count; i += stride) {
+        const float g = A.g[i];
+        const float m = A.b1 * A.m[i] + (1.0f - A.b1) * g;
+        const float v = A.b2 * A.v[i] + (1.0f - A.b2) * (g * g);
+        A.m[i] = m;
+        A.v[i] = v;
+        A.p[i] = A.p[i] - A.lr * (m * A.c1) / (sqrtf(v * A.c2) + A.eps);
+    }
+}
+
+static uint32_t stream_blocks(uint64_t count)
+{
+    const uint64_t b = (count + kBlock - 1) / kBlock;
+    return (uint32_t)(b < 8192 ? (b ? b : 1) : 8192);
+}
+
+hipError_t launch_train_fill(float *a, uint64_t na, float *b, uint64_t nb, double *acc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_train_fill, dim3(stream_blocks(na + nb)), dim3(kBlock), 0, s, a, na, b, nb, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_encode(const TrainEncArgs &A, bool backward, hipStream_t s)
+{
+    const uint64_t threads = (uint64_t)A.n * (uint64_t)A.g.H;
+    const dim3 grid((uint32_t)((threads + kBlock - 1) / kBlock));
+    if (backward) hipLaunchKernelGGL(k_train_enc<true>, grid, dim3(kBlock), 0, s, A);
+    else hipLaunchKernelGGL(k_train_enc<false>, grid, dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_gemm(const GemmArgs &G, int epi, hipStream_t s)
+{
+    const uint64_t chunks = (G.K + G.kchunk - 1) / G.kchunk;
+    const dim3 grid((uint32_t)((G.M + kGM - 1) / kGM), (G.N + kGN - 1) / kGN, (uint32_t)(chunks ? chunks : 1));
+    switch (epi) {
+    case kEpiStore: hipLaunchKernelGGL(k_train_gemm<kEpiStore>, grid, dim3(kBlock), 0, s, G); break;
+    case kEpiAct: hipLaunchKernelGGL(k_train_gemm<kEpiAct>, grid, dim3(kBlock), 0, s, G); break;
+    case kEpiActGrad: hipLaunchKernelGGL(k_train_gemm<kEpiActGrad>, grid, dim3(kBlock), 0, s, G); break;
+    default: hipLaunchKernelGGL(k_train_gemm<kEpiAtomic>, grid, dim3(kBlock), 0, s, G); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_train_loss(const TrainLossArgs &A, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_train_loss, dim3((A.n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_loss_final(const double *acc, uint32_t n, float *loss, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_train_loss_final, dim3(1), dim3(64), 0, s, acc, n, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamArgs &A, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam, dim3(stream_blocks(A.count)), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+}  // namespace lsnif

@@ -79,6 +79,15 @@ LSNIF_REQ_QUEUED, LSNIF_REQ_RUNNING, LSNIF_REQ_DONE = 0, 1, 2
 LSNIF_REQ_SINGLE, LSNIF_REQ_PAIRS = 0, 1
 
 
+class lsnif_adam_cfg(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
+# lsnif_train_target as a numpy record: hit, t, n[3], albedo[3], material (36 bytes)
+TRAIN_TARGET = np.dtype([("hit", np.uint32), ("t", np.float32), ("n", np.float32, 3),
+                         ("albedo", np.float32, 3), ("material", np.int32)])
+
+
 class lsnif_debug_bufs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("count", "tatb", "vox_ijk", "vox_t", "vox_axis",
                                            "points", "slots", "weights", "enc", "out", "act_amax")]
@@ -141,13 +150,23 @@ def load():
     lib.lsnif_autotune_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
                                          C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
                                          C.POINTER(lsnif_tuning)]
+    lib.lsnif_trainer_create.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(lsnif_adam_cfg), C.POINTER(C.c_void_p)]
+    lib.lsnif_trainer_destroy.argtypes = [C.c_void_p]
+    lib.lsnif_trainer_destroy.restype = None
+    lib.lsnif_train_grads.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
+    lib.lsnif_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
+    lib.lsnif_train_apply.argtypes = [C.c_void_p, C.c_void_p]
+    lib.lsnif_trainer_read.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.POINTER(C.c_uint64)]
     for name in ("lsnif_create", "lsnif_desc_bytes", "lsnif_build", "lsnif_release",
                  "lsnif_object_bytes", "lsnif_query", "lsnif_query_debug", "lsnif_profile_enable",
                  "lsnif_profile_read", "lsnif_query_pairs", "lsnif_serve_start", "lsnif_serve_submit",
                  "lsnif_serve_poll", "lsnif_serve_wait", "lsnif_serve_cancel", "lsnif_serve_stats_get",
                  "lsnif_serve_stop", "lsnif_graph_query", "lsnif_graph_pairs", "lsnif_graph_launch",
                  "lsnif_get_tuning", "lsnif_set_tuning", "lsnif_autotune", "lsnif_autotune_pairs",
-                 "lsnif_broad_phase", "lsnif_query_scene", "lsnif_gather_ceiling", "lsnif_bounce"):
+                 "lsnif_broad_phase", "lsnif_query_scene", "lsnif_gather_ceiling", "lsnif_bounce",
+                 "lsnif_trainer_create", "lsnif_train_grads", "lsnif_train_step", "lsnif_train_apply",
+                 "lsnif_trainer_read"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -461,3 +480,61 @@ def hits_from(out):
     import torch
     i = out.view(torch.int32)
     return {"hit": i[:, 0], "t": out[:, 1], "normal": out[:, 2:5], "material": i[:, 5]}
+
+
+def targets_array(hit, t, n, material, albedo=None):
+    """Training targets as the (n, 9) 4-byte array lsnif_train_target expects."""
+    m = len(hit)
+    rec = np.zeros(m, TRAIN_TARGET)
+    rec["hit"] = np.asarray(hit, np.uint32)
+    rec["t"] = np.where(rec["hit"] == 1, np.asarray(t, np.float32), 0.0)
+    rec["n"] = np.asarray(n, np.float32)
+    if albedo is not None:
+        rec["albedo"] = np.asarray(albedo, np.float32)
+    rec["material"] = np.asarray(material, np.int32)
+    return rec.view(np.float32).reshape(m, 9)
+
+
+def lsnif_trainer_create(ctx, object_id, lr=0.01, beta1=0.9, beta2=0.999, eps=1e-8):
+    cfg = lsnif_adam_cfg(lr, beta1, beta2, eps)
+    h = C.c_void_p()
+    _check(load().lsnif_trainer_create(ctx, object_id, C.byref(cfg), C.byref(h)))
+    return h
+
+
+def lsnif_trainer_destroy(tr):
+    load().lsnif_trainer_destroy(tr)
+
+
+def lsnif_train_grads(tr, rays, targets, loss, stream=None):
+    """Gradients of one batch: ``rays`` (n, 8) float32, ``targets`` (n, 9) 4-byte, ``loss`` a
+    device float32 tensor that receives the batch loss."""
+    n = rays.shape[0]
+    assert targets.shape[0] == n
+    _check(load().lsnif_train_grads(tr, C.c_void_p(rays.data_ptr()), C.c_void_p(targets.data_ptr()), n,
+                                    C.c_void_p(loss.data_ptr()), _stream_handle(stream)))
+
+
+def lsnif_train_apply(tr, stream=None):
+    _check(load().lsnif_train_apply(tr, _stream_handle(stream)))
+
+
+def lsnif_train_step(tr, rays, targets, loss, stream=None):
+    n = rays.shape[0]
+    assert targets.shape[0] == n
+    _check(load().lsnif_train_step(tr, C.c_void_p(rays.data_ptr()), C.c_void_p(targets.data_ptr()), n,
+                                   C.c_void_p(loss.data_ptr()), _stream_handle(stream)))
+
+
+def lsnif_trainer_read(tr, obj):
+    """Host copies: (tables, [W_k], grad_tables, [grad_W_k], steps), shaped like ``obj``'s."""
+    tab = np.empty_like(np.asarray(obj.tables, np.float32))
+    gtab = np.empty_like(tab)
+    W = [np.empty_like(np.asarray(w, np.float32)) for w in obj.weights]
+    gW = [np.empty_like(w) for w in W]
+    Wp = (C.c_void_p * len(W))(*[w.ctypes.data for w in W])
+    gWp = (C.c_void_p * len(gW))(*[w.ctypes.data for w in gW])
+    steps = C.c_uint64()
+    _check(load().lsnif_trainer_read(tr, C.c_void_p(tab.ctypes.data), C.cast(Wp, C.c_void_p),
+                                     C.c_void_p(gtab.ctypes.data), C.cast(gWp, C.c_void_p), C.byref(steps)))
+    return tab, W, gtab, gW, steps.value
