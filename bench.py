@@ -378,6 +378,86 @@ def bench_p1(L, steps, warmup, tune):
     return res
 
 
+# FLOPs of one training ray on a fully connected network: forward, weight gradients and input
+# gradients are one multiply-add per weight each
+def train_flops_per_ray(obj):
+    return 3 * 2 * sum(int(w.shape[0]) * int(w.shape[1]) for w in obj.weights)
+
+
+def t1_batch(n=1 << 18):
+    """The training batch: generated before the GPU is touched (the ray cast runs in spawned
+    worker processes)."""
+    import workloads as W
+    from workloads import train as WT
+    obj = W.configs.paper_object(seed=0)
+    print(f"[bench] generating the t1 training batch ({n} rays, ray casting)", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    rays_np, tg = WT.batch(W.icosphere(3), obj, n, seed=31, workers=8)
+    return obj, rays_np, tg, time.perf_counter() - t0
+
+
+def bench_t1(L, steps, warmup, data, cpu=True):
+    """Training (Sec. 5.2, 5.3): the paper's default object shape with FP32 parameters, one
+    batch of 2^18 balanced rays with references from ray casting its mesh, Adam at lr 0.01."""
+    import torch
+    obj, rays_np, tg, gen_s = data
+    n = len(rays_np)
+    res = {"workload": "t1: training the paper's default object shape (c1's icosphere, V=32, levels R=64,128, "
+                       "2^17 x 3 fp32 features, H=18, MLP 108-128-128-12 leaky ReLU, albedo head, 4 materials); "
+                       "batches of 262,144 balanced rays (half from the enclosing sphere, half from the "
+                       "surface) with references from ray casting the mesh; Adam lr 0.01",
+           "rays_per_step": n, "reference_hits": int(tg["hit"].sum()), "batch_gen_s": gen_s}
+    ctx = L.lsnif_create(0)
+    try:
+        oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp32", "fp32"))
+        tr = L.lsnif_trainer_create(ctx, oid)
+        try:
+            rays = torch.from_numpy(rays_np).cuda()
+            tgt = torch.from_numpy(L.targets_array(tg["hit"], tg["t"], tg["n"], tg["material"],
+                                                   tg["albedo"])).cuda()
+            loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+            L.lsnif_train_step(tr, rays, tgt, loss)
+            torch.cuda.synchronize()
+            loss_first = float(loss.item())
+            for _ in range(warmup):
+                L.lsnif_train_step(tr, rays, tgt, loss)
+            print(f"[bench] timing t1: {warmup} warmup + {steps} steps", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                L.lsnif_train_step(tr, rays, tgt, loss)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            flops = train_flops_per_ray(obj) * n
+            res.update({"value": n / ms / 1e3, "unit": "Mrays/s trained", "ms_per_step": ms,
+                        "steps": steps, "warmup": warmup, "gflop_per_step": flops / 1e9,
+                        "layer_tflops": flops / ms / 1e9, "loss_step1": loss_first,
+                        "loss_last": float(loss.item()), "adam_steps": steps + warmup + 1})
+        finally:
+            L.lsnif_trainer_destroy(tr)
+    finally:
+        L.lsnif_destroy(ctx)
+    if cpu:
+        import oracle
+        import oracle.train as OT
+        m = 16384
+        sub = rays_np[:m]
+        tsub = {k: v[:m] for k, v in tg.items()}
+        OT.train_grads(obj, sub[:256], {k: v[:256] for k, v in tsub.items()})   # load and warm
+        t0 = time.perf_counter()
+        g = OT.train_grads(obj, sub, tsub)
+        OT.adam(obj.tables, g["gtab"], 0.0, 0.0, 1)
+        for k, w in enumerate(obj.weights):
+            OT.adam(w, g["gW"][k], 0.0, 0.0, 1)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": m / dt / 1e6, "unit": "Mrays/s trained", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"one step on the first {m} rays of the batch "
+                                                           f"(float64 numpy + the C query oracle), {dt:.2f} s wall"}
+    return res
+
+
 def bench_c2(L, args):
     """The headline: the c2 batch through the FP16 matrix-core path and the plain FP32 path."""
     import torch
@@ -485,9 +565,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--only", choices=["fp16", "fp32"], default=None,
                     help="time one path only (for profiling)")
-    ap.add_argument("--legs", default="c2,c4,c5,p1,small",
+    ap.add_argument("--legs", default="c2,c4,c5,p1,small,t1",
                     help="comma list: c2 (headline), c4 (batched objects), c5 (serving), "
-                         "p1 (the paper's default object shape), small (latency of small batches)")
+                         "p1 (the paper's default object shape), small (latency of small batches), "
+                         "t1 (training steps)")
     ap.add_argument("--c5-requests", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="keep the default tuning (no autotuner)")
     ap.add_argument("--tuning", default=None,
@@ -502,6 +583,9 @@ def main():
               "and this build runs no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
+    legs = set(args.legs.split(","))
+    t1_data = t1_batch() if "t1" in legs else None
+
     import torch
     import workloads as W
     from paper_2504_21627_amd import lsnif as L
@@ -512,7 +596,6 @@ def main():
         dst = src.clone()
         torch.cuda.synchronize()
         del src, dst
-    legs = set(args.legs.split(","))
     if "c2" in legs:
         rec, obj, rays_np = bench_c2(L, args)
     else:
@@ -526,6 +609,8 @@ def main():
         rec["small_batches"] = bench_small(L)
     if "p1" in legs:
         rec["paper_default_p1"] = bench_p1(L, max(args.steps // 4, 5), min(args.warmup, 3), not args.no_tune)
+    if "t1" in legs:
+        rec["training_t1"] = bench_t1(L, max(args.steps // 10, 5), min(args.warmup, 3), t1_data, not args.no_cpu)
     if not args.no_cpu and "c2" in legs:
         print("[bench] timing the oracle on a CPU sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(obj, rays_np, args.cpu_sample)

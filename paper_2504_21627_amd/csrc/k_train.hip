@@ -25,7 +25,14 @@ __global__ __launch_bounds__(kBlock) void k_train_fill(float *a, uint64_t na, fl
 // trilinear over the 8 corners of its cell on every level (corners of weight
 // 0 included), into x[r][(h L + l) F + f]; points past the ray's list get 0.
 // Backward: d loss / d table entry += corner weight x dx for every corner of
-// non-zero weight (float atomics; the order of the additions is not fixed).
+// non-zero weight, with float atomics into one of several copies of the
+// gradient (block b into copy b % copies: consecutive blocks go to different
+// XCDs, so each copy's lines are contended by one XCD's blocks only); the
+// copies are summed afterwards.  The order of the additions is not fixed.
+// Where a ray leaves voxel j and enters voxel j + 1 at the same point (adjacent
+// listed voxels: the same plane crossing, the same clamps), the exit point's
+// thread adds both points' gradients and the entry point's thread adds
+// nothing; each recomputes the other point, so both take the same decision.
 template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainEncArgs A)
 {
     const Geom &g = A.g;
@@ -46,6 +53,16 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
     const uint32_t packed = A.lists[(size_t)(h >> 1) * A.n + r];
     float p[3];
     (void)boundary_point(w, packed, (h & 1u) != 0u, p);
+    bool merge_next = false;
+    if constexpr (BWD) {
+        auto same = [&](uint32_t j, bool is_exit) {
+            float q[3];
+            (void)boundary_point(w, A.lists[(size_t)j * A.n + r], is_exit, q);
+            return q[0] == p[0] && q[1] == p[1] && q[2] == p[2];
+        };
+        if (!(h & 1u) && h >= 2u && same((h >> 1) - 1u, true)) return;   // added by the previous exit point
+        merge_next = (h & 1u) && h + 1u < 2u * nv && same((h + 1u) >> 1, false);
+    }
     const size_t T = (size_t)1 << g.log2_T;
     for (uint32_t l = 0; l < L; ++l) {
         uint32_t i[3];
@@ -53,7 +70,7 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
         level_cell(g, (int)l, p, i, wt);
         float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dx[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if constexpr (BWD)
-            for (uint32_t f = 0; f < F; ++f) dx[f] = x[l * F + f];
+            for (uint32_t f = 0; f < F; ++f) dx[f] = merge_next ? x[l * F + f] + x[LF + l * F + f] : x[l * F + f];
 #pragma unroll
         for (uint32_t c = 0; c < 8; ++c) {
             const uint32_t bx = c & 1u, by = (c >> 1) & 1u, bz = (c >> 2) & 1u;
@@ -62,12 +79,14 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
             const float wz = bz ? wt[2] : 1.0f - wt[2];
             const float wc = (wx * wy) * wz;
             const size_t e = ((size_t)l * T + vertex_slot(g, (int)l, i[0] + bx, i[1] + by, i[2] + bz)) * F;
+            float *gcopy = nullptr;
+            if constexpr (BWD) gcopy = A.gtab + (size_t)(blockIdx.x % A.replicas) * A.n_tab;
             if constexpr (!BWD) {
                 for (uint32_t f = 0; f < F; ++f) acc[f] = __builtin_fmaf(wc, A.tab[e + f], acc[f]);
             } else {
                 if (wc != 0.0f)
                     for (uint32_t f = 0; f < F; ++f)
-                        if (dx[f] != 0.0f) unsafeAtomicAdd(&A.gtab[e + f], wc * dx[f]);
+                        if (dx[f] != 0.0f) unsafeAtomicAdd(&gcopy[e + f], wc * dx[f]);
             }
         }
         if constexpr (!BWD)
@@ -131,12 +150,44 @@ template <int EPI> __global__ __launch_bounds__(kBlock) void k_train_gemm(GemmAr
             const uint32_t gj = j0 + tx * 4 + c;
             if (gj >= G.N) continue;
             float *dst = G.C + gi * G.ldc + gj;
+            if constexpr (EPI == kEpiPartial) dst += (uint64_t)blockIdx.z * G.M * G.ldc;
             float v = acc[r][c];
             if constexpr (EPI == kEpiAct) v = v > 0.0f ? v : v * G.slope;
             if constexpr (EPI == kEpiActGrad) v = G.aux[gi * G.ldc + gj] > 0.0f ? v : v * G.slope;
-            if constexpr (EPI == kEpiAtomic) unsafeAtomicAdd(dst, v);
-            else *dst = v;
+            *dst = v;
         }
+    }
+}
+
+// Sum of the K-chunk partials in two passes: pass 1, block (x, y) sums the
+// chunks y, y + kSumGroups, ... of its 256 entries into part2[y]; pass 2 sums
+// the kSumGroups rows into the layer's gradient.  Both read contiguously.
+__global__ __launch_bounds__(kBlock) void k_sum_partials1(const float *part, uint32_t nz, uint32_t MN, float *part2)
+{
+    const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= MN) return;
+    float s = 0.0f;
+    for (uint32_t z = blockIdx.y; z < nz; z += kSumGroups) s += part[(size_t)z * MN + e];
+    part2[(size_t)blockIdx.y * MN + e] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_partials2(const float *part2, uint32_t M, uint32_t N, float *dst,
+                                                          uint32_t ld)
+{
+    const uint32_t e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= M * N) return;
+    float s = 0.0f;
+    for (uint32_t y = 0; y < kSumGroups; ++y) s += part2[(size_t)y * M * N + e];
+    dst[(size_t)(e / N) * ld + e % N] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_copies(float *a, uint64_t n, uint32_t copies)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        float s = a[i];
+        for (uint32_t r = 1; r < copies; ++r) s += a[(size_t)r * n + i];
+        a[i] = s;
     }
 }
 
@@ -255,8 +306,24 @@ hipError_t launch_train_gemm(const GemmArgs &G, int epi, hipStream_t s)
     case kEpiStore: hipLaunchKernelGGL(k_train_gemm<kEpiStore>, grid, dim3(kBlock), 0, s, G); break;
     case kEpiAct: hipLaunchKernelGGL(k_train_gemm<kEpiAct>, grid, dim3(kBlock), 0, s, G); break;
     case kEpiActGrad: hipLaunchKernelGGL(k_train_gemm<kEpiActGrad>, grid, dim3(kBlock), 0, s, G); break;
-    default: hipLaunchKernelGGL(k_train_gemm<kEpiAtomic>, grid, dim3(kBlock), 0, s, G); break;
+    default: hipLaunchKernelGGL(k_train_gemm<kEpiPartial>, grid, dim3(kBlock), 0, s, G); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const float *part, uint32_t nz, uint32_t M, uint32_t N, float *part2, float *dst,
+                               uint32_t ld, hipStream_t s)
+{
+    const dim3 g1((M * N + kBlock - 1) / kBlock, kSumGroups);
+    hipLaunchKernelGGL(k_sum_partials1, g1, dim3(kBlock), 0, s, part, nz, M * N, part2);
+    hipLaunchKernelGGL(k_sum_partials2, dim3((M * N + kBlock - 1) / kBlock), dim3(kBlock), 0, s, part2, M, N, dst, ld);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_copies(float *a, uint64_t n, uint32_t copies, hipStream_t s)
+{
+    if (copies <= 1) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_copies, dim3(stream_blocks(n)), dim3(kBlock), 0, s, a, n, copies);
     return hipGetLastError();
 }
 

@@ -8,6 +8,11 @@
 // columns past the outputs zero).  Gradients and moments use the same layout,
 // so the head's spare columns get zero gradient and never move.
 //
+// The table gradient is accumulated with float atomics into several copies
+// (one per XCD when memory allows; contention on the entries many rays reach
+// is what bounds the scatter), summed into the first copy at the end.  Weight
+// gradients go through per-chunk partial products and a sum, no atomics.
+//
 // Activations of the backward pass overwrite the forward ones layer by layer:
 // a layer's input is read for its weight gradient, then replaced by the
 // gradient with respect to it (the derivative epilogue reads each element
@@ -15,6 +20,7 @@
 // d loss / d encoding for the scatter.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 
@@ -31,8 +37,9 @@ struct lsnif_trainer {
     lsnif_adam_cfg cfg{};
     uint64_t steps = 0;
     size_t n_tab = 0, n_w = 0;     // floats of tables and packed weights
-    float *grad = nullptr;         // [n_tab + n_w]
-    float *m = nullptr, *v = nullptr;
+    uint32_t copies = 1;           // copies of the table gradient
+    float *grad = nullptr;         // [copies x n_tab] table gradient copies, then [n_w] weight gradients
+    float *m = nullptr, *v = nullptr;   // [n_tab + n_w]
     void *ws = nullptr;
     size_t ws_bytes = 0;
 };
@@ -62,14 +69,42 @@ struct StepWs {
     float *x0;        // [n][in_dim]
     float *act[8];    // act[k] = [n][width], k = 1 .. n_hidden
     float *z, *dz;    // [n][out_dim]
+    float *part;      // partial weight-gradient products
     double *acc;
 };
+
+constexpr uint32_t kCopyBudget = 1u << 30;   // bytes for the table-gradient copies
+
+// K chunk of a weight-gradient product: enough blocks to fill the chip.
+uint32_t wgrad_chunk(uint32_t M, uint32_t N, uint32_t n)
+{
+    const uint32_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    const uint32_t want = tiles >= 2048 ? 1 : 2048 / tiles;
+    uint32_t c = (n + want - 1) / want;
+    c = (c + 15) / 16 * 16;
+    return c < 256 ? 256 : c;
+}
+
+// Floats of the largest partial-product set of the weight gradients, plus the
+// scratch of their two-pass sum.
+size_t part_floats(const Object &ob, uint32_t n)
+{
+    const uint32_t in0 = (uint32_t)(ob.geom.H * ob.geom.L * ob.geom.F), Wd = (uint32_t)ob.width;
+    size_t best = 0;
+    for (int k = 0; k <= ob.mlp.n_hidden; ++k) {
+        const uint32_t M = k == 0 ? in0 : Wd, N = k == ob.mlp.n_hidden ? (uint32_t)ob.mlp.out_dim : Wd;
+        const size_t z = (n + wgrad_chunk(M, N, n) - 1) / wgrad_chunk(M, N, n);
+        best = std::max(best, (z + kSumGroups) * M * N);
+    }
+    return best;
+}
 
 size_t step_ws_bytes(const Object &ob, uint32_t n)
 {
     const size_t in = (size_t)ob.geom.H * ob.geom.L * ob.geom.F, od = (size_t)ob.mlp.out_dim;
     return al256((size_t)n * (ob.geom.H / 2) * 4) + al256(n) + al256((size_t)n * in * 4) +
-           (size_t)ob.mlp.n_hidden * al256((size_t)n * ob.width * 4) + 2 * al256((size_t)n * od * 4) + 256;
+           (size_t)ob.mlp.n_hidden * al256((size_t)n * ob.width * 4) + 2 * al256((size_t)n * od * 4) +
+           al256(part_floats(ob, n) * 4) + 256;
 }
 
 StepWs carve(const Object &ob, uint32_t n, void *ws)
@@ -91,18 +126,10 @@ StepWs carve(const Object &ob, uint32_t n, void *ws)
     w += al256((size_t)n * od * 4);
     S.dz = reinterpret_cast<float *>(w);
     w += al256((size_t)n * od * 4);
+    S.part = reinterpret_cast<float *>(w);
+    w += al256(part_floats(ob, n) * 4);
     S.acc = reinterpret_cast<double *>(w);
     return S;
-}
-
-// K chunk of a weight-gradient product: enough blocks to fill the chip.
-uint32_t wgrad_chunk(uint32_t M, uint32_t N, uint32_t n)
-{
-    const uint32_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
-    const uint32_t want = tiles >= 2048 ? 1 : 2048 / tiles;
-    uint32_t c = (n + want - 1) / want;
-    c = (c + 15) / 16 * 16;
-    return c < 256 ? 256 : c;
 }
 
 lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays, const lsnif_train_target *d_gt,
@@ -116,8 +143,8 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
     const StepWs S = carve(ob, n, tr->ws);
     float *tab = static_cast<float *>(ob.d_tab);
     float *W = static_cast<float *>(const_cast<void *>(ob.d_w));
-    float *gtab = tr->grad, *gW = tr->grad + tr->n_tab;
-    HIP_TRY(launch_train_fill(gtab, tr->n_tab, gW, tr->n_w, S.acc, s));
+    float *gtab = tr->grad, *gW = tr->grad + tr->copies * tr->n_tab;
+    HIP_TRY(launch_train_fill(gtab, tr->copies * tr->n_tab, gW, tr->n_w, S.acc, s));
     // voxel lists: the query path's walk, rays in their given order
     QueryArgs A{};
     A.g = ob.geom;
@@ -134,6 +161,8 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
     E.nvox = S.nvox;
     E.tab = tab;
     E.gtab = gtab;
+    E.replicas = tr->copies;
+    E.n_tab = tr->n_tab;
     E.x = S.x0;
     HIP_TRY(launch_train_encode(E, false, s));
     const float slope = mlp.act == LSNIF_LEAKY_RELU ? mlp.slope : 0.0f;
@@ -184,13 +213,16 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
         Gw.B = g;
         Gw.sbk = out_dim(ku);
         Gw.sbj = 1;
-        Gw.C = gW + mlp.off[ku];
-        Gw.ldc = ld(ku);
+        Gw.C = S.part;
+        Gw.ldc = out_dim(ku);
         Gw.M = in_dim(ku);
         Gw.N = out_dim(ku);
         Gw.K = n;
         Gw.kchunk = wgrad_chunk(Gw.M, Gw.N, n);
-        HIP_TRY(launch_train_gemm(Gw, kEpiAtomic, s));
+        HIP_TRY(launch_train_gemm(Gw, kEpiPartial, s));
+        const uint32_t nz = (n + Gw.kchunk - 1) / Gw.kchunk;
+        HIP_TRY(launch_sum_partials(S.part, nz, Gw.M, Gw.N, S.part + (size_t)nz * Gw.M * Gw.N, gW + mlp.off[ku],
+                                    ld(ku), s));
         GemmArgs Gd{};   // input gradient: g x W^T, times the activation's derivative below the head's input
         Gd.A = g;
         Gd.sai = out_dim(ku);
@@ -211,6 +243,7 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
         g = dst;
     }
     HIP_TRY(launch_train_encode(E, true, s));   // E.x = x0, now d loss / d encoding
+    HIP_TRY(launch_sum_copies(gtab, tr->n_tab, tr->copies, s));
     if (d_loss) HIP_TRY(launch_train_loss_final(S.acc, n, d_loss, s));
     return LSNIF_OK;
 }
@@ -232,7 +265,7 @@ lsnif_status apply(lsnif_trainer *tr, const Object &ob, hipStream_t s)
     A.count = tr->n_tab;
     HIP_TRY(launch_adam(A, s));
     A.p = static_cast<float *>(const_cast<void *>(ob.d_w));
-    A.g = tr->grad + tr->n_tab;
+    A.g = tr->grad + tr->copies * tr->n_tab;
     A.m = tr->m + tr->n_tab;
     A.v = tr->v + tr->n_tab;
     A.count = tr->n_w;
@@ -279,8 +312,10 @@ lsnif_status lsnif_trainer_create(lsnif_ctx *ctx, uint32_t object_id, const lsni
     tr->cfg = c;
     tr->n_tab = (size_t)ob.geom.L * ((size_t)1 << ob.geom.log2_T) * ob.geom.F;
     tr->n_w = weight_floats(ob);
+    tr->copies = (uint32_t)std::max<size_t>(1, std::min<size_t>(8, kCopyBudget / (tr->n_tab * sizeof(float))));
     const size_t bytes = (tr->n_tab + tr->n_w) * sizeof(float);
-    if (hipMalloc(&tr->grad, bytes) != hipSuccess || hipMalloc(&tr->m, bytes) != hipSuccess ||
+    const size_t gbytes = (tr->copies * tr->n_tab + tr->n_w) * sizeof(float);
+    if (hipMalloc(&tr->grad, gbytes) != hipSuccess || hipMalloc(&tr->m, bytes) != hipSuccess ||
         hipMalloc(&tr->v, bytes) != hipSuccess) {
         (void)hipFree(tr->grad);
         (void)hipFree(tr->m);
@@ -288,7 +323,7 @@ lsnif_status lsnif_trainer_create(lsnif_ctx *ctx, uint32_t object_id, const lsni
         delete tr;
         return fail(LSNIF_E_NOMEM, "trainer buffers of 3 x %llu bytes", (unsigned long long)bytes);
     }
-    if (hipMemset(tr->grad, 0, bytes) != hipSuccess || hipMemset(tr->m, 0, bytes) != hipSuccess ||
+    if (hipMemset(tr->grad, 0, gbytes) != hipSuccess || hipMemset(tr->m, 0, bytes) != hipSuccess ||
         hipMemset(tr->v, 0, bytes) != hipSuccess) {
         lsnif_trainer_destroy(tr);
         return fail(LSNIF_E_DEVICE, "clearing the trainer buffers failed");
@@ -366,7 +401,7 @@ lsnif_status lsnif_trainer_read(lsnif_trainer *tr, float *tables, float *const *
     for (int which = 0; which < 2; ++which) {
         float *const *dst = which ? grad_W : W;
         if (!dst) continue;
-        const void *src = which ? static_cast<const void *>(tr->grad + tr->n_tab) : ob->d_w;
+        const void *src = which ? static_cast<const void *>(tr->grad + tr->copies * tr->n_tab) : ob->d_w;
         HIP_TRY(hipMemcpy(packed.data(), src, tr->n_w * 4, hipMemcpyDeviceToHost));
         for (int k = 0; k <= nh; ++k) {
             if (!dst[k]) continue;

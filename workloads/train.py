@@ -53,9 +53,25 @@ def materials_of(verts, tris, n_mat):
     return ((cen[:, 0] > 0).astype(np.int64) + 2 * (cen[:, 1] > 0).astype(np.int64)) % n_mat
 
 
-def targets(verts, tris, rays, n_mat, seed=0):
+def _cast_part(args):
+    return ray_cast(*args)
+
+
+def ray_cast_parallel(verts, tris, rays, workers):
+    """ray_cast over `workers` processes (spawned: they import numpy and this module only)."""
+    if workers <= 1 or len(rays) < 8192:
+        return ray_cast(verts, tris, rays)
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    parts = np.array_split(np.arange(len(rays)), workers * 4)
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(_cast_part, [(verts, tris, rays[p]) for p in parts]))
+    return tuple(np.concatenate([r[i] for r in res]) for i in range(3))
+
+
+def targets(verts, tris, rays, n_mat, seed=0, workers=1):
     """Reference signals of a ray batch as a dict of arrays (hit, t, n, albedo, material)."""
-    hit, t, tri = ray_cast(verts, tris, rays)
+    hit, t, tri = ray_cast_parallel(verts, tris, rays, workers)
     fn, _ = face_normals(np.asarray(verts, np.float64), tris)
     mats = materials_of(verts, tris, n_mat)
     colours = np.random.default_rng(seed).uniform(0.05, 0.95, size=(n_mat, 3))
@@ -67,10 +83,10 @@ def targets(verts, tris, rays, n_mat, seed=0):
             "material": m.astype(np.int32)}
 
 
-def batch(mesh, obj, n_rays, seed=0):
+def batch(mesh, obj, n_rays, seed=0, workers=1):
     """A training batch for ``obj`` (built from ``mesh`` = (verts, tris)): the balanced rays of
     Sec. 5.2 and their reference signals."""
     from .rays import balanced_rays
     verts, tris = mesh
     rays = balanced_rays(streams(seed)[RAYS], verts, tris, n_rays, obj.bmin, obj.bmax)
-    return rays, targets(verts, tris, rays, obj.n_mat, seed)
+    return rays, targets(verts, tris, rays, obj.n_mat, seed, workers)
