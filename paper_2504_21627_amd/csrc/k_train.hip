@@ -21,25 +21,31 @@ __global__ __launch_bounds__(kBlock) void k_train_fill(float *a, uint64_t na, fl
     if (acc && blockIdx.x == 0 && threadIdx.x == 0) *acc = 0.0;
 }
 
-// Thread = (ray r, boundary point h).  Forward: the point's L x F features,
+// Forward: thread = (ray r, boundary point h): the point's L x F features,
 // trilinear over the 8 corners of its cell on every level (corners of weight
 // 0 included), into x[r][(h L + l) F + f]; points past the ray's list get 0.
-// Backward: d loss / d table entry += corner weight x dx for every corner of
-// non-zero weight, with float atomics into one of several copies of the
+//
+// Backward: thread = (ray r, point h, feature f), so that the F features of a
+// corner, adjacent in the table, go out from adjacent lanes of one atomic
+// instruction.  d loss / d table entry += corner weight x dx for every corner
+// of non-zero weight, with float atomics into one of several copies of the
 // gradient (block b into copy b % copies: consecutive blocks go to different
 // XCDs, so each copy's lines are contended by one XCD's blocks only); the
 // copies are summed afterwards.  The order of the additions is not fixed.
 // Where a ray leaves voxel j and enters voxel j + 1 at the same point (adjacent
 // listed voxels: the same plane crossing, the same clamps), the exit point's
-// thread adds both points' gradients and the entry point's thread adds
+// threads add both points' gradients and the entry point's threads add
 // nothing; each recomputes the other point, so both take the same decision.
 template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainEncArgs A)
 {
     const Geom &g = A.g;
     const uint32_t H = (uint32_t)g.H, L = (uint32_t)g.L, F = (uint32_t)g.F, LF = L * F;
+    const uint32_t per = BWD ? F : 1u;   // threads per point
     const uint64_t idx = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    const uint64_t r = idx / H;
-    const uint32_t h = (uint32_t)(idx - r * H);
+    const uint64_t rh = idx / per;
+    const uint32_t f0 = (uint32_t)(idx - rh * per);
+    const uint64_t r = rh / H;
+    const uint32_t h = (uint32_t)(rh - r * H);
     if (r >= A.n) return;
     float *x = A.x + (size_t)r * H * LF + (size_t)h * LF;
     const uint32_t nv = A.nvox[r];
@@ -64,13 +70,18 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
         merge_next = (h & 1u) && h + 1u < 2u * nv && same((h + 1u) >> 1, false);
     }
     const size_t T = (size_t)1 << g.log2_T;
+    float *gcopy = nullptr;
+    if constexpr (BWD) gcopy = A.gtab + (size_t)(blockIdx.x % A.replicas) * A.n_tab;
     for (uint32_t l = 0; l < L; ++l) {
         uint32_t i[3];
         float wt[3];
         level_cell(g, (int)l, p, i, wt);
-        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dx[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if constexpr (BWD)
-            for (uint32_t f = 0; f < F; ++f) dx[f] = merge_next ? x[l * F + f] + x[LF + l * F + f] : x[l * F + f];
+        float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dx = 0.0f;
+        if constexpr (BWD) {
+            dx = x[l * F + f0];
+            if (merge_next) dx += x[LF + l * F + f0];
+            if (dx == 0.0f) continue;
+        }
 #pragma unroll
         for (uint32_t c = 0; c < 8; ++c) {
             const uint32_t bx = c & 1u, by = (c >> 1) & 1u, bz = (c >> 2) & 1u;
@@ -79,14 +90,10 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
             const float wz = bz ? wt[2] : 1.0f - wt[2];
             const float wc = (wx * wy) * wz;
             const size_t e = ((size_t)l * T + vertex_slot(g, (int)l, i[0] + bx, i[1] + by, i[2] + bz)) * F;
-            float *gcopy = nullptr;
-            if constexpr (BWD) gcopy = A.gtab + (size_t)(blockIdx.x % A.replicas) * A.n_tab;
             if constexpr (!BWD) {
                 for (uint32_t f = 0; f < F; ++f) acc[f] = __builtin_fmaf(wc, A.tab[e + f], acc[f]);
             } else {
-                if (wc != 0.0f)
-                    for (uint32_t f = 0; f < F; ++f)
-                        if (dx[f] != 0.0f) unsafeAtomicAdd(&gcopy[e + f], wc * dx[f]);
+                if (wc != 0.0f) unsafeAtomicAdd(&gcopy[e + f0], wc * dx);
             }
         }
         if constexpr (!BWD)
@@ -94,64 +101,94 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
     }
 }
 
-// Tiled float32 product, 64 x 64 outputs per 256-thread block (4 x 4 per
-// thread), K in slices of 16 staged through LDS.  Block x = row tile, y =
-// column tile, z = K chunk.  Operand tiles are loaded along whichever index
-// has unit stride, so both plain and transposed operands read contiguously.
-constexpr uint32_t kGM = 64, kGN = 64, kGK = 16;
+// Tiled float32 product on the matrix cores: 64 x 128 outputs per 256-thread
+// block (the full width of a hidden layer, so the row operand is read once),
+// K in slices of 32 staged through LDS, the next slice loaded into registers
+// while the current one is multiplied.  Each wave computes a 32 x 64 block as
+// two v_mfma_f32_32x32x2f32 accumulators (float32 operands and accumulation).
+// Block x = row tile, y = column tile, z = K chunk.  Operand tiles are loaded
+// along whichever index has unit stride, so plain and transposed operands
+// both read contiguously.  Operand layout per lane l (i = l % 32, q = l / 32):
+// A holds A[i][k0 + q], B holds B[k0 + q][i], and accumulator r holds
+// D[8 (r / 4) + 4 q + r % 4][i].
+constexpr uint32_t kLA = kGM * kGK / kBlock, kLB = kGN * kGK / kBlock;   // loads per thread per slice
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 template <int EPI> __global__ __launch_bounds__(kBlock) void k_train_gemm(GemmArgs G)
 {
     __shared__ float As[kGK][kGM + 4];
     __shared__ float Bs[kGK][kGN + 4];
-    const uint32_t tid = threadIdx.x, tx = tid & 15u, ty = tid >> 4;
+    const uint32_t tid = threadIdx.x;
     const uint64_t i0 = (uint64_t)blockIdx.x * kGM;
     const uint32_t j0 = blockIdx.y * kGN;
     const uint64_t kb = (uint64_t)blockIdx.z * G.kchunk;
     const uint64_t ke = kb + G.kchunk < G.K ? kb + G.kchunk : G.K;
     const bool a_k_unit = G.sak == 1, b_j_unit = G.sbj == 1;
-    float acc[4][4];
+    const uint32_t lane = tid & 63u, wv = tid >> 6, wi = wv & 1u, wj = wv >> 1, li = lane & 31u, lq = lane >> 5;
+    // element e of a slice: A (i, k) and B (k, j) positions, chosen so that lanes read along the unit stride
+    auto a_pos = [&](uint32_t e, uint32_t &ai, uint32_t &ak) {
+        ai = a_k_unit ? e / kGK : e % kGM;
+        ak = a_k_unit ? e % kGK : e / kGM;
+    };
+    auto b_pos = [&](uint32_t e, uint32_t &bk, uint32_t &bj) {
+        bj = b_j_unit ? e % kGN : e / kGK;
+        bk = b_j_unit ? e / kGN : e % kGK;
+    };
+    float ra[kLA], rb[kLB];
+    auto fetch = [&](uint64_t k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+        for (uint32_t q = 0; q < kLA; ++q) {
+            uint32_t ai, ak;
+            a_pos(tid + q * kBlock, ai, ak);
+            const uint64_t gi = i0 + ai, gk = k0 + ak;
+            ra[q] = (gi < G.M && gk < ke) ? G.A[gi * G.sai + gk * G.sak] : 0.0f;
+        }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0f;
+        for (uint32_t q = 0; q < kLB; ++q) {
+            uint32_t bk, bj;
+            b_pos(tid + q * kBlock, bk, bj);
+            const uint64_t gj = j0 + bj, gk = k0 + bk;
+            rb[q] = (gj < G.N && gk < ke) ? G.B[gk * G.sbk + gj * G.sbj] : 0.0f;
+        }
+    };
+    f32x16_t acc0, acc1;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.0f;
+    if (kb < ke) fetch(kb);
     for (uint64_t k0 = kb; k0 < ke; k0 += kGK) {
 #pragma unroll
-        for (uint32_t q = 0; q < 4; ++q) {
-            const uint32_t e = tid + q * kBlock;
-            const uint32_t ai = a_k_unit ? e >> 4 : e & 63u, ak = a_k_unit ? e & 15u : e >> 6;
-            const uint64_t gi = i0 + ai, gk = k0 + ak;
-            As[ak][ai] = (gi < G.M && gk < ke) ? G.A[gi * G.sai + gk * G.sak] : 0.0f;
-            const uint32_t bj = b_j_unit ? e & 63u : e >> 4, bk = b_j_unit ? e >> 6 : e & 15u;
-            const uint64_t gj = j0 + bj, gk2 = k0 + bk;
-            Bs[bk][bj] = (gj < G.N && gk2 < ke) ? G.B[gk2 * G.sbk + gj * G.sbj] : 0.0f;
+        for (uint32_t q = 0; q < kLA; ++q) {
+            uint32_t ai, ak;
+            a_pos(tid + q * kBlock, ai, ak);
+            As[ak][ai] = ra[q];
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kLB; ++q) {
+            uint32_t bk, bj;
+            b_pos(tid + q * kBlock, bk, bj);
+            Bs[bk][bj] = rb[q];
         }
         __syncthreads();
+        if (k0 + kGK < ke) fetch(k0 + kGK);   // in flight while this slice is multiplied
 #pragma unroll
-        for (uint32_t k = 0; k < kGK; ++k) {
-            float a[4], b[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = As[k][ty * 4 + r];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = Bs[k][tx * 4 + c];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = __builtin_fmaf(a[r], b[c], acc[r][c]);
+        for (uint32_t k = 0; k < kGK; k += 2) {
+            const float a = As[k + lq][wi * 32 + li];
+            const float b0 = Bs[k + lq][wj * 64 + li], b1 = Bs[k + lq][wj * 64 + 32 + li];
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc1, 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const uint64_t gi = i0 + ty * 4 + r;
-        if (gi >= G.M) continue;
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t gj = j0 + wj * 64 + h * 32 + li;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const uint32_t gj = j0 + tx * 4 + c;
-            if (gj >= G.N) continue;
+        for (int r = 0; r < 16; ++r) {
+            const uint64_t gi = i0 + wi * 32 + 8 * (r / 4) + 4 * lq + (r % 4);
+            if (gi >= G.M || gj >= G.N) continue;
             float *dst = G.C + gi * G.ldc + gj;
             if constexpr (EPI == kEpiPartial) dst += (uint64_t)blockIdx.z * G.M * G.ldc;
-            float v = acc[r][c];
+            float v = h ? acc1[r] : acc0[r];
             if constexpr (EPI == kEpiAct) v = v > 0.0f ? v : v * G.slope;
             if constexpr (EPI == kEpiActGrad) v = G.aux[gi * G.ldc + gj] > 0.0f ? v : v * G.slope;
             *dst = v;
@@ -291,7 +328,7 @@ hipError_t launch_train_fill(float *a, uint64_t na, float *b, uint64_t nb, doubl
 
 hipError_t launch_train_encode(const TrainEncArgs &A, bool backward, hipStream_t s)
 {
-    const uint64_t threads = (uint64_t)A.n * (uint64_t)A.g.H;
+    const uint64_t threads = (uint64_t)A.n * (uint64_t)A.g.H * (backward ? (uint64_t)A.g.F : 1u);
     const dim3 grid((uint32_t)((threads + kBlock - 1) / kBlock));
     if (backward) hipLaunchKernelGGL(k_train_enc<true>, grid, dim3(kBlock), 0, s, A);
     else hipLaunchKernelGGL(k_train_enc<false>, grid, dim3(kBlock), 0, s, A);

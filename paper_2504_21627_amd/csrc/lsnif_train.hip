@@ -78,10 +78,10 @@ constexpr uint32_t kCopyBudget = 1u << 30;   // bytes for the table-gradient cop
 // K chunk of a weight-gradient product: enough blocks to fill the chip.
 uint32_t wgrad_chunk(uint32_t M, uint32_t N, uint32_t n)
 {
-    const uint32_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+    const uint32_t tiles = ((M + kGM - 1) / kGM) * ((N + kGN - 1) / kGN);
     const uint32_t want = tiles >= 2048 ? 1 : 2048 / tiles;
     uint32_t c = (n + want - 1) / want;
-    c = (c + 15) / 16 * 16;
+    c = (c + kGK - 1) / kGK * kGK;
     return c < 256 ? 256 : c;
 }
 
