@@ -101,26 +101,30 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
     }
 }
 
-// Tiled float32 product on the matrix cores: 64 x 128 outputs per 256-thread
-// block (the full width of a hidden layer, so the row operand is read once),
+// Tiled float32 product on the matrix cores: 64 x BN outputs per 256-thread
+// block (BN = 128, the full width of a hidden layer, reads the row operand
+// once; BN = 64 gives twice the blocks, which the products whose epilogue
+// reads a second operand prefer),
 // K in slices of 32 staged through LDS, the next slice loaded into registers
-// while the current one is multiplied.  Each wave computes a 32 x 64 block as
-// two v_mfma_f32_32x32x2f32 accumulators (float32 operands and accumulation).
+// while the current one is multiplied.  Each wave computes a 32 x BN/2 block
+// as BN/64 v_mfma_f32_32x32x2f32 accumulators (float32 operands and
+// accumulation).
 // Block x = row tile, y = column tile, z = K chunk.  Operand tiles are loaded
 // along whichever index has unit stride, so plain and transposed operands
 // both read contiguously.  Operand layout per lane l (i = l % 32, q = l / 32):
 // A holds A[i][k0 + q], B holds B[k0 + q][i], and accumulator r holds
 // D[8 (r / 4) + 4 q + r % 4][i].
-constexpr uint32_t kLA = kGM * kGK / kBlock, kLB = kGN * kGK / kBlock;   // loads per thread per slice
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-template <int EPI> __global__ __launch_bounds__(kBlock) void k_train_gemm(GemmArgs G)
+template <int EPI, uint32_t BN> __global__ __launch_bounds__(kBlock) void k_train_gemm(GemmArgs G)
 {
+    constexpr uint32_t kLA = kGM * kGK / kBlock, kLB = BN * kGK / kBlock;   // loads per thread per slice
+    constexpr uint32_t WB = BN / 64;                                       // 32 x 32 blocks per wave
     __shared__ float As[kGK][kGM + 4];
-    __shared__ float Bs[kGK][kGN + 4];
+    __shared__ float Bs[kGK][BN + 4];
     const uint32_t tid = threadIdx.x;
     const uint64_t i0 = (uint64_t)blockIdx.x * kGM;
-    const uint32_t j0 = blockIdx.y * kGN;
+    const uint32_t j0 = blockIdx.y * BN;
     const uint64_t kb = (uint64_t)blockIdx.z * G.kchunk;
     const uint64_t ke = kb + G.kchunk < G.K ? kb + G.kchunk : G.K;
     const bool a_k_unit = G.sak == 1, b_j_unit = G.sbj == 1;
@@ -131,8 +135,8 @@ template <int EPI> __global__ __launch_bounds__(kBlock) void k_train_gemm(GemmAr
         ak = a_k_unit ? e % kGK : e / kGM;
     };
     auto b_pos = [&](uint32_t e, uint32_t &bk, uint32_t &bj) {
-        bj = b_j_unit ? e % kGN : e / kGK;
-        bk = b_j_unit ? e / kGN : e % kGK;
+        bj = b_j_unit ? e % BN : e / kGK;
+        bk = b_j_unit ? e / BN : e % kGK;
     };
     float ra[kLA], rb[kLB];
     auto fetch = [&](uint64_t k0) {
@@ -151,9 +155,11 @@ template <int EPI> __global__ __launch_bounds__(kBlock) void k_train_gemm(GemmAr
             rb[q] = (gj < G.N && gk < ke) ? G.B[gk * G.sbk + gj * G.sbj] : 0.0f;
         }
     };
-    f32x16_t acc0, acc1;
+    f32x16_t acc[WB];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.0f;
+    for (uint32_t h = 0; h < WB; ++h)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[h][r] = 0.0f;
     if (kb < ke) fetch(kb);
     for (uint64_t k0 = kb; k0 < ke; k0 += kGK) {
 #pragma unroll
@@ -173,22 +179,23 @@ template <int EPI> __global__ __launch_bounds__(kBlock) void k_train_gemm(GemmAr
 #pragma unroll
         for (uint32_t k = 0; k < kGK; k += 2) {
             const float a = As[k + lq][wi * 32 + li];
-            const float b0 = Bs[k + lq][wj * 64 + li], b1 = Bs[k + lq][wj * 64 + 32 + li];
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc1, 0, 0, 0);
+#pragma unroll
+            for (uint32_t h = 0; h < WB; ++h)
+                acc[h] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, Bs[k + lq][wj * (BN / 2) + h * 32 + li], acc[h],
+                                                              0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const uint32_t gj = j0 + wj * 64 + h * 32 + li;
+    for (uint32_t h = 0; h < WB; ++h) {
+        const uint32_t gj = j0 + wj * (BN / 2) + h * 32 + li;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const uint64_t gi = i0 + wi * 32 + 8 * (r / 4) + 4 * lq + (r % 4);
             if (gi >= G.M || gj >= G.N) continue;
             float *dst = G.C + gi * G.ldc + gj;
             if constexpr (EPI == kEpiPartial) dst += (uint64_t)blockIdx.z * G.M * G.ldc;
-            float v = h ? acc1[r] : acc0[r];
+            float v = acc[h][r];
             if constexpr (EPI == kEpiAct) v = v > 0.0f ? v : v * G.slope;
             if constexpr (EPI == kEpiActGrad) v = G.aux[gi * G.ldc + gj] > 0.0f ? v : v * G.slope;
             *dst = v;
@@ -338,12 +345,13 @@ hipError_t launch_train_encode(const TrainEncArgs &A, bool backward, hipStream_t
 hipError_t launch_train_gemm(const GemmArgs &G, int epi, hipStream_t s)
 {
     const uint64_t chunks = (G.K + G.kchunk - 1) / G.kchunk;
-    const dim3 grid((uint32_t)((G.M + kGM - 1) / kGM), (G.N + kGN - 1) / kGN, (uint32_t)(chunks ? chunks : 1));
+    const uint32_t mt = (uint32_t)((G.M + kGM - 1) / kGM), z = (uint32_t)(chunks ? chunks : 1);
+    const dim3 wide(mt, (G.N + kGN - 1) / kGN, z), narrow(mt, (G.N + 63) / 64, z);
     switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL(k_train_gemm<kEpiStore>, grid, dim3(kBlock), 0, s, G); break;
-    case kEpiAct: hipLaunchKernelGGL(k_train_gemm<kEpiAct>, grid, dim3(kBlock), 0, s, G); break;
-    case kEpiActGrad: hipLaunchKernelGGL(k_train_gemm<kEpiActGrad>, grid, dim3(kBlock), 0, s, G); break;
-    default: hipLaunchKernelGGL(k_train_gemm<kEpiPartial>, grid, dim3(kBlock), 0, s, G); break;
+    case kEpiStore: hipLaunchKernelGGL((k_train_gemm<kEpiStore, 64>), narrow, dim3(kBlock), 0, s, G); break;
+    case kEpiAct: hipLaunchKernelGGL((k_train_gemm<kEpiAct, kGN>), wide, dim3(kBlock), 0, s, G); break;
+    case kEpiActGrad: hipLaunchKernelGGL((k_train_gemm<kEpiActGrad, 64>), narrow, dim3(kBlock), 0, s, G); break;
+    default: hipLaunchKernelGGL((k_train_gemm<kEpiPartial, kGN>), wide, dim3(kBlock), 0, s, G); break;
     }
     return hipGetLastError();
 }
