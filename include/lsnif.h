@@ -433,10 +433,12 @@ lsnif_status lsnif_serve_stop(lsnif_ctx *ctx);
  * FP32 MLP, in place: the object's device tables and weights ARE the trained
  * parameters, so the object answers lsnif_query with the current parameters
  * between steps (a query and a step in flight at once race).  The trainer
- * adds, on the device, one gradient, one first-moment and one second-moment
- * buffer per parameter (3 x the object's table and weight bytes) and a
- * per-step workspace that grows with the batch (about 4 (in_dim + 4 width +
- * 2 outputs) + 4 H/2 + 1 bytes per ray).
+ * adds, on the device, first and second moments of every parameter, the
+ * weight gradients, up to 8 copies of the table gradient (as many as fit in
+ * 1 GiB, at least one; the scatter spreads its atomics over them) and a
+ * per-step workspace that grows with the batch (about 4 (in_dim + n_hidden
+ * width + 2 outputs) + 4 H/2 + 1 bytes per ray, plus the weight-gradient
+ * partial sums, a few tens of MB).
  *
  * Loss of one training batch of n rays: (1/n) sum over the rays of
  *   softplus(z0) - y.hit z0                                  occlusion: sigmoid + binary cross-entropy
