@@ -384,23 +384,67 @@ def train_flops_per_ray(obj):
     return 3 * 2 * sum(int(w.shape[0]) * int(w.shape[1]) for w in obj.weights)
 
 
-def t1_batch(n=1 << 18):
-    """The training batch: generated before the GPU is touched (the ray cast runs in spawned
-    worker processes)."""
+def t1_batch(n=1 << 18, extra=4, held_out=1 << 16):
+    """The training batches: generated before the GPU is touched (the ray cast runs in spawned
+    worker processes).  The timed batch, `extra` further training batches of n / 4 rays and a
+    held-out batch, each from its own ray seed."""
     import workloads as W
     from workloads import train as WT
     obj = W.configs.paper_object(seed=0)
-    print(f"[bench] generating the t1 training batch ({n} rays, ray casting)", file=sys.stderr, flush=True)
+    print(f"[bench] generating the t1 training batches ({n} + {extra} x {n // 4} + {held_out} rays, ray casting)",
+          file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    rays_np, tg = WT.batch(W.icosphere(3), obj, n, seed=31, workers=8)
-    return obj, rays_np, tg, time.perf_counter() - t0
+    mesh = W.icosphere(3)
+    rays_np, tg = WT.batch(mesh, obj, n, seed=31, workers=8)
+    more = [WT.batch(mesh, obj, n // 4, seed=32 + i, workers=8) for i in range(extra)]
+    test = WT.batch(mesh, obj, held_out, seed=99, workers=8)
+    return obj, rays_np, tg, time.perf_counter() - t0, more, test
 
 
-def bench_t1(L, steps, warmup, data, cpu=True):
+def t1_quality(L, ctx, oid, tr, obj, batches, test, steps):
+    """Train on, cycling over the batches, then score the object on the held-out rays against
+    the ray-cast references: visibility, hit distance and normal of the FP32 query, and the
+    FP16 query of the trained parameters against the FP32 one."""
+    import torch
+    dev = [(torch.from_numpy(r).cuda(), torch.from_numpy(L.targets_array(t["hit"], t["t"], t["n"], t["material"],
+                                                                          t["albedo"])).cuda()) for r, t in batches]
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    for k in range(steps):
+        r, t = dev[k % len(dev)]
+        L.lsnif_train_step(tr, r, t, loss)
+    rays_np, tg = test
+    rays = torch.from_numpy(rays_np).cuda()
+    out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
+    L.lsnif_query(ctx, oid, rays, out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    hit = g[:, 0].view(np.uint32) == 1
+    ref = tg["hit"] == 1
+    both = hit & ref
+    t_err = np.abs(g[both, 1] - tg["t"][both]) / np.maximum(np.abs(tg["t"][both]), 1e-6)
+    cosang = np.clip(np.sum(g[both, 2:5] * tg["n"][both], axis=1), -1, 1)
+    tab, Ws, _, _, n_steps = L.lsnif_trainer_read(tr, obj)
+    import dataclasses
+    trained = dataclasses.replace(obj, tables=tab, weights=Ws)
+    oid16 = L.lsnif_build(ctx, L.ObjectDesc(trained, "fp16", "fp16"))
+    out16 = torch.empty_like(out)
+    L.lsnif_query(ctx, oid16, rays, out16)
+    torch.cuda.synchronize()
+    hit16 = out16.cpu().numpy()[:, 0].view(np.uint32) == 1
+    L.lsnif_release(ctx, oid16)
+    return {"adam_steps": int(n_steps), "held_out_rays": len(rays_np), "reference_hits": int(ref.sum()),
+            "visibility_accuracy": float((hit == ref).mean()), "hit_recall": float(both.sum() / max(ref.sum(), 1)),
+            "hit_precision": float(both.sum() / max(hit.sum(), 1)),
+            "t_rel_err_median": float(np.median(t_err)) if both.any() else None,
+            "normal_err_median_rad": float(np.median(np.arccos(cosang))) if both.any() else None,
+            "fp16_vs_fp32_visibility": float((hit16 == hit).mean()), "last_batch_loss": float(loss.item())}
+
+
+def bench_t1(L, steps, warmup, data, cpu=True, quality_steps=400):
     """Training (Sec. 5.2, 5.3): the paper's default object shape with FP32 parameters, one
     batch of 2^18 balanced rays with references from ray casting its mesh, Adam at lr 0.01."""
     import torch
-    obj, rays_np, tg, gen_s = data
+    obj, rays_np, tg, gen_s, more, test = data
     n = len(rays_np)
     res = {"workload": "t1: training the paper's default object shape (c1's icosphere, V=32, levels R=64,128, "
                        "2^17 x 3 fp32 features, H=18, MLP 108-128-128-12 leaky ReLU, albedo head, 4 materials); "
@@ -435,6 +479,9 @@ def bench_t1(L, steps, warmup, data, cpu=True):
                         "steps": steps, "warmup": warmup, "gflop_per_step": flops / 1e9,
                         "layer_tflops": flops / ms / 1e9, "loss_step1": loss_first,
                         "loss_last": float(loss.item()), "adam_steps": steps + warmup + 1})
+            if quality_steps:
+                print("[bench] t1: training on to score held-out rays", file=sys.stderr, flush=True)
+                res["trained"] = t1_quality(L, ctx, oid, tr, obj, [(rays_np, tg)] + list(more), test, quality_steps)
         finally:
             L.lsnif_trainer_destroy(tr)
     finally:
@@ -570,6 +617,8 @@ def main():
                          "p1 (the paper's default object shape), small (latency of small batches), "
                          "t1 (training steps)")
     ap.add_argument("--c5-requests", type=int, default=2000)
+    ap.add_argument("--t1-quality-steps", type=int, default=400,
+                    help="t1: further training steps before scoring held-out rays (0: skip the scoring)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tuning (no autotuner)")
     ap.add_argument("--tuning", default=None,
                     help="sort_bits,pair_bits,hot_lds_bytes[,walk_chunks] for the c2 object instead of the "
@@ -610,7 +659,8 @@ def main():
     if "p1" in legs:
         rec["paper_default_p1"] = bench_p1(L, max(args.steps // 4, 5), min(args.warmup, 3), not args.no_tune)
     if "t1" in legs:
-        rec["training_t1"] = bench_t1(L, max(args.steps // 10, 5), min(args.warmup, 3), t1_data, not args.no_cpu)
+        rec["training_t1"] = bench_t1(L, max(args.steps // 10, 5), min(args.warmup, 3), t1_data, not args.no_cpu,
+                                      args.t1_quality_steps)
     if not args.no_cpu and "c2" in legs:
         print("[bench] timing the oracle on a CPU sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(obj, rays_np, args.cpu_sample)
