@@ -483,9 +483,12 @@ lsnif_status lsnif_trainer_create(lsnif_ctx *ctx, uint32_t object_id, const lsni
 /* Waits for the device and frees the trainer's buffers; the object keeps its
  * trained parameters. */
 void lsnif_trainer_destroy(lsnif_trainer *tr);
-/* Forward pass, loss and backward pass of one batch (device buffers, n >= 1):
- * the gradients of the batch loss replace the trainer's gradients and the loss
- * goes to d_loss[0] (device float).  Asynchronous on `stream`. */
+/* Forward pass, loss and backward pass of one batch (device buffers, n >= 1,
+ * at most 2^24; rays 16-byte and targets 4-byte aligned): the gradients of the
+ * batch loss replace the trainer's gradients and the loss goes to d_loss[0]
+ * (device float; NULL skips it).  Targets must be finite where hit = 1.
+ * Asynchronous on `stream`; the trainer's workspace grows to the batch
+ * (LSNIF_E_NOMEM if it cannot). */
 lsnif_status lsnif_train_grads(lsnif_trainer *tr, const lsnif_ray *d_rays, const lsnif_train_target *d_gt,
                                uint32_t n, float *d_loss, void *stream);
 /* One Adam step with the trainer's current gradients.  Asynchronous. */

@@ -138,21 +138,46 @@ template <int EPI, uint32_t BN> __global__ __launch_bounds__(kBlock) void k_trai
         bj = b_j_unit ? e % BN : e / kGK;
         bk = b_j_unit ? e / BN : e % kGK;
     };
+    // each thread's elements keep their row / column across slices: their addresses at the
+    // chunk's first slice, and whether the row or column exists, are fixed once
     float ra[kLA], rb[kLB];
+    const float *pa[kLA], *pb[kLB];
+    bool va[kLA], vb[kLB];
+#pragma unroll
+    for (uint32_t q = 0; q < kLA; ++q) {
+        uint32_t ai, ak;
+        a_pos(tid + q * kBlock, ai, ak);
+        va[q] = i0 + ai < G.M;
+        pa[q] = G.A + (va[q] ? (i0 + ai) * G.sai + (kb + ak) * G.sak : 0);
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kLB; ++q) {
+        uint32_t bk, bj;
+        b_pos(tid + q * kBlock, bk, bj);
+        vb[q] = j0 + bj < G.N;
+        pb[q] = G.B + (vb[q] ? (kb + bk) * G.sbk + (j0 + bj) * G.sbj : 0);
+    }
+    const uint64_t step_a = (uint64_t)kGK * G.sak, step_b = (uint64_t)kGK * G.sbk;
     auto fetch = [&](uint64_t k0) {
+        const uint64_t s = (k0 - kb) / kGK;
+        if (k0 + kGK <= ke) {   // a whole slice: only the row / column bound
 #pragma unroll
-        for (uint32_t q = 0; q < kLA; ++q) {
-            uint32_t ai, ak;
-            a_pos(tid + q * kBlock, ai, ak);
-            const uint64_t gi = i0 + ai, gk = k0 + ak;
-            ra[q] = (gi < G.M && gk < ke) ? G.A[gi * G.sai + gk * G.sak] : 0.0f;
-        }
+            for (uint32_t q = 0; q < kLA; ++q) ra[q] = va[q] ? pa[q][s * step_a] : 0.0f;
 #pragma unroll
-        for (uint32_t q = 0; q < kLB; ++q) {
-            uint32_t bk, bj;
-            b_pos(tid + q * kBlock, bk, bj);
-            const uint64_t gj = j0 + bj, gk = k0 + bk;
-            rb[q] = (gj < G.N && gk < ke) ? G.B[gk * G.sbk + gj * G.sbj] : 0.0f;
+            for (uint32_t q = 0; q < kLB; ++q) rb[q] = vb[q] ? pb[q][s * step_b] : 0.0f;
+        } else {
+#pragma unroll
+            for (uint32_t q = 0; q < kLA; ++q) {
+                uint32_t ai, ak;
+                a_pos(tid + q * kBlock, ai, ak);
+                ra[q] = (va[q] && k0 + ak < ke) ? pa[q][s * step_a] : 0.0f;
+            }
+#pragma unroll
+            for (uint32_t q = 0; q < kLB; ++q) {
+                uint32_t bk, bj;
+                b_pos(tid + q * kBlock, bk, bj);
+                rb[q] = (vb[q] && k0 + bk < ke) ? pb[q][s * step_b] : 0.0f;
+            }
         }
     };
     f32x16_t acc[WB];
