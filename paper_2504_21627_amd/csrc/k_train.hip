@@ -22,8 +22,11 @@ __global__ __launch_bounds__(kBlock) void k_train_fill(float *a, uint64_t na, fl
 }
 
 // Forward: thread = (ray r, boundary point h): the point's L x F features,
-// trilinear over the 8 corners of its cell on every level (corners of weight
-// 0 included), into x[r][(h L + l) F + f]; points past the ray's list get 0.
+// trilinear over the corners of its cell on every level, into
+// x[r][(h L + l) F + f]; points past the ray's list get 0.  On a level aligned
+// with the voxel faces the point's crossing-axis weight is exactly 0 or 1, so
+// only the 4 corners on that side are visited (the others have weight 0; the
+// sparse encoding of Sec. 3.2); other levels visit all 8.
 //
 // Backward: thread = (ray r, point h, feature f), so that the F features of a
 // corner, adjacent in the table, go out from adjacent lanes of one atomic
@@ -58,7 +61,7 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
     setup_ray(g, A.rays[2 * r], A.rays[2 * r + 1], w);
     const uint32_t packed = A.lists[(size_t)(h >> 1) * A.n + r];
     float p[3];
-    (void)boundary_point(w, packed, (h & 1u) != 0u, p);
+    const uint32_t face = (uint32_t)boundary_point(w, packed, (h & 1u) != 0u, p);
     bool merge_next = false;
     if constexpr (BWD) {
         auto same = [&](uint32_t j, bool is_exit) {
@@ -82,8 +85,12 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
             if (merge_next) dx += x[LF + l * F + f0];
             if (dx == 0.0f) continue;
         }
-#pragma unroll
-        for (uint32_t c = 0; c < 8; ++c) {
+        const bool al = (g.aligned_mask >> l) & 1u;
+        const uint32_t nc = al ? 4u : 8u, fb = wt[face] != 0.0f ? 1u : 0u;
+        const uint32_t low = (1u << face) - 1u;
+        for (uint32_t cc = 0; cc < nc; ++cc) {
+            // aligned level: corner index cc with the crossing axis's bit (fb) inserted at bit `face`
+            const uint32_t c = al ? ((cc & low) | (fb << face) | ((cc & ~low) << 1)) : cc;
             const uint32_t bx = c & 1u, by = (c >> 1) & 1u, bz = (c >> 2) & 1u;
             const float wx = bx ? wt[0] : 1.0f - wt[0];
             const float wy = by ? wt[1] : 1.0f - wt[1];
