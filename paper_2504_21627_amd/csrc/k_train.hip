@@ -109,9 +109,8 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
 }
 
 // Tiled float32 product on the matrix cores: 64 x BN outputs per 256-thread
-// block (BN = 128, the full width of a hidden layer, reads the row operand
-// once; BN = 64 gives twice the blocks, which the products whose epilogue
-// reads a second operand prefer),
+// block (the launches use BN = 64: at 126 VGPRs it runs 4 waves per SIMD, and
+// that beat BN = 128, which reads the row operand once but needs 212),
 // K in slices of 32 staged through LDS, the next slice loaded into registers
 // while the current one is multiplied.  Each wave computes a 32 x BN/2 block
 // as BN/64 v_mfma_f32_32x32x2f32 accumulators (float32 operands and
@@ -123,7 +122,8 @@ template <bool BWD> __global__ __launch_bounds__(kBlock) void k_train_enc(TrainE
 // D[8 (r / 4) + 4 q + r % 4][i].
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-template <int EPI, uint32_t BN> __global__ __launch_bounds__(kBlock) void k_train_gemm(GemmArgs G)
+template <int EPI, uint32_t BN>
+__global__ __launch_bounds__(kBlock) void k_train_gemm(GemmArgs G)
 {
     constexpr uint32_t kLA = kGM * kGK / kBlock, kLB = BN * kGK / kBlock;   // loads per thread per slice
     constexpr uint32_t WB = BN / 64;                                       // 32 x 32 blocks per wave
@@ -145,45 +145,48 @@ template <int EPI, uint32_t BN> __global__ __launch_bounds__(kBlock) void k_trai
         bj = b_j_unit ? e % BN : e / kGK;
         bk = b_j_unit ? e / BN : e % kGK;
     };
-    // each thread's elements keep their row / column across slices: their addresses at the
-    // chunk's first slice, and whether the row or column exists, are fixed once
+    // each thread's elements keep their row / column across slices: a slice's operands are a
+    // uniform base (the block's corner, advanced by whole slices) plus a fixed 32-bit offset per
+    // element (small: within one 64 x 32 or 32 x BN tile), and a bit per element says whether
+    // its row / column exists
     float ra[kLA], rb[kLB];
-    const float *pa[kLA], *pb[kLB];
-    bool va[kLA], vb[kLB];
+    uint32_t oa[kLA], ob[kLB], va = 0, vb = 0;
 #pragma unroll
     for (uint32_t q = 0; q < kLA; ++q) {
         uint32_t ai, ak;
         a_pos(tid + q * kBlock, ai, ak);
-        va[q] = i0 + ai < G.M;
-        pa[q] = G.A + (va[q] ? (i0 + ai) * G.sai + (kb + ak) * G.sak : 0);
+        va |= (i0 + ai < G.M ? 1u : 0u) << q;
+        oa[q] = (uint32_t)(ai * G.sai + ak * G.sak);
     }
 #pragma unroll
     for (uint32_t q = 0; q < kLB; ++q) {
         uint32_t bk, bj;
         b_pos(tid + q * kBlock, bk, bj);
-        vb[q] = j0 + bj < G.N;
-        pb[q] = G.B + (vb[q] ? (kb + bk) * G.sbk + (j0 + bj) * G.sbj : 0);
+        vb |= (j0 + bj < G.N ? 1u : 0u) << q;
+        ob[q] = (uint32_t)(bk * G.sbk + bj * G.sbj);
     }
+    const float *A0 = G.A + i0 * G.sai + kb * G.sak, *B0 = G.B + kb * G.sbk + (uint64_t)j0 * G.sbj;
     const uint64_t step_a = (uint64_t)kGK * G.sak, step_b = (uint64_t)kGK * G.sbk;
     auto fetch = [&](uint64_t k0) {
         const uint64_t s = (k0 - kb) / kGK;
+        const float *As0 = A0 + s * step_a, *Bs0 = B0 + s * step_b;
         if (k0 + kGK <= ke) {   // a whole slice: only the row / column bound
 #pragma unroll
-            for (uint32_t q = 0; q < kLA; ++q) ra[q] = va[q] ? pa[q][s * step_a] : 0.0f;
+            for (uint32_t q = 0; q < kLA; ++q) ra[q] = (va >> q) & 1u ? As0[oa[q]] : 0.0f;
 #pragma unroll
-            for (uint32_t q = 0; q < kLB; ++q) rb[q] = vb[q] ? pb[q][s * step_b] : 0.0f;
+            for (uint32_t q = 0; q < kLB; ++q) rb[q] = (vb >> q) & 1u ? Bs0[ob[q]] : 0.0f;
         } else {
 #pragma unroll
             for (uint32_t q = 0; q < kLA; ++q) {
                 uint32_t ai, ak;
                 a_pos(tid + q * kBlock, ai, ak);
-                ra[q] = (va[q] && k0 + ak < ke) ? pa[q][s * step_a] : 0.0f;
+                ra[q] = ((va >> q) & 1u) && k0 + ak < ke ? As0[oa[q]] : 0.0f;
             }
 #pragma unroll
             for (uint32_t q = 0; q < kLB; ++q) {
                 uint32_t bk, bj;
                 b_pos(tid + q * kBlock, bk, bj);
-                rb[q] = (vb[q] && k0 + bk < ke) ? pb[q][s * step_b] : 0.0f;
+                rb[q] = ((vb >> q) & 1u) && k0 + bk < ke ? Bs0[ob[q]] : 0.0f;
             }
         }
     };
@@ -378,12 +381,12 @@ hipError_t launch_train_gemm(const GemmArgs &G, int epi, hipStream_t s)
 {
     const uint64_t chunks = (G.K + G.kchunk - 1) / G.kchunk;
     const uint32_t mt = (uint32_t)((G.M + kGM - 1) / kGM), z = (uint32_t)(chunks ? chunks : 1);
-    const dim3 wide(mt, (G.N + kGN - 1) / kGN, z), narrow(mt, (G.N + 63) / 64, z);
+    const dim3 grid(mt, (G.N + kGN - 1) / kGN, z);
     switch (epi) {
-    case kEpiStore: hipLaunchKernelGGL((k_train_gemm<kEpiStore, 64>), narrow, dim3(kBlock), 0, s, G); break;
-    case kEpiAct: hipLaunchKernelGGL((k_train_gemm<kEpiAct, kGN>), wide, dim3(kBlock), 0, s, G); break;
-    case kEpiActGrad: hipLaunchKernelGGL((k_train_gemm<kEpiActGrad, 64>), narrow, dim3(kBlock), 0, s, G); break;
-    default: hipLaunchKernelGGL((k_train_gemm<kEpiPartial, kGN>), wide, dim3(kBlock), 0, s, G); break;
+    case kEpiStore: hipLaunchKernelGGL((k_train_gemm<kEpiStore, kGN>), grid, dim3(kBlock), 0, s, G); break;
+    case kEpiAct: hipLaunchKernelGGL((k_train_gemm<kEpiAct, kGN>), grid, dim3(kBlock), 0, s, G); break;
+    case kEpiActGrad: hipLaunchKernelGGL((k_train_gemm<kEpiActGrad, kGN>), grid, dim3(kBlock), 0, s, G); break;
+    default: hipLaunchKernelGGL((k_train_gemm<kEpiPartial, kGN>), grid, dim3(kBlock), 0, s, G); break;
     }
     return hipGetLastError();
 }

@@ -33,9 +33,8 @@ struct GemmArgs {
     float slope;              // activation slope below 0 (0 for ReLU)
 };
 
-// Output tile of a block (rows x columns; the products whose epilogue reads a
-// second operand, and plain stores, use 64 columns) and the K slice staged per step.
-constexpr uint32_t kGM = 64, kGN = 128, kGK = 32;
+// Output tile of a block (rows x columns) and the K slice staged per step.
+constexpr uint32_t kGM = 64, kGN = 64, kGK = 32;
 
 // kEpiPartial: K chunk z stores its partial product at C + z M ldc (summed afterwards).
 enum GemmEpi : int { kEpiStore = 0, kEpiAct = 1, kEpiActGrad = 2, kEpiPartial = 3 };
