@@ -259,3 +259,34 @@ def test_train_edge_cases(L, mesh):
         L.lsnif_trainer_destroy(tr)
     finally:
         L.lsnif_destroy(ctx)
+
+
+def random_targets(rays, seed, n_mat):
+    """Seeded targets of any value (gradient parity does not need them to be geometric):
+    a quarter of the rays hit at t in [0, 4], unit normals, materials and albedos."""
+    rng = np.random.default_rng(seed)
+    n = len(rays)
+    nrm = rng.standard_normal((n, 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return {"hit": (rng.random(n) < 0.25).astype(np.uint32), "t": rng.uniform(0, 4, n).astype(np.float32),
+            "n": nrm.astype(np.float32), "albedo": rng.random((n, 3)).astype(np.float32),
+            "material": rng.integers(0, n_mat, n).astype(np.int32)}
+
+
+def test_train_grads_match_oracle_c2_object(L):
+    """c2's object: 16 levels (10 hashed, one face-aligned), 2^19 entries x 2 features, 576
+    inputs (18 K slices of the first product), 64 MiB of table gradient per copy."""
+    obj = W.configs.c2_object()
+    rays = W.configs.subsample(W.configs.c2_rays(), 1500, seed=41)
+    tg = random_targets(rays, 42, obj.n_mat)
+    keep = margin_keep(obj, rays, tg)
+    print("c2 rays kept", int(keep.sum()), "of", len(keep), flush=True)
+    assert keep.mean() > 0.7
+    rays, tg = subset(rays, tg, keep)
+    ref = OT.train_grads(obj, rays, tg, bounds=True)
+    loss, gtab, gW, _, _, _ = gpu_grads(L, obj, rays, tg)
+    assert abs(loss - ref["loss"]) <= 1e-5 * ref["loss"], (loss, ref["loss"])
+    check_grad(gtab, ref["gtab"], ref["gtab_abs"], "tables")
+    assert np.count_nonzero(ref["gtab"]) > 10000
+    for k in range(len(gW)):
+        check_grad(gW[k], ref["gW"][k], ref["gW_abs"][k], f"layer {k}")
