@@ -502,7 +502,9 @@ def bench_t1(L, steps, warmup, data, cpu=True, quality_steps=400):
         dt = time.perf_counter() - t0
         res["cpu_baseline"] = {"value": m / dt / 1e6, "unit": "Mrays/s trained", "cores": oracle.num_threads(),
                                "kind": "oracle", "sample": f"one step on the first {m} rays of the batch "
-                                                           f"(float64 numpy + the C query oracle), {dt:.2f} s wall"}
+                                                           f"(the C query oracle on {oracle.num_threads()} OpenMP "
+                                                           f"threads for the walk and encoding, then float64 numpy, "
+                                                           f"mostly one thread, for the rest), {dt:.2f} s wall"}
     return res
 
 
