@@ -463,6 +463,11 @@ lsnif_status lsnif_serve_stop(lsnif_ctx *ctx);
  * paper's setting is lr 0.01 with batches of 2^18 rays. */
 typedef struct lsnif_trainer lsnif_trainer;
 
+/* A trainer's gradients, moments and workspace are shared by its calls: steps
+ * on one trainer must be ordered (one stream, or synchronised between
+ * streams).  Calls take the context's lock while they enqueue;
+ * lsnif_trainer_destroy must not overlap another call on the same trainer. */
+
 /* Reference signals of one training ray (from ray casting the true geometry). */
 typedef struct {
     uint32_t hit;        /* 1: the ray hits the object, at parameter t of the ray */
