@@ -445,11 +445,19 @@ __device__ __forceinline__ void decode_store(const QueryArgs &A, const Mlp &mm, 
                 h.n[1] = o[3] * inv;
                 h.n[2] = o[4] * inv;
             }
+            // argmax over the material logits o[m0 .. m0 + n_mat), ties to the lowest index;
+            // written over the static slots of o so that o stays in registers
             const int m0 = 5 + 3 * mm.has_albedo;
             int best = 0;
-            float bv = o[m0];
-            for (int k = 1; k < mm.n_mat; ++k)
-                if (o[m0 + k] > bv) { bv = o[m0 + k]; best = k; }
+            float bv = 0.0f;
+#pragma unroll
+            for (int k = 5; k < kMaxOut; ++k) {
+                const int mk = k - m0;
+                if (mk >= 0 && mk < mm.n_mat && (mk == 0 || o[k] > bv)) {
+                    bv = o[k];
+                    best = mk;
+                }
+            }
             h.material = best;
         }
     }
@@ -751,8 +759,11 @@ __device__ __forceinline__ void query_f32_body(const QueryArgs &A, const Geom &g
         A.dbg.tatb[2 * r] = w.ta;
         A.dbg.tatb[2 * r + 1] = w.tb;
     }
-    if (A.dbg.out)
-        for (int k = 0; k < mm.out_dim; ++k) A.dbg.out[(size_t)r * mm.out_dim + k] = count > 0 ? o[k] : 0.0f;
+    if (A.dbg.out) {
+#pragma unroll
+        for (int k = 0; k < kMaxOut; ++k)
+            if (k < mm.out_dim) A.dbg.out[(size_t)r * mm.out_dim + k] = count > 0 ? o[k] : 0.0f;
+    }
     decode_store<PAIRS>(A, mm, r, ln.pair, w, count, o);
 }
 
@@ -1084,8 +1095,11 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
         A.dbg.tatb[2 * r] = w.ta;
         A.dbg.tatb[2 * r + 1] = w.tb;
     }
-    if (A.dbg.out)
-        for (int k = 0; k < mm.out_dim; ++k) A.dbg.out[(size_t)r * mm.out_dim + k] = count > 0 ? o[k] : 0.0f;
+    if (A.dbg.out) {
+#pragma unroll
+        for (int k = 0; k < kMaxOut; ++k)
+            if (k < mm.out_dim) A.dbg.out[(size_t)r * mm.out_dim + k] = count > 0 ? o[k] : 0.0f;
+    }
     decode_store<PAIRS>(A, mm, r, ln.pair, w, count, o);
 }
 
