@@ -507,3 +507,116 @@ def test_grazing_recheck_against_bruteforce():
         changed += l32 != set(listed)
         grazing_required += len(s["must_grazing"])
     assert changed >= 50 and fp32_fails >= 10 and grazing_required >= 50
+
+
+def vertex_table(R, F=3, log2_T=10):
+    """One dense level whose entry for vertex (x, y, z) holds (x, y, z): the interpolated
+    feature at a point is the point itself (in level units, which are voxel units for R = V)."""
+    side = R + 1
+    v = np.arange(side ** 3)
+    tab = np.zeros((1, 1 << log2_T, F), f32)
+    tab[0, : side ** 3, :3] = np.stack([v % side, (v // side) % side, v // (side * side)], 1)
+    return tab
+
+
+def first_entry_point(ref):
+    """Entry point of the first listed voxel of a brute-force voxel list (voxel units): the
+    crossing axis snapped to the face plane, the others clamped into the voxel."""
+    ijk, tin, _, ia, _ = ref["vox"][0]
+    o, d = ref["o"], ref["d"]
+    p = np.empty(3)
+    for b in range(3):
+        if b == ia:
+            p[b] = ijk[b] if d[b] > 0 else ijk[b] + 1
+        else:
+            p[b] = np.clip(f32(o[b] + f32(tin * d[b])), ijk[b], ijk[b] + 1)
+    return p
+
+
+def map_rays(rays, m):
+    """World rays into an instance's object space, x = A x + b row by row in float32."""
+    A, b = m[:, :3], m[:, 3]
+    ro = rays.copy()
+    for a in range(3):
+        ro[:, a] = ((A[a, 0] * rays[:, 0] + A[a, 1] * rays[:, 1]) + A[a, 2] * rays[:, 2]) + b[a]
+        ro[:, 3 + a] = (A[a, 0] * rays[:, 3] + A[a, 1] * rays[:, 4]) + A[a, 2] * rays[:, 5]
+    return ro
+
+
+def test_pairs_world_normal_is_inverse_transpose():
+    """Sec. 4: the winning pair's normal returns to world space.  A normal is a covector, so
+    with x_obj = A x_world + b it maps as normalize(A^T n_obj).  The +-identity network makes
+    n_obj = normalize(first entry point) in closed form from the brute-force voxel list; A is a
+    rotation times a non-uniform scale times a shear, so A n_obj would differ on almost every
+    ray."""
+    V = 8
+    rng = np.random.default_rng(41)
+    occ = rng.uniform(size=V ** 3) < 0.3
+    obj = tiny_object(V, occ, L=1, F=3, log2_T=10, R=[V], H=6, tables=vertex_table(V),
+                      weights=identity_network(1, 3, 6))
+    c, s = np.cos(0.7), np.sin(0.7)
+    rot = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+    A = rot @ np.diag([1.3, 0.7, 1.1]) @ np.array([[1.0, 0.4, 0.0], [0.0, 1.0, -0.3], [0.0, 0.0, 1.0]])
+    m = np.concatenate([A, np.array([[0.1], [-0.2], [0.05]])], 1).astype(f32)
+    Af = m[:, :3].astype(np.float64)
+    rays = adversarial_rays(rng, V, 300)
+    n = len(rays)
+    r = oracle.query_pairs([obj], [(0, m)], rays, np.arange(n, dtype=np.uint32),
+                           np.zeros(n, np.uint32))
+    ro = map_rays(rays, m)
+    checked = discriminating = 0
+    for i in range(n):
+        ref = voxel_list(ro[i], occ, V, obj.bmin, obj.bmax, 6)
+        if ref is None or not ref["vox"]:
+            assert r["hit"][i] == 0
+            continue
+        p = first_entry_point(ref)
+        if p.sum() <= 0 or ro[i, 7] < ref["ta"]:
+            continue
+        assert r["hit"][i] == 1 and r["winner"][i] == 0
+        n_obj = p / np.linalg.norm(p)
+        want = Af.T @ n_obj
+        want /= np.linalg.norm(want)
+        assert np.allclose(r["normal"][i], want, atol=2e-6), (i, r["normal"][i], want)
+        wrong = Af @ n_obj
+        wrong /= np.linalg.norm(wrong)
+        discriminating += np.abs(wrong - want).max() > 1e-2
+        checked += 1
+    assert checked > 100 and discriminating > 0.9 * checked
+
+
+def test_local_hit_distance_sigmoid_direction():
+    """Sec. 5.3: the hit distance is predicted on the ray's AABB interval [ta, tb] as
+    t = ta + sigmoid(z_t) (tb - ta), so a positive logit moves the hit toward tb.  Here the
+    t logit is k (p_x - p_y) for the first entry point p (known in closed form), which takes
+    both signs; sigmoid(-z) or 1 - sigmoid(z) would put t on the other side of the midpoint."""
+    V = 8
+    rng = np.random.default_rng(43)
+    occ = rng.uniform(size=V ** 3) < 0.3
+    net = identity_network(1, 3, 6)
+    k = 0.6
+    net[2][1, :] = 0.0
+    net[2][1, 0], net[2][1, 3] = k, -k          # +k x+ - k x-  = k p_x
+    net[2][1, 1], net[2][1, 4] = -k, k          # -k y+ + k y-  = -k p_y
+    obj = tiny_object(V, occ, L=1, F=3, log2_T=10, R=[V], H=6, tables=vertex_table(V), weights=net)
+    rays = adversarial_rays(rng, V, 400)
+    r = oracle.query(obj, rays)
+    pos = neg = 0
+    for i, ray in enumerate(rays):
+        ref = voxel_list(ray, occ, V, obj.bmin, obj.bmax, 6)
+        if ref is None or not ref["vox"]:
+            continue
+        p = first_entry_point(ref)
+        if p.sum() <= 0 or ray[7] < ref["ta"]:
+            continue
+        z = k * (p[0] - p[1])
+        ta, tb = np.float64(ref["ta"]), np.float64(ref["tb"])
+        want = ta + (tb - ta) / (1.0 + np.exp(-z))
+        assert r["hit"][i] == 1
+        assert abs(np.float64(r["t"][i]) - want) <= 1e-6 * max(abs(want), tb - ta), (i, r["t"][i], want)
+        if abs(z) > 0.3:
+            flipped = ta + (tb - ta) / (1.0 + np.exp(z))
+            assert abs(flipped - want) > 1e-3 * (tb - ta)
+            pos += z > 0
+            neg += z < 0
+    assert pos > 30 and neg > 30
