@@ -246,6 +246,10 @@ lsnif_status lsnif_create(const lsnif_ctx_desc *desc, lsnif_ctx **out)
         HIP_TRY(hipGetDeviceCount(&n));
         if (dev < 0 || dev >= n) return fail(LSNIF_E_INVALID, "device %d not in [0, %d)", dev, n);
     }
+    if (dev >= 0) {
+        const lsnif_status st = noalloc_init(dev);
+        if (st) return st;
+    }
     lsnif_ctx *c = new (std::nothrow) lsnif_ctx();
     if (!c) return fail(LSNIF_E_NOMEM, "host allocation failed");
     c->device = dev;
@@ -696,7 +700,8 @@ static lsnif_status walk_then_query(lsnif_ctx *ctx, QueryArgs A, bool pairs, boo
 }
 
 lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
-                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws, int chunks, float *gather_sums)
+                           const lsnif_debug_bufs *dbg, hipStream_t s, void *ws, int chunks, float *gather_sums,
+                           bool timed)
 {
     QueryArgs A{};
     A.g = ob.geom;
@@ -727,7 +732,7 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
         A.dbg.act_amax = dbg->act_amax;
     }
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    if (ctx->profiling) {
+    if (ctx->profiling && timed) {
         for (auto &e : ev)
             if (!(e = take_event(ctx))) return fail(LSNIF_E_DEVICE, "hipEventCreate failed");
         HIP_TRY(hipEventRecord(ev[0], s));

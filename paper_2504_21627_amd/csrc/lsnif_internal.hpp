@@ -139,7 +139,10 @@ lsnif_status check_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_
 // (<= 0: the object's tuning; 1: the walk of the whole batch first).
 lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
                            const lsnif_debug_bufs *dbg, hipStream_t s, void *ws, int chunks = 0,
-                           float *gather_sums = nullptr);
+                           float *gather_sums = nullptr, bool timed = true);
+// Device address of the allocation-free query's scratch array on `device`, taken once
+// per device (with that device current) at context creation.
+lsnif_status noalloc_init(int device);
 lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray *d_rays, uint32_t n_rays,
                            const uint32_t *d_pair_ray, const uint32_t *d_pair_inst, uint32_t n_pairs,
                            const lsnif_instance *d_inst, uint32_t n_inst, lsnif_hit *d_out, hipStream_t s, void *ws,

@@ -115,6 +115,7 @@ def load():
     lib.lsnif_release.argtypes = [C.c_void_p, C.c_uint32]
     lib.lsnif_object_bytes.argtypes = [C.c_void_p, C.c_uint32, C.POINTER(C.c_uint64)]
     lib.lsnif_query.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
+    lib.lsnif_query_noalloc.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p]
     lib.lsnif_query_debug.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_void_p,
                                       C.POINTER(lsnif_debug_bufs), C.c_void_p]
     lib.lsnif_query_pairs.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
@@ -260,6 +261,18 @@ def lsnif_query(ctx, object_id, rays, out, stream=None):
     assert rays.is_cuda and out.is_cuda and out.shape[0] >= n
     _check(load().lsnif_query(ctx, object_id, C.c_void_p(rays.data_ptr()), n,
                               C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+
+
+def lsnif_query_noalloc(ctx, object_id, rays, out, stream=None):
+    """``lsnif_query`` with its workspace in the library's fixed per-device scratch array
+    (``NOALLOC_SCRATCH_BYTES``); allocates nothing."""
+    n = rays.shape[0]
+    assert rays.is_cuda and out.is_cuda and out.shape[0] >= n
+    _check(load().lsnif_query_noalloc(ctx, object_id, C.c_void_p(rays.data_ptr()), n,
+                                      C.c_void_p(out.data_ptr()), _stream_handle(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # LSNIF_NOALLOC_SCRATCH_BYTES of include/lsnif.h
 
 
 def lsnif_query_debug(ctx, object_id, rays, out, bufs: dict, stream=None):
