@@ -165,17 +165,20 @@ __global__ __launch_bounds__(kBlock) void k_pairs_payload(PairPlan P)
     const uint32_t r = P.pair_ray[p], i = P.pair_inst[p];
     const unsigned long long key = ((unsigned long long)ordered_bits(res.t) << 32) | (unsigned long long)i;
     if (key != P.minkey[r]) return;
+    // World normal: the object normal through the transpose of the 3x3 block of
+    // world_to_object (the inverse transpose of object_to_world), renormalised.
+    // float32 throughout; a few ulp of the unit normal, far inside the normal bar.
     const float *m = P.inst[i].world_to_object;
-    double wn[3];
+    float wn[3];
 #pragma unroll
-    for (int b = 0; b < 3; ++b)
-        wn[b] = (double)m[b] * res.n[0] + (double)m[4 + b] * res.n[1] + (double)m[8 + b] * res.n[2];
-    const double nn = sqrt(wn[0] * wn[0] + wn[1] * wn[1] + wn[2] * wn[2]);
+    for (int b = 0; b < 3; ++b) wn[b] = fmaf(m[8 + b], res.n[2], fmaf(m[4 + b], res.n[1], m[b] * res.n[0]));
+    const float nn2 = fmaf(wn[2], wn[2], fmaf(wn[1], wn[1], wn[0] * wn[0]));
+    const float inv = nn2 > 0.0f ? 1.0f / sqrtf(nn2) : 0.0f;
     lsnif_hit h;
     h.hit = 1;
     h.t = res.t;
 #pragma unroll
-    for (int b = 0; b < 3; ++b) h.n[b] = nn > 0.0 ? (float)(wn[b] / nn) : 0.0f;
+    for (int b = 0; b < 3; ++b) h.n[b] = wn[b] * inv;
     h.material = res.material;
     P.out[r] = h;
 }

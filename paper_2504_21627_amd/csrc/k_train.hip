@@ -11,14 +11,13 @@
 
 namespace lsnif {
 
-__global__ __launch_bounds__(kBlock) void k_train_fill(float *a, uint64_t na, float *b, uint64_t nb, double *acc)
+__global__ __launch_bounds__(kBlock) void k_train_fill(float *a, uint64_t na, float *b, uint64_t nb)
 {
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < na + nb; i += stride) {
         if (i < na) a[i] = 0.0f;
         else b[i - na] = 0.0f;
     }
-    if (acc && blockIdx.x == 0 && threadIdx.x == 0) *acc = 0.0;
 }
 
 // Forward: thread = (ray r, boundary point h): the point's L x F features,
@@ -272,11 +271,14 @@ __global__ __launch_bounds__(kBlock) void k_sum_copies(float *a, uint64_t n, uin
 
 __device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
 
-// Thread = ray: its loss (float64 sum over the batch) and d loss / d z.
+// Thread = ray: its loss and d loss / d z.  The block's rays' losses are summed
+// in float32 (waves, then the block) into loss_part[block]; k_train_loss_final
+// adds the blocks' sums in a fixed order, so the batch loss is deterministic.
 __global__ __launch_bounds__(kBlock) void k_train_loss(TrainLossArgs A)
 {
+    __shared__ float wsum[kBlock / 64];
     const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
-    double lsum = 0.0;
+    float lsum = 0.0f;
     if (r < A.n) {
         const float *z = A.z + (size_t)r * A.ldz;
         float *dz = A.dz + (size_t)r * A.ldz;
@@ -328,19 +330,36 @@ __global__ __launch_bounds__(kBlock) void k_train_loss(TrainLossArgs A)
                         d[m0 + k] = expf(z[m0 + k] - mx) / sum - ((int32_t)k == y.material ? 1.0f : 0.0f);
                 }
             }
-            lsum = (double)l;
+            lsum = l;
 #pragma unroll
             for (int k = 0; k < kMaxOut; ++k) d[k] *= inv_n;
         }
         for (uint32_t k = 0; k < A.out_dim; ++k) dz[k] = d[k];
     }
     for (int o = 32; o >= 1; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-    if ((threadIdx.x & 63u) == 0 && lsum != 0.0) unsafeAtomicAdd(A.loss_acc, lsum);
+    if ((threadIdx.x & 63u) == 0) wsum[threadIdx.x >> 6] = lsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float b = 0.0f;
+        for (uint32_t k = 0; k < kBlock / 64; ++k) b += wsum[k];
+        A.loss_part[blockIdx.x] = b;
+    }
 }
 
-__global__ void k_train_loss_final(const double *acc, uint32_t n, float *loss)
+// One block: the mean loss of the batch from the per-block sums.
+__global__ __launch_bounds__(kBlock) void k_train_loss_final(const float *part, uint32_t nparts, uint32_t n,
+                                                             float *loss)
 {
-    if (threadIdx.x == 0) loss[0] = (float)(acc[0] / (double)n);
+    __shared__ float red[kBlock];
+    float s = 0.0f;
+    for (uint32_t i = threadIdx.x; i < nparts; i += kBlock) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t h = kBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0] / (float)n;
 }
 
 __global__ __launch_bounds__(kBlock) void k_adam(AdamArgs A)
@@ -362,9 +381,9 @@ static uint32_t stream_blocks(uint64_t count)
     return (uint32_t)(b < 8192 ? (b ? b : 1) : 8192);
 }
 
-hipError_t launch_train_fill(float *a, uint64_t na, float *b, uint64_t nb, double *acc, hipStream_t s)
+hipError_t launch_train_fill(float *a, uint64_t na, float *b, uint64_t nb, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_train_fill, dim3(stream_blocks(na + nb)), dim3(kBlock), 0, s, a, na, b, nb, acc);
+    hipLaunchKernelGGL(k_train_fill, dim3(stream_blocks(na + nb)), dim3(kBlock), 0, s, a, na, b, nb);
     return hipGetLastError();
 }
 
@@ -413,9 +432,10 @@ hipError_t launch_train_loss(const TrainLossArgs &A, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_train_loss_final(const double *acc, uint32_t n, float *loss, hipStream_t s)
+hipError_t launch_train_loss_final(const float *part, uint32_t n, float *loss, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_train_loss_final, dim3(1), dim3(64), 0, s, acc, n, loss);
+    const uint32_t nparts = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_train_loss_final, dim3(1), dim3(kBlock), 0, s, part, nparts, n, loss);
     return hipGetLastError();
 }
 

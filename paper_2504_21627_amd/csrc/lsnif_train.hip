@@ -70,7 +70,7 @@ struct StepWs {
     float *act[8];    // act[k] = [n][width], k = 1 .. n_hidden
     float *z, *dz;    // [n][out_dim]
     float *part;      // partial weight-gradient products
-    double *acc;
+    float *loss_part; // per-block loss sums
 };
 
 constexpr uint32_t kCopyBudget = 1u << 30;   // bytes for the table-gradient copies
@@ -104,7 +104,7 @@ size_t step_ws_bytes(const Object &ob, uint32_t n)
     const size_t in = (size_t)ob.geom.H * ob.geom.L * ob.geom.F, od = (size_t)ob.mlp.out_dim;
     return al256((size_t)n * (ob.geom.H / 2) * 4) + al256(n) + al256((size_t)n * in * 4) +
            (size_t)ob.mlp.n_hidden * al256((size_t)n * ob.width * 4) + 2 * al256((size_t)n * od * 4) +
-           al256(part_floats(ob, n) * 4) + 256;
+           al256(part_floats(ob, n) * 4) + al256((size_t)(n + kBlock - 1) / kBlock * 4);
 }
 
 StepWs carve(const Object &ob, uint32_t n, void *ws)
@@ -128,7 +128,7 @@ StepWs carve(const Object &ob, uint32_t n, void *ws)
     w += al256((size_t)n * od * 4);
     S.part = reinterpret_cast<float *>(w);
     w += al256(part_floats(ob, n) * 4);
-    S.acc = reinterpret_cast<double *>(w);
+    S.loss_part = reinterpret_cast<float *>(w);
     return S;
 }
 
@@ -144,7 +144,7 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
     float *tab = static_cast<float *>(ob.d_tab);
     float *W = static_cast<float *>(const_cast<void *>(ob.d_w));
     float *gtab = tr->grad, *gW = tr->grad + tr->copies * tr->n_tab;
-    HIP_TRY(launch_train_fill(gtab, tr->copies * tr->n_tab, gW, tr->n_w, S.acc, s));
+    HIP_TRY(launch_train_fill(gtab, tr->copies * tr->n_tab, gW, tr->n_w, s));
     // voxel lists: the query path's walk, rays in their given order
     QueryArgs A{};
     A.g = ob.geom;
@@ -200,7 +200,7 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
     Lo.out_dim = od;
     Lo.n_mat = (uint32_t)mlp.n_mat;
     Lo.has_albedo = (uint32_t)mlp.has_albedo;
-    Lo.loss_acc = S.acc;
+    Lo.loss_part = S.loss_part;
     HIP_TRY(launch_train_loss(Lo, s));
     // backward: g holds d loss / d (output of layer k)
     const float *g = S.dz;
@@ -244,7 +244,7 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
     }
     HIP_TRY(launch_train_encode(E, true, s));   // E.x = x0, now d loss / d encoding
     HIP_TRY(launch_sum_copies(gtab, tr->n_tab, tr->copies, s));
-    if (d_loss) HIP_TRY(launch_train_loss_final(S.acc, n, d_loss, s));
+    if (d_loss) HIP_TRY(launch_train_loss_final(S.loss_part, n, d_loss, s));
     return LSNIF_OK;
 }
 

@@ -48,7 +48,7 @@ struct TrainLossArgs {
     const float *z;           // [n][ldz] raw outputs
     float *dz;                // [n][ldz] d loss / d z
     uint32_t ldz, out_dim, n_mat, has_albedo;
-    double *loss_acc;         // sum of the per-ray losses
+    float *loss_part;         // per-block sums of the per-ray losses, one float per block
 };
 
 struct AdamArgs {
@@ -58,7 +58,7 @@ struct AdamArgs {
     float lr, b1, b2, eps, c1, c2;   // c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)
 };
 
-hipError_t launch_train_fill(float *a, uint64_t na, float *b, uint64_t nb, double *acc, hipStream_t s);
+hipError_t launch_train_fill(float *a, uint64_t na, float *b, uint64_t nb, hipStream_t s);
 hipError_t launch_train_encode(const TrainEncArgs &A, bool backward, hipStream_t s);
 hipError_t launch_train_gemm(const GemmArgs &G, int epi, hipStream_t s);
 // dst[i ld + j] = sum over z < nz of part[(z M + i) N + j], i < M, j < N; part2 holds
@@ -69,7 +69,7 @@ hipError_t launch_sum_partials(const float *part, uint32_t nz, uint32_t M, uint3
 // a[i] += sum over r = 1 .. copies-1 of a[r n + i], i < n.
 hipError_t launch_sum_copies(float *a, uint64_t n, uint32_t copies, hipStream_t s);
 hipError_t launch_train_loss(const TrainLossArgs &A, hipStream_t s);
-hipError_t launch_train_loss_final(const double *acc, uint32_t n, float *loss, hipStream_t s);
+hipError_t launch_train_loss_final(const float *part, uint32_t n, float *loss, hipStream_t s);
 hipError_t launch_adam(const AdamArgs &A, hipStream_t s);
 
 }  // namespace lsnif
