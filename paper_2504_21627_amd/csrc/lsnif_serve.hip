@@ -359,11 +359,29 @@ private:
                     ++it;
                 }
             }
-            // admission, in arrival order
+            // admission, in arrival order.  The workspace is sized again here, under the
+            // context's lock held until the request is enqueued: a build, release or tuning
+            // change since submit may have changed the layout the query will use.
             while (!queue_.empty() && inflight_.size() < cfg_.max_inflight) {
                 const uint64_t t = queue_.front();
                 Req &q = reqs_[t];
-                if (!arena_.alloc(q.need, q.off)) break;
+                std::unique_lock<std::recursive_mutex> cg(ctx_->mu, std::defer_lock);
+                if (!dry_) cg.lock();
+                size_t need = 0;
+                lsnif_status zst = sizing(q.r, need);
+                if (!zst && need > arena_.size())
+                    zst = fail(LSNIF_E_NOMEM, "request needs %llu bytes of workspace, the budget is %llu",
+                               (unsigned long long)need, (unsigned long long)arena_.size());
+                if (zst) {   // it can no longer run: it ends without holding a slot
+                    queue_.pop_front();
+                    q.state = zst;
+                    q.t_done = Clock::now();
+                    ++failed_;
+                    changed = true;
+                    continue;
+                }
+                if (!arena_.alloc(need, q.off)) break;
+                q.need = need;
                 queue_.pop_front();
                 q.stream = (int)(next_stream_++ % std::max<uint32_t>(1, cfg_.n_streams));
                 q.t_admit = Clock::now();
