@@ -341,23 +341,24 @@ def test_grazing_recheck_parity(L, ctx, mlp):
     assert changed >= 20, changed
 
 
-@pytest.mark.parametrize("width", [64, 128])
+@pytest.mark.parametrize("width,H", [(128, 18), (64, 10), (64, 18)])
 @pytest.mark.parametrize("feat,mlp", [("fp32", "fp32"), ("fp16", "fp16"), ("fp16", "bf16")])
-def test_paper_shaped_object_parity(L, ctx, c1, feat, mlp, width):
+def test_paper_shaped_object_parity(L, ctx, c1, feat, mlp, width, H):
     """An object shaped like the paper's default (Sec. 5.1): V = 32 surface voxels, two
     face-aligned hashed levels (R = 64, 128; 2^17 entries) of 3 features, a 2-hidden-layer
-    leaky-ReLU MLP of width 128 (the paper's) or 64 (its low-quality variant's) and the
-    albedo head (8 + 4 outputs).  Exercises the F = 3 gathers, the 4-corner collapse on both
-    levels, leaky ReLU, the albedo outputs and the width-128 kernels."""
+    leaky-ReLU MLP and the albedo head (8 + 4 outputs): width 128 with H = 18 points (the
+    paper's default), width 64 with H = 10 (its low-quality variant, Sec. 6.4), and width
+    64 with H = 18.  Exercises the F = 3 gathers, the 4-corner collapse on both levels,
+    leaky ReLU, the albedo outputs, the width-128 kernels and the shorter point cap."""
     from tests.test_oracle_pins import tiny_object
     base = c1["objects"][0]
     occ = np.unpackbits(base.occ.view(np.uint8), bitorder="little").astype(bool)[: base.V ** 3]
-    obj = tiny_object(base.V, occ, L=2, F=3, log2_T=17, R=[64, 128], H=18, width=width, n_hidden=2,
+    obj = tiny_object(base.V, occ, L=2, F=3, log2_T=17, R=[64, 128], H=H, width=width, n_hidden=2,
                       n_mat=4, has_albedo=1, act=1, bmin=tuple(base.bmin), bmax=tuple(base.bmax), seed=21)
     obj.tables *= np.float32(1e-2)
     assert obj.out_dim == 12
     rays = c1["rays"]
-    _say(f"paper-shaped object {feat}/{mlp} width {width}: {len(rays)} rays")
+    _say(f"paper-shaped object {feat}/{mlp} width {width} H {H}: {len(rays)} rays")
     oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
     try:
         g = gpu_query(L, ctx, oid, rays, debug=True, obj=obj)
