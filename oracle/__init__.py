@@ -225,3 +225,35 @@ def query_pairs(objects, instances, rays, pair_ray, pair_inst):
     if rc != 0:
         raise RuntimeError(f"oracle_query_pairs failed ({rc})")
     return r
+
+
+def layer_inputs(obj, enc):
+    """The input of every layer of the object's MLP (Sec. 5.1; bias-free layers, ReLU or
+    leaky ReLU between them) for encodings ``enc`` (n, in_dim), in float64, and the raw
+    outputs: ``([x_0 = enc, x_1, ..., x_last], out)``, each x_k of shape (n, dims_k).
+    Each layer is one float64 matrix product (numpy), then the activation."""
+    x = np.asarray(enc, np.float64)
+    xs = [x]
+    for k, w in enumerate(obj.weights):
+        y = x @ np.asarray(w, np.float64).T
+        if k + 1 < len(obj.weights):
+            y = np.maximum(y, 0.0) if obj.act == 0 else np.where(y > 0.0, y, float(np.float32(obj.leaky_slope)) * y)
+            xs.append(y)
+        x = y
+    return xs, x
+
+
+def act_amax(obj, rays, chunk=16384):
+    """Per-layer activation range for the FP8-e4m3 MLP's static scales (reading of the
+    configs' "per-layer scale"): the largest |input| of each layer over a calibration
+    batch of rays, in float64, from the oracle's own encodings.  Rays without a
+    candidate voxel do not run the network and contribute nothing."""
+    amax = np.zeros(len(obj.weights))
+    for a in range(0, len(rays), chunk):
+        o = query(obj, rays[a:a + chunk], debug=True)
+        cand = o["count"] > 0
+        if not cand.any():
+            continue
+        xs, _ = layer_inputs(obj, o["enc"][cand])
+        amax = np.maximum(amax, [np.abs(x).max() for x in xs])
+    return amax

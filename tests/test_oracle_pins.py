@@ -297,6 +297,29 @@ def test_leaky_relu_network_matches_blas():
     assert np.allclose(r["out"][m], x.T[m], rtol=1e-12, atol=1e-300)
 
 
+@pytest.mark.parametrize("act", [0, 1])
+def test_layer_inputs_and_act_amax(act):
+    """oracle.layer_inputs ends in the C oracle's own raw outputs (1e-12), for ReLU and leaky
+    ReLU; act_amax takes each layer's largest |input| over the candidate rays, so its first
+    entry is the largest |encoding| and the others are positive (ReLU outputs of a
+    Kaiming-initialised network on nonzero encodings)."""
+    V = 8
+    occ = np.random.default_rng(7).uniform(size=V ** 3) < 0.5
+    obj = tiny_object(V, occ, L=2, F=2, R=[4, 8], H=10, width=16, n_hidden=2, act=act)
+    obj.leaky_slope = 0.01
+    rays = adversarial_rays(np.random.default_rng(7), V, 200)
+    r = oracle.query(obj, rays, debug=True)
+    m = r["count"] > 0
+    xs, out = oracle.layer_inputs(obj, r["enc"][m])
+    assert len(xs) == len(obj.weights)
+    assert [x.shape[1] for x in xs] == [w.shape[1] for w in obj.weights]
+    assert np.allclose(out, r["out"][m], rtol=1e-12, atol=1e-13 * np.abs(r["out"][m]).max())
+    amax = oracle.act_amax(obj, rays, chunk=97)
+    assert amax[0] == np.abs(r["enc"][m]).max()
+    assert np.all(amax > 0)
+    assert np.allclose(amax, [np.abs(x).max() for x in xs], rtol=0, atol=0)
+
+
 def test_miss_invariants():
     """No occupied voxel on the ray -> miss, whatever the weights; zero network -> miss."""
     V = 8
