@@ -82,8 +82,22 @@ typedef struct lsnif_ctx lsnif_ctx;
 typedef struct {
     int32_t device;          /* HIP device ordinal; -1 = a host-only context (serving dry runs) */
     uint64_t hbm_budget;     /* bytes the context may hold for objects; 0 = no limit */
-    const char *autotune_cache; /* path of the tile-size cache, or NULL */
+    const char *autotune_cache; /* path of the autotune cache file, or NULL (see below) */
 } lsnif_ctx_desc;
+
+/* Autotune cache.  With a path, lsnif_create reads the file if it exists (a
+ * missing file is an empty cache; an unreadable or malformed file, or an entry
+ * out of lsnif_set_tuning's ranges, fails creation with LSNIF_E_INVALID), every
+ * lsnif_build whose object matches an entry starts with that entry's launch
+ * parameters instead of the defaults (no timing), and every successful
+ * lsnif_autotune / lsnif_autotune_pairs records its winners (per object, the
+ * object's whole lsnif_tuning after the call) and rewrites the file (a sibling
+ * temporary file renamed over it).  JSON: {"lsnif_autotune_cache": 1,
+ * "entries": {key: {"sort_bits", "pair_bits", "hot_lds_bytes", "walk_chunks",
+ * "persistent"}}},
+ * key = "<gfx arch> V=.. L=.. F=.. log2_T=.. H=.. width=.. feat=<dtype> mlp=<dtype>".
+ * Launch parameters change speed only, never a result.  Contexts that share a
+ * file and autotune concurrently keep the last writer's entries. */
 
 /*
  * One LSNIF object (Sec. 3.3, 5.1): voxels + sparse hash grid + MLP weights.
@@ -326,12 +340,22 @@ lsnif_status lsnif_bounce(lsnif_ctx *ctx, const lsnif_ray *d_rays, const lsnif_h
  *                 share the GPU.  1 (the default) walks the whole batch first.
  *                 Ranges hold at least 256 tiles; the serving loop always walks
  *                 whole requests.
+ *  persistent     0 or 1: with 1, width-64 objects with a matrix-core MLP
+ *                 run the query kernel as a persistent grid (as many
+ *                 workgroups as the GPU holds at once) whose workgroups on
+ *                 each XCD take tiles from that XCD's own contiguous eighth of
+ *                 the coherence order, then from the tails of the others, so
+ *                 each XCD's L2 serves one region of rays (or one object's
+ *                 pairs) at a time; 0 launches one workgroup per tile, dealt to
+ *                 the XCDs in runs of 8.  Width-128 and FP32-MLP objects always
+ *                 take one workgroup per tile.
  * lsnif_autotune times each candidate (sort_bits 0, 4, 5, 6 x hot_lds_bytes 0,
- * 20480, 40960, then walk_chunks 1, 2, 4, 8 for the best of those) on the
+ * 20480, 40960, then walk_chunks 1, 2, 4, 8, then persistent 0 and 1, each for
+ * the best so far) on the
  * caller's batch, a warm-up and three timed queries each on a private stream,
  * keeps the fastest for the object and returns it.  lsnif_autotune_pairs does
  * the same for a pair query (pair_bits 2, 3, 4, 5 x hot_lds_bytes, then
- * walk_chunks), applying one choice to every object of the context.  Both
+ * walk_chunks, then persistent), applying one choice to every object of the context.  Both
  * overwrite d_out, synchronise the device and, like lsnif_set_tuning, make the
  * context's captured graphs stale.
  */
@@ -340,6 +364,7 @@ typedef struct {
     int32_t pair_bits;
     int32_t hot_lds_bytes;
     int32_t walk_chunks;
+    int32_t persistent;
 } lsnif_tuning;
 
 lsnif_status lsnif_get_tuning(lsnif_ctx *ctx, uint32_t object_id, lsnif_tuning *tuning);
@@ -385,8 +410,15 @@ void lsnif_graph_destroy(lsnif_graph *graph);
  * requests in arrival order as soon as a slot and workspace within the HBM
  * budget are free, spreads admitted requests over several HIP streams so
  * their kernels overlap on the device, and frees each request's slot and
- * workspace when its work completes.  Results are those of the direct calls:
- * a request's answer does not depend on what else is in flight.
+ * workspace when its work completes.  Small requests waiting together are
+ * merged: the request at the head of the queue and the ones right behind it
+ * with the same target (the same object_id, or pairs over the same d_inst and
+ * n_inst), each of at most merge_rays rays, up to merge_max requests and
+ * 2,097,152 rays in all, are admitted as one launch that takes one slot: their
+ * rays and pairs are staged into one batch in the launch's workspace, one
+ * query answers it, and each request's answers are copied to its own d_out;
+ * they complete together.  Results are those of the direct calls: a request's
+ * answer does not depend on what else is in flight or merged with it.
  *
  * The serve calls are thread-safe.  The caller owns every buffer a request
  * names and keeps it alive until the request is done; buffers are device
@@ -399,7 +431,9 @@ typedef struct {
     uint32_t max_queue;     /* waiting requests beyond which submit returns LSNIF_E_BUSY; 0 = 65536 */
     uint64_t dry_run_ns_per_ray; /* > 0: touch no device; a request "completes" this many ns per
                                     ray after admission and writes nothing (tests of the
-                                    admission logic on hosts without a GPU) */
+                                    admission logic on hosts without a GPU; no merging) */
+    uint32_t merge_rays;    /* largest request (rays) that may be merged; 0 = 262144 */
+    uint32_t merge_max;     /* requests per merged launch, 1..32 (1: no merging); 0 = 32 */
 } lsnif_serve_cfg;
 
 enum { LSNIF_REQ_SINGLE = 0, LSNIF_REQ_PAIRS = 1 };
@@ -426,6 +460,7 @@ typedef struct {
     uint64_t ws_bytes_peak;          /* most workspace held at once */
     double p50_ms, p99_ms, mean_ms, max_ms;   /* submit -> completion, completed requests */
     double elapsed_s;                /* since lsnif_serve_start */
+    uint64_t launches;               /* admitted launches (a merged launch answers several requests) */
 } lsnif_serve_stats;
 
 /* Request states reported by lsnif_serve_poll (negative values are the final
@@ -527,6 +562,16 @@ lsnif_status lsnif_train_step(lsnif_trainer *tr, const lsnif_ray *d_rays, const 
  * row-major [out][in] as in lsnif_object_desc; *steps = Adam steps taken. */
 lsnif_status lsnif_trainer_read(lsnif_trainer *tr, float *tables, float *const *W, float *grad_tables,
                                 float *const *grad_W, uint64_t *steps);
+/* Training kernel time.  While the trainer's context has kernel timing on
+ * (lsnif_profile_enable), every lsnif_train_grads / lsnif_train_step records
+ * HIP events on its stream around the forward layer products, around the
+ * backward layer products (weight and input gradients, with the partial-product
+ * sums), and around the scatter of the encoding's gradient onto the tables.
+ * This call waits for those events and returns, summed over the steps since
+ * the last read, the layer products' milliseconds (forward + backward) and the
+ * scatter's, and the number of steps (any pointer may be NULL). */
+lsnif_status lsnif_train_profile_read(lsnif_trainer *tr, double *products_ms, double *scatter_ms,
+                                      uint32_t *steps);
 
 /* Kernel timing.  While enabled, every query on the context records HIP
  * events on its stream before the coherence sort (pair queries: the pair

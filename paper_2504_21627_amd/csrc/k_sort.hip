@@ -6,6 +6,10 @@
 // walks and their hash-grid gathers touch the same cache lines.  Order within
 // a key is whatever the atomics give; every ray's result is independent of
 // the order the rays are processed in.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "lsnif_kernels.hpp"
 #include "lsnif_launch.hpp"
 
@@ -140,6 +144,42 @@ hipError_t launch_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *part, hipStr
     hipLaunchKernelGGL(k_scan_partial, dim3(nblocks), dim3(kBlock), 0, s, v, n, part);
     hipLaunchKernelGGL(k_scan_final, dim3(nblocks), dim3(kBlock), 0, s, v, n, part);
     return hipGetLastError();
+}
+
+__global__ void k_clear_queue(unsigned long long *q)
+{
+    if (threadIdx.x < 8) q[threadIdx.x] = 0ull;
+}
+
+hipError_t launch_clear_queue(unsigned long long *q, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_queue, dim3(1), dim3(64), 0, s, q);
+    return hipGetLastError();
+}
+
+uint32_t persistent_blocks(const void *kernel, size_t lds, uint32_t tiles)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, size_t>, uint32_t> known;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    uint32_t nb = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = known.find({dev, kernel, lds});
+        if (it != known.end()) nb = it->second;
+    }
+    if (!nb) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, lds) != hipSuccess) per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 8;
+        nb = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)(cus > 0 ? cus : 8);
+        nb = nb < 8 ? 8 : nb / 8 * 8;
+        std::lock_guard<std::mutex> lk(mu);
+        known[{dev, kernel, lds}] = nb;
+    }
+    const uint32_t want = (tiles + 7u) / 8u * 8u;
+    return want < nb ? (want ? want : 8u) : nb;
 }
 
 hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *keys, uint32_t *hist,

@@ -254,6 +254,14 @@ lsnif_status lsnif_create(const lsnif_ctx_desc *desc, lsnif_ctx **out)
     if (!c) return fail(LSNIF_E_NOMEM, "host allocation failed");
     c->device = dev;
     c->budget = desc ? desc->hbm_budget : 0;
+    c->arch = device_arch(dev);
+    if (desc && desc->autotune_cache && desc->autotune_cache[0]) {
+        c->cache_path = desc->autotune_cache;
+        if (const lsnif_status st = cache_load(c)) {
+            delete c;
+            return st;
+        }
+    }
     *out = c;
     return LSNIF_OK;
 }
@@ -343,6 +351,16 @@ lsnif_status lsnif_build(lsnif_ctx *ctx, const lsnif_object_desc *d, uint32_t *o
     ob.esz = (uint32_t)(d->F * dtype_size(d->feat_dtype));
     ob.hot_budget = 0;   // hot levels are off until a tuning asks for them
     plan_hot_levels(g, ob.esz, ob.hot_budget);
+    // an autotune cache entry for this architecture, shape and precision replaces the defaults
+    auto cached = ctx->cache.find(cache_key(ctx, ob));
+    if (cached != ctx->cache.end()) {
+        g.sort_bits = (uint32_t)cached->second.sort_bits;
+        g.pair_bits = (uint32_t)cached->second.pair_bits;
+        ob.hot_budget = (uint32_t)cached->second.hot_lds_bytes;
+        ob.walk_chunks = (uint32_t)cached->second.walk_chunks;
+        ob.persistent = (uint32_t)cached->second.persistent;
+        plan_hot_levels(g, ob.esz, ob.hot_budget);
+    }
     // occupancy as 4x4x4 bricks: one 64-bit mask per brick, then one bit per brick
     const int V = d->V, NB = (V + 3) / 4;
     const size_t nbricks = (size_t)NB * NB * NB;
@@ -640,9 +658,12 @@ static size_t list_ws_bytes(size_t n_slots, uint32_t cap)
     return al256(n_slots) + al256(n_slots * cap * sizeof(uint32_t));
 }
 
+// The persistent query kernel's 8 tile-queue counters: one 256-byte granule after the lists.
+constexpr size_t kQueueBytes = 256;
+
 size_t query_ws_bytes(uint32_t n, uint32_t sort_bits, uint32_t cap)
 {
-    return sort_ws_bytes(n, sort_bits) + list_ws_bytes(n, cap);
+    return sort_ws_bytes(n, sort_bits) + list_ws_bytes(n, cap) + kQueueBytes;
 }
 
 size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs, uint32_t cap, uint32_t pair_bits)
@@ -650,7 +671,7 @@ size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs, uint32
     const size_t n_slots = (size_t)(n_pairs + kBlock - 1) / kBlock * kBlock + (size_t)kBlock * n_objs;
     return al256((size_t)n_rays * 8) + al256((size_t)n_pairs * sizeof(PairRes)) + al256((size_t)n_pairs * 4) +
            al256(n_slots * 4) + al256(n_slots / kBlock * 4) + al256((size_t)n_objs * pair_bins(pair_bits) * 4) +
-           2 * al256((size_t)n_objs * 4) + list_ws_bytes(n_slots, cap);
+           2 * al256((size_t)n_objs * 4) + list_ws_bytes(n_slots, cap) + kQueueBytes;
 }
 
 // The walk kernel, then the query kernel, over `ntiles` tiles.  With k > 1 tile
@@ -750,6 +771,8 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
     char *wl = static_cast<char *>(ws) + sort_bytes;
     A.nvox = reinterpret_cast<uint8_t *>(wl);
     A.lists = reinterpret_cast<uint32_t *>(wl + al256(n));
+    A.queue = reinterpret_cast<unsigned long long *>(wl + list_ws_bytes(n, ob.geom.H >> 1));
+    A.persistent = ob.persistent && !dbg && !gather_sums ? 1u : 0u;
     const int kbm = ob.mlp.kb_point;
     const uint32_t k = dbg ? 1u : (chunks > 0 ? (uint32_t)chunks : ob.walk_chunks);
     lsnif_status st = walk_then_query(ctx, A, false, ob.geom.recheck != 0, grid, k, s, ev[2],
@@ -817,6 +840,7 @@ lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps)
         ps.recheck = ps.recheck || kv.second.geom.recheck;
         ps.walk_chunks = std::max(ps.walk_chunks, kv.second.walk_chunks);
         ps.pair_bits = std::max(ps.pair_bits, kv.second.geom.pair_bits);
+        ps.persistent = std::max(ps.persistent, kv.second.persistent);
     }
     lsnif_status st = upload_table(ctx, ps.n_objs);
     if (st) return st;
@@ -897,6 +921,8 @@ lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray
         A.pr.res = P.res;
         A.nvox = nvox;
         A.lists = lists;
+        A.queue = reinterpret_cast<unsigned long long *>(w + list_ws_bytes(n_slots, (uint32_t)ps.maxH >> 1));
+        A.persistent = ps.persistent;
         const int kbm = ps.kbm;
         const uint32_t k = chunks > 0 ? (uint32_t)chunks : ps.walk_chunks;
         lsnif_status st = walk_then_query(ctx, A, true, ps.recheck, n_tiles, k, s, ev[2],

@@ -39,6 +39,7 @@ struct Object {
     uint32_t esz = 0;             // bytes of one table entry on the device
     uint32_t hot_budget = kHotLdsBudget;   // LDS budget the hot levels were planned for
     uint32_t walk_chunks = kWalkChunks;    // tile ranges of a query whose walk runs ahead
+    uint32_t persistent = 0;               // query kernel as a persistent grid (width 64)
     uint64_t bytes = 0;
 };
 
@@ -108,6 +109,11 @@ struct lsnif_ctx {
     // serving loop, when started; `mu` orders the direct calls against it
     lsnif::Server *server = nullptr;
     std::recursive_mutex mu;
+    // autotune cache: the device's architecture name, the file's path (empty: none) and
+    // its entries, read at creation and rewritten by every autotune call
+    std::string arch;
+    std::string cache_path;
+    std::map<std::string, lsnif_tuning> cache;
 };
 
 namespace lsnif {
@@ -120,6 +126,7 @@ struct PairsSetup {
     bool recheck = false;   // some object re-decides grazing voxels in float64
     uint32_t walk_chunks = 1;   // largest walk_chunks of the objects
     uint32_t pair_bits = 1;     // finest pair grouping of the objects
+    uint32_t persistent = 0;    // some object asks for the persistent query kernel
     uint32_t n_objs = 0;
 };
 lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps);
@@ -140,6 +147,16 @@ lsnif_status check_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_
 lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_rays, uint32_t n, lsnif_hit *d_out,
                            const lsnif_debug_bufs *dbg, hipStream_t s, void *ws, int chunks = 0,
                            float *gather_sums = nullptr, bool timed = true);
+// Launch parameters: range checks, and setting them on an object (re-plans its hot levels).
+lsnif_status check_tuning(const lsnif_tuning *t);
+void apply_tuning(lsnif_ctx *ctx, Object &ob, const lsnif_tuning &t);
+lsnif_tuning object_tuning(const Object &ob);
+// Autotune cache (lsnif_cache.hip): architecture name of a device ("host" for -1), an
+// object's cache key, reading the file into ctx->cache and writing ctx->cache back.
+std::string device_arch(int device);
+std::string cache_key(const lsnif_ctx *ctx, const Object &ob);
+lsnif_status cache_load(lsnif_ctx *ctx);
+lsnif_status cache_save(lsnif_ctx *ctx);
 // Device address of the allocation-free query's scratch array on `device`, taken once
 // per device (with that device current) at context creation.
 lsnif_status noalloc_init(int device);

@@ -86,6 +86,9 @@ struct QueryArgs {
     uint32_t *lists;          // voxel lists by slot: entry j of slot i at lists[j n + i]
     uint8_t *nvox;            // listed voxels of each slot
     uint32_t tile0;           // first tile of the launch (a launch may cover a range of the tiles)
+    uint32_t n_tiles;         // tiles of the launch (persistent kernels: the range they share out)
+    unsigned long long *queue;   // persistent kernels: 8 tile-queue counters, zero at launch
+    uint32_t persistent;      // run the query kernel as a persistent grid (width-64 matrix-core kernels)
     uint32_t width;           // hidden width of the launch's objects (64 or 128), picks the kernel
     Dbg dbg;
     PairArgs pr;
@@ -522,6 +525,47 @@ __device__ __forceinline__ uint32_t block_tile(uint32_t tile0)
     return tile0 + ((k / C) * 8u + x) * C + k % C;
 }
 
+// Persistent query kernels: a grid of as many blocks as fit on the chip at once,
+// each taking tiles until none are left.  The launch's n_tiles tiles are cut
+// into 8 contiguous ranges of the coherence order, range x for the blocks that
+// run on XCD x (blockIdx mod 8: the dispatcher's round robin), so each XCD's
+// L2 serves one stretch of rays (or of one object's pairs) at a time.  A
+// block takes the next tile from the head of its own range; once that range
+// is empty it takes tiles from the tails of the other ranges.  Each range's
+// counter packs the head claims (low 32 bits) and the tail claims (high 32
+// bits) into one 64-bit word, so one atomic add both claims and sees the
+// other side: a head claim h is valid iff h + s < len, a tail claim iff
+// len - 1 - s >= h, for the (h, s) it read.  Every tile is claimed exactly
+// once, every claim fails once the range is used up, and each block leaves
+// when all eight ranges are: the grid always drains.
+constexpr uint32_t kNoTile = 0xffffffffu;
+
+__device__ __forceinline__ uint32_t queue_take(const QueryArgs &A, uint32_t x)
+{
+    for (uint32_t q = 0; q < 8u; ++q) {
+        const uint32_t v = (x + q) & 7u;
+        const uint32_t lo = (uint32_t)((uint64_t)A.n_tiles * v / 8u);
+        const uint32_t len = (uint32_t)((uint64_t)A.n_tiles * (v + 1u) / 8u) - lo;
+        unsigned long long *c = A.queue + v;
+        const unsigned long long seen = __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint64_t)(uint32_t)seen + (seen >> 32) >= len) continue;   // used up (the atomic decides)
+        const unsigned long long old = atomicAdd(c, q == 0 ? 1ull : (1ull << 32));
+        const uint32_t h = (uint32_t)old, s = (uint32_t)(old >> 32);
+        if ((uint64_t)h + s < len) return A.tile0 + lo + (q == 0 ? h : len - 1u - s);
+    }
+    return kNoTile;
+}
+
+// The block's next tile (kNoTile: none left), the same value for every thread.
+// The trailing barrier also ends the block's use of LDS for the previous tile.
+__device__ __forceinline__ uint32_t next_tile(const QueryArgs &A, uint32_t &s_tile)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) s_tile = queue_take(A, blockIdx.x & 7u);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(s_tile);
+}
+
 template <bool PAIRS>
 __device__ __forceinline__ void slot_ray(const QueryArgs &A, const Geom &g, uint32_t slot, uint32_t &r,
                                          uint32_t &pair, bool &live, VRay &w)
@@ -575,13 +619,13 @@ __device__ __forceinline__ void walk_body(const QueryArgs &A, const Geom &g, uin
 
 template <bool PAIRS>
 __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g, Shared &S, uint32_t *s_list,
-                                              Lane &L)
+                                              Lane &L, uint32_t tile)
 {
     const uint32_t tid = threadIdx.x;
     const int cap = g.H >> 1;
     if (tid <= (uint32_t)cap) S.hist[tid] = 0;
     __syncthreads();
-    const uint32_t slot0 = block_tile(A.tile0) * kBlock + tid;
+    const uint32_t slot0 = tile * kBlock + tid;
     uint32_t r0, pair0;
     bool live0;
     VRay w;
@@ -642,7 +686,7 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g,
     L.src = src;
     L.r = __float_as_uint(st[13 * kBlock + src]);
     L.pair = __float_as_uint(st[14 * kBlock + src]);
-    L.live = PAIRS ? L.pair != 0xffffffffu : block_tile(A.tile0) * kBlock + src < A.n;
+    L.live = PAIRS ? L.pair != 0xffffffffu : tile * kBlock + src < A.n;
 }
 
 // ---------------------------------------------------------------- float32 path
@@ -652,10 +696,10 @@ __device__ __forceinline__ void walk_and_sort(const QueryArgs &A, const Geom &g,
 // contiguous and every lane reads the same address.
 // Object of this block's tile: one value for the whole block, read through the
 // scalar path so that everything derived from it (tables, weights) stays uniform.
-__device__ __forceinline__ int tile_object(const PairArgs &P, uint32_t tile0)
+__device__ __forceinline__ int tile_object(const PairArgs &P, uint32_t tile)
 {
     typedef const __attribute__((address_space(4))) int32_t cint;
-    return __builtin_amdgcn_readfirstlane(((cint *)P.tile_obj)[block_tile(tile0)]);
+    return __builtin_amdgcn_readfirstlane(((cint *)P.tile_obj)[tile]);
 }
 // The object table, read through the constant address space in the device pass (the
 // host pass only type-checks kernel bodies and has no such address space).
@@ -670,13 +714,14 @@ typedef const __attribute__((address_space(4))) float cfloat;
 
 template <typename TF, int F, int WIDTH, bool PAIRS, bool HOT>
 __device__ __forceinline__ void query_f32_body(const QueryArgs &A, const Geom &g, const Mlp &mm,
-                                               const TF *__restrict__ tab, uint32_t *s_list, Shared &S)
+                                               const TF *__restrict__ tab, uint32_t *s_list, Shared &S,
+                                               uint32_t tile)
 {
     constexpr int NL = 4;
     Lane ln;
     uint32_t *hot = s_list + (A.g.H >> 1) * kBlock;   // after the voxel lists (sized for the launch)
     if constexpr (HOT) stage_hot_levels<TF, F>(g, tab, hot);
-    walk_and_sort<PAIRS>(A, g, S, s_list, ln);
+    walk_and_sort<PAIRS>(A, g, S, s_list, ln, tile);
     const uint32_t src = ln.src, r = ln.r;
     const bool live = ln.live;
     const VRay &w = ln.w;
@@ -768,19 +813,27 @@ __device__ __forceinline__ void query_f32_body(const QueryArgs &A, const Geom &g
 }
 
 template <typename TF, int F, int WIDTH, bool PAIRS, bool HOT>
+__device__ __forceinline__ void query_f32_tile(const QueryArgs &A, uint32_t *s_list, Shared &S, uint32_t tile)
+{
+    if constexpr (PAIRS) {
+        const int o = tile_object(A.pr, tile);
+        if (o < 0) return;
+        const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
+        query_f32_body<TF, F, WIDTH, true, HOT>(A, O.g, O.m, (const TF *)O.tables, s_list, S, tile);
+    } else {
+        query_f32_body<TF, F, WIDTH, false, HOT>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list, S,
+                                                 tile);
+    }
+}
+
+template <typename TF, int F, int WIDTH, bool PAIRS, bool HOT>
 __global__ __launch_bounds__(kBlock) void k_query_f32(QueryArgs A)
 {
     extern __shared__ uint32_t s_list[];
     __shared__ Shared S;
-    if constexpr (PAIRS) {
-        const int o = tile_object(A.pr, A.tile0);
-        if (o < 0) return;
-        const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
-        query_f32_body<TF, F, WIDTH, true, HOT>(A, O.g, O.m, (const TF *)O.tables, s_list, S);
-    } else {
-        query_f32_body<TF, F, WIDTH, false, HOT>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list, S);
-    }
+    query_f32_tile<TF, F, WIDTH, PAIRS, HOT>(A, s_list, S, block_tile(A.tile0));
 }
+
 
 // ------------------------------------------------------------ matrix-core path
 //
@@ -916,7 +969,8 @@ __device__ __forceinline__ void swap32(uint32_t &x, uint32_t &y)
 
 template <typename TF, typename TM, int F, int WIDTH, int KBM, bool PAIRS, bool HOT>
 __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g, const Mlp &mm,
-                                               const TF *__restrict__ tab, uint32_t *s_list, Shared &S)
+                                               const TF *__restrict__ tab, uint32_t *s_list, Shared &S,
+                                               uint32_t tile)
 {
     typedef typename MmaT<TM>::vec vec_t;
     constexpr int DW = MmaT<TM>::DW;
@@ -927,7 +981,7 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
     Lane ln;
     uint32_t *hot = s_list + (A.g.H >> 1) * kBlock;   // after the voxel lists (sized for the launch)
     if constexpr (HOT) stage_hot_levels<TF, F>(g, tab, hot);
-    walk_and_sort<PAIRS>(A, g, S, s_list, ln);
+    walk_and_sort<PAIRS>(A, g, S, s_list, ln, tile);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t src = ln.src, r = ln.r;
     const bool live = ln.live;
@@ -1104,18 +1158,37 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
 }
 
 template <typename TF, typename TM, int F, int WIDTH, int KBM, bool PAIRS, bool HOT>
+__device__ __forceinline__ void query_mma_tile(const QueryArgs &A, uint32_t *s_list, Shared &S, uint32_t tile)
+{
+    if constexpr (PAIRS) {
+        const int o = tile_object(A.pr, tile);
+        if (o < 0) return;
+        const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
+        query_mma_body<TF, TM, F, WIDTH, KBM, true, HOT>(A, O.g, O.m, (const TF *)O.tables, s_list, S, tile);
+    } else {
+        query_mma_body<TF, TM, F, WIDTH, KBM, false, HOT>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list,
+                                                          S, tile);
+    }
+}
+
+template <typename TF, typename TM, int F, int WIDTH, int KBM, bool PAIRS, bool HOT>
 __global__ __launch_bounds__(kBlock) void k_query_mma(QueryArgs A)
 {
     extern __shared__ uint32_t s_list[];
     __shared__ Shared S;
-    if constexpr (PAIRS) {
-        const int o = tile_object(A.pr, A.tile0);
-        if (o < 0) return;
-        const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
-        query_mma_body<TF, TM, F, WIDTH, KBM, true, HOT>(A, O.g, O.m, (const TF *)O.tables, s_list, S);
-    } else {
-        query_mma_body<TF, TM, F, WIDTH, KBM, false, HOT>(A, A.g, A.m, reinterpret_cast<const TF *>(A.tables), s_list,
-                                                    S);
+    query_mma_tile<TF, TM, F, WIDTH, KBM, PAIRS, HOT>(A, s_list, S, block_tile(A.tile0));
+}
+
+template <typename TF, typename TM, int F, int WIDTH, int KBM, bool PAIRS, bool HOT>
+__global__ __launch_bounds__(kBlock) void k_query_mma_persist(QueryArgs A)
+{
+    extern __shared__ uint32_t s_list[];
+    __shared__ Shared S;
+    __shared__ uint32_t s_tile;
+    for (;;) {
+        const uint32_t tile = next_tile(A, s_tile);
+        if (tile == kNoTile) break;
+        query_mma_tile<TF, TM, F, WIDTH, KBM, PAIRS, HOT>(A, s_list, S, tile);
     }
 }
 
@@ -1136,7 +1209,7 @@ __device__ __forceinline__ void gather_only_body(const QueryArgs &A, float *sums
     const Geom &g = A.g;
     const TF *__restrict__ tab = reinterpret_cast<const TF *>(A.tables);
     Lane ln;
-    walk_and_sort<false>(A, g, S, s_list, ln);
+    walk_and_sort<false>(A, g, S, s_list, ln, block_tile(A.tile0));
     const int count = 2 * ln.nvox;
     const int wmax = __builtin_amdgcn_readfirstlane(wave_max(count));
     float total = 0.0f, prev = 0.0f;
@@ -1191,6 +1264,25 @@ struct BroadArgs {
     uint32_t *pair_ray, *pair_inst;
 };
 
+// ------------------------------------------------------------ merged serving
+// One member of a merged serving launch: its own buffers and where its rays and
+// pairs start in the staged arrays.
+struct MergeMember {
+    const float4 *rays;           // [2 n_rays] (a ray is two float4)
+    lsnif_hit *out;               // [n_rays]
+    const uint32_t *pair_ray, *pair_inst;   // [n_pairs] (pair requests)
+    uint32_t ray0, pair0, n_rays, n_pairs;
+};
+constexpr uint32_t kMergeMax = 32;   // members of one merged launch (the kernel argument holds them)
+struct MergeArgs {
+    MergeMember m[kMergeMax];
+    uint32_t n_members, n_rays, n_pairs;
+    float4 *rays;                 // staged rays [2 n_rays]
+    uint32_t *pair_ray, *pair_inst;   // staged pairs [n_pairs]
+    lsnif_hit *out;               // staged answers [n_rays]
+};
+static_assert(sizeof(MergeArgs) <= 4096, "merged-launch arguments must fit a kernel's argument space");
+
 // ------------------------------------------------------------------ bounce rays
 struct BounceArgs {
     const float4 *rays;       // the rays just answered (world space)
@@ -1219,7 +1311,7 @@ __global__ __launch_bounds__(kBlock) void k_walk(QueryArgs A)
 {
     __shared__ uint32_t coarse[kCoarseLdsWords];
     if constexpr (PAIRS) {
-        const int o = tile_object(A.pr, A.tile0);
+        const int o = tile_object(A.pr, block_tile(A.tile0));
         if (o < 0) return;   // the query kernel skips such a tile too
         const cObjDev &O = ((const cObjDev *)A.pr.objs)[o];
         walk_body<true, RECHECK>(A, O.g, coarse);

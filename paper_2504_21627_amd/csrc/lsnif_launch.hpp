@@ -36,8 +36,18 @@ hipError_t launch_broad_write(const BroadArgs &B, hipStream_t s);
 struct BounceArgs;
 hipError_t launch_bounce_mark(const BounceArgs &B, hipStream_t s);
 hipError_t launch_bounce_write(const BounceArgs &B, hipStream_t s);
+// Persistent query kernels: zero the 8 tile-queue counters at q (one 256-byte granule),
+// and the grid for `kernel` with `lds` dynamic bytes: as many blocks as the chip holds at
+// once (a multiple of 8, one per XCD in turn), at most the launch's tiles rounded up to 8.
+hipError_t launch_clear_queue(unsigned long long *q, hipStream_t s);
+uint32_t persistent_blocks(const void *kernel, size_t lds, uint32_t tiles);
 // In-place exclusive scan of n counters; `part` holds (n + 1023) / 1024 partial sums.
 hipError_t launch_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *part, hipStream_t s);
+// Merged serving launches: stage the members' rays and re-indexed pairs, and copy the
+// staged answers back to each member's output.
+struct MergeArgs;
+hipError_t launch_merge_pack(const MergeArgs &M, hipStream_t s);
+hipError_t launch_merge_unpack(const MergeArgs &M, hipStream_t s);
 struct PairPlan;
 hipError_t launch_pairs_prepare(const PairPlan &P, hipStream_t s);
 hipError_t launch_pairs_payload(const PairPlan &P, hipStream_t s);

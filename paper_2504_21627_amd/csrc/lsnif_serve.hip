@@ -10,6 +10,15 @@
 //    workspace return to the pool, which may admit the next request.
 // The first waiting request blocks the ones behind it (no overtaking), so a
 // large request is not starved by a stream of small ones.
+//
+// Small requests that wait together are merged: the request at the head of
+// the queue and the ones right behind it that query the same target (the same
+// object, or pairs over the same instance array), each of at most merge_rays
+// rays, up to merge_max of them and 2^21 rays in all, are admitted as one
+// launch: their rays and pairs are staged into one batch (k_serve.hip), one
+// query answers it, and each request's answers are copied back to its own
+// output.  Every member completes when the launch does.  A ray's answer does
+// not depend on its batch, so merged and direct answers are the same bits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -88,7 +97,19 @@ struct Req {
     Clock::time_point t_submit, t_admit, t_done;
     hipEvent_t done_ev = nullptr;
     int stream = 0;
+    std::vector<uint64_t> members;      // a merged launch's first request: the others it answers
 };
+
+constexpr uint32_t kMergeRays = 1u << 18;     // default largest request that may be merged
+constexpr uint64_t kMergeTotal = 1ull << 21;  // rays of one merged launch at most
+
+inline size_t al256s(size_t x) { return (x + 255) / 256 * 256; }
+
+// Staging of a merged launch: rays, pair ray and instance indices, answers.
+inline size_t merge_stage_bytes(uint64_t rays, uint64_t pairs)
+{
+    return al256s(rays * sizeof(lsnif_ray)) + 2 * al256s(pairs * 4) + al256s(rays * sizeof(lsnif_hit));
+}
 
 class Server {
 public:
@@ -100,6 +121,8 @@ public:
         if (!cfg_.hbm_budget) cfg_.hbm_budget = 4ull << 30;
         if (!cfg_.n_streams) cfg_.n_streams = 4;
         if (!cfg_.max_queue) cfg_.max_queue = 65536;
+        if (!cfg_.merge_rays) cfg_.merge_rays = kMergeRays;
+        if (!cfg_.merge_max || cfg_.merge_max > kMergeMax) cfg_.merge_max = kMergeMax;
         dry_ = cfg_.dry_run_ns_per_ray > 0;
         if (!dry_) {
             if (ctx_->device < 0) return fail(LSNIF_E_INVALID, "a host-only context serves dry runs only");
@@ -215,6 +238,7 @@ public:
             s.max_ms = v.back();
         }
         s.elapsed_s = std::chrono::duration<double>(Clock::now() - t0_).count();
+        s.launches = launches_;
     }
 
     // Finish admitted work, cancel waiting requests, join the thread, free resources.
@@ -280,6 +304,96 @@ private:
         return LSNIF_OK;
     }
 
+    // A request that may share a launch with its neighbours in the queue.
+    bool mergeable(const lsnif_request &r) const
+    {
+        return r.n_rays > 0 && r.n_rays <= cfg_.merge_rays &&
+               (r.kind == LSNIF_REQ_SINGLE || (r.kind == LSNIF_REQ_PAIRS && r.n_pairs > 0));
+    }
+    static bool same_target(const lsnif_request &a, const lsnif_request &b)
+    {
+        if (a.kind != b.kind) return false;
+        if (a.kind == LSNIF_REQ_SINGLE) return a.object_id == b.object_id;
+        return a.d_inst == b.d_inst && a.n_inst == b.n_inst;
+    }
+
+    // Workspace of a merged launch of `rays` rays and `pairs` pairs like `r` (ctx->mu held).
+    lsnif_status group_sizing(const lsnif_request &r, uint64_t rays, uint64_t pairs, size_t &need)
+    {
+        if (rays > 0xffffffffull || pairs > 0xffffffffull) return fail(LSNIF_E_INVALID, "merged launch too large");
+        if (r.kind == LSNIF_REQ_PAIRS) {
+            PairsSetup ps;
+            const lsnif_status st = pairs_setup(ctx_, ps);
+            if (st) return st;
+            need = merge_stage_bytes(rays, pairs) +
+                   pairs_ws_bytes((uint32_t)rays, (uint32_t)pairs, ps.n_objs, ps.maxH >> 1, ps.pair_bits);
+            return LSNIF_OK;
+        }
+        auto it = ctx_->objects.find(r.object_id);
+        if (it == ctx_->objects.end()) return fail(LSNIF_E_NOTFOUND, "no object %u", r.object_id);
+        need = merge_stage_bytes(rays, 0) +
+               query_ws_bytes((uint32_t)rays, it->second.geom.sort_bits, (uint32_t)it->second.geom.H >> 1);
+        return LSNIF_OK;
+    }
+
+    // Enqueue a merged launch: the leader q and its members, `rays` and `pairs` in all
+    // (mu_ and ctx->mu held).
+    lsnif_status launch_group(Req &q, uint64_t rays, uint64_t pairs)
+    {
+        hipStream_t s = streams_[q.stream];
+        char *w = static_cast<char *>(base_) + q.off;
+        MergeArgs M{};
+        M.rays = reinterpret_cast<float4 *>(w);
+        w += al256s(rays * sizeof(lsnif_ray));
+        M.pair_ray = reinterpret_cast<uint32_t *>(w);
+        w += al256s(pairs * 4);
+        M.pair_inst = reinterpret_cast<uint32_t *>(w);
+        w += al256s(pairs * 4);
+        M.out = reinterpret_cast<lsnif_hit *>(w);
+        w += al256s(rays * sizeof(lsnif_hit));
+        M.n_rays = (uint32_t)rays;
+        M.n_pairs = (uint32_t)pairs;
+        uint32_t r0 = 0, p0 = 0;
+        auto add = [&](const lsnif_request &r) {
+            MergeMember &m = M.m[M.n_members++];
+            m.rays = reinterpret_cast<const float4 *>(r.d_rays);
+            m.out = r.d_out;
+            m.pair_ray = r.d_pair_ray;
+            m.pair_inst = r.d_pair_inst;
+            m.ray0 = r0;
+            m.pair0 = p0;
+            m.n_rays = r.n_rays;
+            m.n_pairs = r.kind == LSNIF_REQ_PAIRS ? r.n_pairs : 0;
+            r0 += m.n_rays;
+            p0 += m.n_pairs;
+        };
+        add(q.r);
+        for (uint64_t t : q.members) add(reqs_[t].r);
+        for (uint32_t k = 0; k < M.n_members; ++k)
+            if (reinterpret_cast<uintptr_t>(M.m[k].rays) % 16 || reinterpret_cast<uintptr_t>(M.m[k].out) % 4)
+                return fail(LSNIF_E_INVALID, "rays must be 16-byte and hits 4-byte aligned");
+        if (launch_merge_pack(M, s) != hipSuccess) return fail(LSNIF_E_DEVICE, "merge pack launch failed");
+        lsnif_status st;
+        const lsnif_ray *srays = reinterpret_cast<const lsnif_ray *>(M.rays);
+        if (q.r.kind == LSNIF_REQ_PAIRS) {
+            PairsSetup ps;
+            st = pairs_setup(ctx_, ps);
+            if (!st)
+                st = enqueue_pairs(ctx_, ps, srays, M.n_rays, M.pair_ray, M.pair_inst, M.n_pairs, q.r.d_inst,
+                                   q.r.n_inst, M.out, s, w, 1);
+        } else {
+            auto it = ctx_->objects.find(q.r.object_id);
+            st = it == ctx_->objects.end() ? fail(LSNIF_E_NOTFOUND, "no object %u", q.r.object_id)
+                                           : enqueue_query(ctx_, it->second, srays, M.n_rays, M.out, nullptr, s, w, 1);
+        }
+        if (st) return st;
+        if (launch_merge_unpack(M, s) != hipSuccess) return fail(LSNIF_E_DEVICE, "merge unpack launch failed");
+        q.done_ev = take_event();
+        if (!q.done_ev) return fail(LSNIF_E_DEVICE, "hipEventCreate failed");
+        if (hipEventRecord(q.done_ev, s) != hipSuccess) return fail(LSNIF_E_DEVICE, "hipEventRecord failed");
+        return LSNIF_OK;
+    }
+
     hipEvent_t take_event()
     {
         if (!spare_ev_.empty()) {
@@ -330,13 +444,23 @@ private:
             spare_ev_.push_back(q.done_ev);
             q.done_ev = nullptr;
         }
-        if (state == LSNIF_REQ_DONE) {
-            ++completed_;
-            rays_done_ += q.r.n_rays;
-            lat_ms_.push_back(std::chrono::duration<double, std::milli>(q.t_done - q.t_submit).count());
-        } else {
-            ++failed_;
+        auto account = [&](Req &x) {
+            if (state == LSNIF_REQ_DONE) {
+                ++completed_;
+                rays_done_ += x.r.n_rays;
+                lat_ms_.push_back(std::chrono::duration<double, std::milli>(x.t_done - x.t_submit).count());
+            } else {
+                ++failed_;
+            }
+        };
+        account(q);
+        for (uint64_t m : q.members) {   // the requests a merged launch answered end with it
+            Req &x = reqs_[m];
+            x.state = state;
+            x.t_done = q.t_done;
+            account(x);
         }
+        q.members.clear();
         inflight_.erase(std::remove(inflight_.begin(), inflight_.end(), ticket), inflight_.end());
     }
 
@@ -367,11 +491,33 @@ private:
                 Req &q = reqs_[t];
                 std::unique_lock<std::recursive_mutex> cg(ctx_->mu, std::defer_lock);
                 if (!dry_) cg.lock();
+                // the requests right behind it that can share its launch
+                std::vector<uint64_t> grp{t};
+                uint64_t g_rays = q.r.n_rays, g_pairs = q.r.n_pairs;
+                if (!dry_ && mergeable(q.r)) {
+                    for (size_t i = 1; i < queue_.size() && grp.size() < cfg_.merge_max; ++i) {
+                        const Req &o = reqs_[queue_[i]];
+                        if (!mergeable(o.r) || !same_target(q.r, o.r) || g_rays + o.r.n_rays > kMergeTotal) break;
+                        g_rays += o.r.n_rays;
+                        g_pairs += o.r.n_pairs;
+                        grp.push_back(queue_[i]);
+                    }
+                }
                 size_t need = 0;
-                lsnif_status zst = sizing(q.r, need);
-                if (!zst && need > arena_.size())
-                    zst = fail(LSNIF_E_NOMEM, "request needs %llu bytes of workspace, the budget is %llu",
-                               (unsigned long long)need, (unsigned long long)arena_.size());
+                lsnif_status zst = LSNIF_OK;
+                if (grp.size() > 1) {
+                    zst = group_sizing(q.r, g_rays, g_pairs, need);
+                    if (zst || need > arena_.size()) {   // alone, then
+                        grp.resize(1);
+                        zst = LSNIF_OK;
+                    }
+                }
+                if (grp.size() == 1) {
+                    zst = sizing(q.r, need);
+                    if (!zst && need > arena_.size())
+                        zst = fail(LSNIF_E_NOMEM, "request needs %llu bytes of workspace, the budget is %llu",
+                                   (unsigned long long)need, (unsigned long long)arena_.size());
+                }
                 if (zst) {   // it can no longer run: it ends without holding a slot
                     queue_.pop_front();
                     q.state = zst;
@@ -382,13 +528,19 @@ private:
                 }
                 if (!arena_.alloc(need, q.off)) break;
                 q.need = need;
-                queue_.pop_front();
+                const auto now_admit = Clock::now();
+                q.members.assign(grp.begin() + 1, grp.end());
+                for (uint64_t m : grp) {
+                    Req &x = reqs_[m];
+                    x.t_admit = now_admit;
+                    x.state = LSNIF_REQ_RUNNING;
+                    ++admitted_;
+                }
+                queue_.erase(queue_.begin(), queue_.begin() + (std::ptrdiff_t)grp.size());
                 q.stream = (int)(next_stream_++ % std::max<uint32_t>(1, cfg_.n_streams));
-                q.t_admit = Clock::now();
-                q.state = LSNIF_REQ_RUNNING;
-                ++admitted_;
                 inflight_.push_back(t);
-                const lsnif_status st = launch(q);
+                ++launches_;
+                const lsnif_status st = q.members.empty() ? launch(q) : launch_group(q, g_rays, g_pairs);
                 if (st) finish(t, q, st);
                 changed = true;
             }
@@ -444,7 +596,7 @@ private:
     std::vector<double> lat_ms_;
     uint64_t next_ticket_ = 1, next_stream_ = 0;
     uint64_t submitted_ = 0, admitted_ = 0, completed_ = 0, rejected_ = 0, cancelled_ = 0, timed_out_ = 0,
-             failed_ = 0, rays_done_ = 0;
+             failed_ = 0, rays_done_ = 0, launches_ = 0;
     Clock::time_point t0_;
 };
 

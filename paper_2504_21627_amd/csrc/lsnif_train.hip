@@ -21,8 +21,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <new>
+#include <vector>
 
 #include "lsnif_internal.hpp"
 #include "lsnif_launch.hpp"
@@ -42,6 +44,10 @@ struct lsnif_trainer {
     float *m = nullptr, *v = nullptr;   // [n_tab + n_w]
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    // with the context's profiling on: per step, events around the forward layer products,
+    // the backward layer products (with their partial sums) and the table-gradient scatter
+    std::vector<std::array<hipEvent_t, 6>> prof;
+    std::vector<hipEvent_t> spare;
 };
 
 namespace {
@@ -51,6 +57,17 @@ size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 size_t weight_floats(const Object &ob)
 {
     return (size_t)ob.mlp.off[ob.mlp.n_hidden] + (size_t)ob.width * kMaxOut;
+}
+
+hipEvent_t take_event(lsnif_trainer *tr)
+{
+    if (!tr->spare.empty()) {
+        hipEvent_t e = tr->spare.back();
+        tr->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
 }
 
 lsnif_status find(lsnif_trainer *tr, Object *&ob)
@@ -141,6 +158,12 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
     lsnif_status st = grow_workspace(tr->ws, tr->ws_bytes, step_ws_bytes(ob, n));
     if (st) return st;
     const StepWs S = carve(ob, n, tr->ws);
+    std::array<hipEvent_t, 6> ev{};
+    if (tr->ctx->profiling) {
+        for (auto &e : ev)
+            if (!(e = take_event(tr))) return fail(LSNIF_E_DEVICE, "hipEventCreate failed");
+    }
+    auto mark = [&](int i) -> hipError_t { return ev[i] ? hipEventRecord(ev[i], s) : hipSuccess; };
     float *tab = static_cast<float *>(ob.d_tab);
     float *W = static_cast<float *>(const_cast<void *>(ob.d_w));
     float *gtab = tr->grad, *gW = tr->grad + tr->copies * tr->n_tab;
@@ -171,6 +194,7 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
     auto out_dim = [&](uint32_t k) { return k == nh ? od : Wd; };
     auto ld = [&](uint32_t k) { return k == nh ? (uint32_t)kMaxOut : Wd; };
     // forward: layer k maps its input to act[k + 1] (or the raw outputs z)
+    HIP_TRY(mark(0));
     for (uint32_t k = 0; k <= nh; ++k) {
         GemmArgs G{};
         G.A = layer_in(k);
@@ -188,6 +212,7 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
         G.slope = slope;
         HIP_TRY(launch_train_gemm(G, k == nh ? kEpiStore : kEpiAct, s));
     }
+    HIP_TRY(mark(1));
     TrainLossArgs Lo{};
     Lo.g = ob.geom;
     Lo.rays = A.rays;
@@ -204,6 +229,7 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
     HIP_TRY(launch_train_loss(Lo, s));
     // backward: g holds d loss / d (output of layer k)
     const float *g = S.dz;
+    HIP_TRY(mark(2));
     for (int k = (int)nh; k >= 0; --k) {
         const uint32_t ku = (uint32_t)k;
         GemmArgs Gw{};   // weight gradient: input^T x g over the batch
@@ -242,7 +268,11 @@ lsnif_status grads(lsnif_trainer *tr, const Object &ob, const lsnif_ray *d_rays,
         HIP_TRY(launch_train_gemm(Gd, k > 0 ? kEpiActGrad : kEpiStore, s));
         g = dst;
     }
+    HIP_TRY(mark(3));
+    HIP_TRY(mark(4));
     HIP_TRY(launch_train_encode(E, true, s));   // E.x = x0, now d loss / d encoding
+    HIP_TRY(mark(5));
+    if (ev[0]) tr->prof.push_back(ev);
     HIP_TRY(launch_sum_copies(gtab, tr->n_tab, tr->copies, s));
     if (d_loss) HIP_TRY(launch_train_loss_final(S.loss_part, n, d_loss, s));
     return LSNIF_OK;
@@ -341,6 +371,9 @@ void lsnif_trainer_destroy(lsnif_trainer *tr)
     (void)hipFree(tr->m);
     (void)hipFree(tr->v);
     (void)hipFree(tr->ws);
+    for (auto &v : tr->prof)
+        for (hipEvent_t e : v) (void)hipEventDestroy(e);
+    for (hipEvent_t e : tr->spare) (void)hipEventDestroy(e);
     delete tr;
 }
 
@@ -381,6 +414,30 @@ lsnif_status lsnif_train_step(lsnif_trainer *tr, const lsnif_ray *d_rays, const 
     const hipStream_t s = static_cast<hipStream_t>(stream);
     if ((st = grads(tr, *ob, d_rays, d_gt, n, d_loss, s))) return st;
     return apply(tr, *ob, s);
+}
+
+lsnif_status lsnif_train_profile_read(lsnif_trainer *tr, double *products_ms, double *scatter_ms, uint32_t *steps)
+{
+    if (!tr) return fail(LSNIF_E_INVALID, "trainer is NULL");
+    std::lock_guard<std::recursive_mutex> lk(tr->ctx->mu);
+    DeviceGuard guard(tr->ctx->device);
+    double prod = 0.0, scat = 0.0;
+    lsnif_status st = LSNIF_OK;
+    for (auto &v : tr->prof) {
+        float a = 0.0f, b = 0.0f, c = 0.0f;
+        if (!st && (hipEventSynchronize(v[5]) != hipSuccess || hipEventElapsedTime(&a, v[0], v[1]) != hipSuccess ||
+                    hipEventElapsedTime(&b, v[2], v[3]) != hipSuccess ||
+                    hipEventElapsedTime(&c, v[4], v[5]) != hipSuccess))
+            st = fail(LSNIF_E_DEVICE, "reading the training step's events failed");
+        prod += (double)a + (double)b;
+        scat += c;
+        for (hipEvent_t e : v) tr->spare.push_back(e);
+    }
+    if (steps) *steps = (uint32_t)tr->prof.size();
+    tr->prof.clear();
+    if (products_ms) *products_ms = prod;
+    if (scatter_ms) *scatter_ms = scat;
+    return st;
 }
 
 lsnif_status lsnif_trainer_read(lsnif_trainer *tr, float *tables, float *const *W, float *grad_tables,

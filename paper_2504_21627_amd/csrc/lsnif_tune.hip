@@ -1,4 +1,6 @@
 // Per-object launch parameters and the autotuner that picks them by timing.
+// With an autotune cache (lsnif_cache.hip) each winner is also written to the
+// cache file, under the key of every object it applies to.
 //
 // Every candidate runs the real query on the caller's batch (one warm-up, then
 // three timed queries between HIP events on a private stream), so the choice
@@ -13,9 +15,7 @@
 
 using namespace lsnif;
 
-namespace {
-
-constexpr int kTimedReps = 3;
+namespace lsnif {
 
 lsnif_status check_tuning(const lsnif_tuning *t)
 {
@@ -25,25 +25,36 @@ lsnif_status check_tuning(const lsnif_tuning *t)
     if (t->hot_lds_bytes < 0 || t->hot_lds_bytes > (int32_t)kHotLdsBudget)
         return fail(LSNIF_E_INVALID, "hot_lds_bytes must be 0..%u", kHotLdsBudget);
     if (t->walk_chunks < 1 || t->walk_chunks > 16) return fail(LSNIF_E_INVALID, "walk_chunks must be 1..16");
+    if (t->persistent != 0 && t->persistent != 1) return fail(LSNIF_E_INVALID, "persistent must be 0 or 1");
     return LSNIF_OK;
 }
 
-void apply(lsnif_ctx *ctx, Object &ob, const lsnif_tuning &t)
+void apply_tuning(lsnif_ctx *ctx, Object &ob, const lsnif_tuning &t)
 {
     ob.geom.sort_bits = (uint32_t)t.sort_bits;
     ob.geom.pair_bits = (uint32_t)t.pair_bits;
     ob.hot_budget = (uint32_t)t.hot_lds_bytes;
     ob.walk_chunks = (uint32_t)t.walk_chunks;
+    ob.persistent = (uint32_t)t.persistent;
     plan_hot_levels(ob.geom, ob.esz, ob.hot_budget);
     ctx->table_dirty = true;
     ++ctx->generation;
 }
 
-lsnif_tuning current(const Object &ob)
+lsnif_tuning object_tuning(const Object &ob)
 {
     return lsnif_tuning{(int32_t)ob.geom.sort_bits, (int32_t)ob.geom.pair_bits, (int32_t)ob.hot_budget,
-                        (int32_t)ob.walk_chunks};
+                        (int32_t)ob.walk_chunks, (int32_t)ob.persistent};
 }
+
+}  // namespace lsnif
+
+namespace {
+
+constexpr int kTimedReps = 3;
+
+void apply(lsnif_ctx *ctx, Object &ob, const lsnif_tuning &t) { apply_tuning(ctx, ob, t); }
+lsnif_tuning current(const Object &ob) { return object_tuning(ob); }
 
 // Milliseconds per call of `enqueue(stream)`, averaged over kTimedReps after a warm-up.
 template <typename Enqueue> lsnif_status time_ms(Enqueue &&enqueue, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float &ms)
@@ -146,17 +157,24 @@ lsnif_status lsnif_autotune(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray 
         };
         for (int sb : {0, 4, 5, 6})
             for (int32_t hot : kHotCandidates)
-                if (lsnif_status e = run(lsnif_tuning{sb, start.pair_bits, hot, start.walk_chunks})) return e;
+                if (lsnif_status e = run(lsnif_tuning{sb, start.pair_bits, hot, start.walk_chunks, start.persistent}))
+                    return e;
         const lsnif_tuning best = win;
         for (int32_t ch : kChunkCandidates)
             if (ch != best.walk_chunks)
-                if (lsnif_status e = run(lsnif_tuning{best.sort_bits, best.pair_bits, best.hot_lds_bytes, ch})) return e;
-        return LSNIF_OK;
+                if (lsnif_status e = run(lsnif_tuning{best.sort_bits, best.pair_bits, best.hot_lds_bytes, ch,
+                                                      best.persistent}))
+                    return e;
+        lsnif_tuning flip = win;
+        flip.persistent = 1 - flip.persistent;
+        return run(flip);
     });
     apply(ctx, ob, st ? start : win);
     if (st) return st;
     *best = win;
-    return LSNIF_OK;
+    if (ctx->cache_path.empty()) return LSNIF_OK;
+    ctx->cache[cache_key(ctx, ob)] = win;
+    return cache_save(ctx);
 }
 
 lsnif_status lsnif_autotune_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t n_rays,
@@ -176,11 +194,13 @@ lsnif_status lsnif_autotune_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint3
     auto apply_all = [&](const lsnif_tuning &t) {
         for (auto &kv : ctx->objects)
             apply(ctx, kv.second,
-                  lsnif_tuning{(int32_t)kv.second.geom.sort_bits, t.pair_bits, t.hot_lds_bytes, t.walk_chunks});
+                  lsnif_tuning{(int32_t)kv.second.geom.sort_bits, t.pair_bits, t.hot_lds_bytes, t.walk_chunks,
+                               t.persistent});
     };
     lsnif_tuning win{};
     float win_ms = -1.0f;
     const uint32_t start_chunks = ctx->objects.begin()->second.walk_chunks;
+    const int32_t start_persist = (int32_t)ctx->objects.begin()->second.persistent;
     lsnif_status st = with_stream([&](hipStream_t s, hipEvent_t e0, hipEvent_t e1) -> lsnif_status {
         auto run = [&](const lsnif_tuning &t) -> lsnif_status {
             apply_all(t);
@@ -206,12 +226,15 @@ lsnif_status lsnif_autotune_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint3
         };
         for (int pb : {2, 3, 4, 5})
             for (int32_t hot : kHotCandidates)
-                if (lsnif_status e = run(lsnif_tuning{0, pb, hot, (int32_t)start_chunks})) return e;
+                if (lsnif_status e = run(lsnif_tuning{0, pb, hot, (int32_t)start_chunks, start_persist})) return e;
         const lsnif_tuning best = win;
         for (int32_t ch : kChunkCandidates)
             if (ch != best.walk_chunks)
-                if (lsnif_status e = run(lsnif_tuning{0, best.pair_bits, best.hot_lds_bytes, ch})) return e;
-        return LSNIF_OK;
+                if (lsnif_status e = run(lsnif_tuning{0, best.pair_bits, best.hot_lds_bytes, ch, best.persistent}))
+                    return e;
+        lsnif_tuning flip = win;
+        flip.persistent = 1 - flip.persistent;
+        return run(flip);
     });
     if (st) {
         for (auto &p : start) apply(ctx, ctx->objects[p.first], p.second);
@@ -219,7 +242,9 @@ lsnif_status lsnif_autotune_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint3
     }
     apply_all(win);
     *best = current(ctx->objects.begin()->second);
-    return LSNIF_OK;
+    if (ctx->cache_path.empty()) return LSNIF_OK;
+    for (auto &kv : ctx->objects) ctx->cache[cache_key(ctx, kv.second)] = current(kv.second);
+    return cache_save(ctx);
 }
 
 }  // extern "C"

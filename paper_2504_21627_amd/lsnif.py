@@ -47,7 +47,7 @@ class lsnif_object_desc(C.Structure):
 
 class lsnif_tuning(C.Structure):
     _fields_ = [("sort_bits", C.c_int32), ("pair_bits", C.c_int32), ("hot_lds_bytes", C.c_int32),
-                ("walk_chunks", C.c_int32)]
+                ("walk_chunks", C.c_int32), ("persistent", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -55,7 +55,8 @@ class lsnif_tuning(C.Structure):
 
 class lsnif_serve_cfg(C.Structure):
     _fields_ = [("max_inflight", C.c_uint32), ("hbm_budget", C.c_uint64), ("n_streams", C.c_uint32),
-                ("max_queue", C.c_uint32), ("dry_run_ns_per_ray", C.c_uint64)]
+                ("max_queue", C.c_uint32), ("dry_run_ns_per_ray", C.c_uint64), ("merge_rays", C.c_uint32),
+                ("merge_max", C.c_uint32)]
 
 
 class lsnif_request(C.Structure):
@@ -69,7 +70,8 @@ class lsnif_serve_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("submitted", "admitted", "completed", "rejected", "cancelled",
                                            "timed_out", "failed", "queued", "inflight",
                                            "rays_completed", "ws_bytes_peak")] + \
-               [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "elapsed_s")]
+               [(n, C.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "elapsed_s")] + \
+               [("launches", C.c_uint64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -159,6 +161,8 @@ def load():
     lib.lsnif_train_apply.argtypes = [C.c_void_p, C.c_void_p]
     lib.lsnif_trainer_read.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.POINTER(C.c_uint64)]
+    lib.lsnif_train_profile_read.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                             C.POINTER(C.c_uint32)]
     for name in ("lsnif_create", "lsnif_desc_bytes", "lsnif_build", "lsnif_release",
                  "lsnif_object_bytes", "lsnif_query", "lsnif_query_debug", "lsnif_profile_enable",
                  "lsnif_profile_read", "lsnif_query_pairs", "lsnif_serve_start", "lsnif_serve_submit",
@@ -167,7 +171,7 @@ def load():
                  "lsnif_get_tuning", "lsnif_set_tuning", "lsnif_autotune", "lsnif_autotune_pairs",
                  "lsnif_broad_phase", "lsnif_query_scene", "lsnif_gather_ceiling", "lsnif_bounce",
                  "lsnif_trainer_create", "lsnif_train_grads", "lsnif_train_step", "lsnif_train_apply",
-                 "lsnif_trainer_read"):
+                 "lsnif_trainer_read", "lsnif_train_profile_read", "lsnif_query_noalloc"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -367,8 +371,8 @@ def lsnif_get_tuning(ctx, object_id):
     return t.as_dict()
 
 
-def lsnif_set_tuning(ctx, object_id, sort_bits, pair_bits, hot_lds_bytes, walk_chunks=1):
-    t = lsnif_tuning(sort_bits, pair_bits, hot_lds_bytes, walk_chunks)
+def lsnif_set_tuning(ctx, object_id, sort_bits, pair_bits, hot_lds_bytes, walk_chunks=1, persistent=0):
+    t = lsnif_tuning(sort_bits, pair_bits, hot_lds_bytes, walk_chunks, persistent)
     _check(load().lsnif_set_tuning(ctx, object_id, C.byref(t)))
 
 
@@ -419,8 +423,9 @@ def lsnif_graph_destroy(graph):
     load().lsnif_graph_destroy(graph)
 
 
-def lsnif_serve_start(ctx, max_inflight=0, hbm_budget=0, n_streams=0, max_queue=0, dry_run_ns_per_ray=0):
-    cfg = lsnif_serve_cfg(max_inflight, hbm_budget, n_streams, max_queue, dry_run_ns_per_ray)
+def lsnif_serve_start(ctx, max_inflight=0, hbm_budget=0, n_streams=0, max_queue=0, dry_run_ns_per_ray=0,
+                      merge_rays=0, merge_max=0):
+    cfg = lsnif_serve_cfg(max_inflight, hbm_budget, n_streams, max_queue, dry_run_ns_per_ray, merge_rays, merge_max)
     _check(load().lsnif_serve_start(ctx, C.byref(cfg)))
 
 
@@ -537,6 +542,13 @@ def lsnif_train_step(tr, rays, targets, loss, stream=None):
     assert targets.shape[0] == n
     _check(load().lsnif_train_step(tr, C.c_void_p(rays.data_ptr()), C.c_void_p(targets.data_ptr()), n,
                                    C.c_void_p(loss.data_ptr()), _stream_handle(stream)))
+
+
+def lsnif_train_profile_read(tr):
+    """(layer-product ms, scatter ms, steps) summed over the steps timed since the last read."""
+    a, b, k = C.c_double(), C.c_double(), C.c_uint32()
+    _check(load().lsnif_train_profile_read(tr, C.byref(a), C.byref(b), C.byref(k)))
+    return a.value, b.value, k.value
 
 
 def lsnif_trainer_read(tr, obj):

@@ -109,3 +109,27 @@ def test_c2_footprint(L):
     mlp = 576 * 64 + 64 * 64 * 2 + 64 * 9
     assert b16 == 128 ** 3 // 8 + tab16 + 2 * mlp
     assert b32 == 128 ** 3 // 8 + 2 * tab16 + 4 * mlp
+
+
+def test_autotune_cache_file_is_read_and_validated(L, tmp_path):
+    """A context reads its autotune cache at creation (a host-only context here): a missing
+    file is an empty cache, a well-formed file loads, and a malformed file or an entry out of
+    the tuning ranges fails creation with LSNIF_E_INVALID and a message naming the file."""
+    path = tmp_path / "tune.json"
+    ctx = L.lsnif_create(-1, autotune_cache=str(path))          # no file yet
+    L.lsnif_destroy(ctx)
+    key = "gfx950 V=128 L=16 F=2 log2_T=19 H=18 width=64 feat=fp16 mlp=fp16"
+    good = ('{"lsnif_autotune_cache": 1, "note": [1, {"x": null}], "entries": {"%s": '
+            '{"sort_bits": 6, "pair_bits": 4, "hot_lds_bytes": 20480, "walk_chunks": 2, "persistent": 1}}}' % key)
+    path.write_text(good)
+    L.lsnif_destroy(L.lsnif_create(-1, autotune_cache=str(path)))
+    bad = [good[:-3],                                              # truncated
+           good.replace('"walk_chunks": 2', '"walk_chunks": 99'),  # out of range
+           good.replace('"sort_bits": 6, ', ''),                   # missing parameter
+           good.replace('"lsnif_autotune_cache": 1', '"lsnif_autotune_cache": 2'),
+           good.replace('"pair_bits": 4', '"pair_bits": 4.5')]
+    for text in bad:
+        path.write_text(text)
+        with pytest.raises(L.LsnifError) as e:
+            L.lsnif_create(-1, autotune_cache=str(path))
+        assert e.value.status == L.LSNIF_E_INVALID and "tune.json" in str(e.value), text

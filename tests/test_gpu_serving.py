@@ -141,3 +141,57 @@ def test_serving_tuning_change_while_queued(L, scene):
         assert np.array_equal(ref.cpu().numpy().view(np.uint32), out_small.cpu().numpy().view(np.uint32))
     finally:
         L.lsnif_destroy(ctx)
+
+
+@pytest.mark.parametrize("merge_max", [32, 1])
+def test_serving_merged_launches(L, scene, merge_max):
+    """Small requests submitted together share launches (merge_max 32; 1 turns merging
+    off): single-object requests on two objects, interleaved so only neighbours with the
+    same object merge, and pair requests, one of which names a ray past its own rays and
+    an instance past the array.  Every answer equals the request's direct call bit for
+    bit, and with merging on there are fewer launches than requests."""
+    import torch
+    objs, insts, rays, pr, pi, windows = scene
+    rng = np.random.default_rng(31)
+    ctx = L.lsnif_create(0)
+    try:
+        ids = [L.lsnif_build(ctx, L.ObjectDesc(o, "fp16", "fp16")) for o in objs[:2]]
+        inst = torch.from_numpy(L.instances_array([(ids[k % 2], m) for k, m in insts[:4]])).cuda()
+        reqs, refs = [], []
+        for j in range(24):
+            n = int(rng.integers(1, 3000))
+            r = torch.from_numpy(W.sphere_to_box_rays(rng, n, radius=3.0, half_box=1.0)).cuda()
+            out = torch.full((n, 6), 7.0, device="cuda")
+            ref = torch.empty_like(out)
+            if j < 12:
+                oid = ids[(j // 3) % 2]          # runs of three requests per object
+                reqs.append((L.make_request(rays=r, out=out, object_id=oid), r, out))
+                L.lsnif_query(ctx, oid, r, ref)
+            else:
+                m = 2 * n
+                p_r = torch.from_numpy(rng.integers(0, n, m).astype(np.int32)).cuda()
+                p_i = torch.from_numpy(rng.integers(0, 4, m).astype(np.int32)).cuda()
+                if j == 15:
+                    p_r[0] = n + 5              # no such ray in this request: dropped
+                    p_i[1] = 9                  # no such instance: dropped
+                reqs.append((L.make_request(rays=r, out=out, pair_ray=p_r, pair_inst=p_i, inst=inst), r, out,
+                             p_r, p_i))
+                L.lsnif_query_pairs(ctx, r, p_r, p_i, inst, ref)
+            refs.append(ref)
+        torch.cuda.synchronize()
+        L.lsnif_serve_start(ctx, max_inflight=2, hbm_budget=256 << 20, n_streams=2, merge_max=merge_max)
+        tickets = [L.lsnif_serve_submit(ctx, q[0]) for q in reqs]
+        for t in tickets:
+            assert L.lsnif_serve_wait(ctx, t, 60_000_000_000) == L.LSNIF_OK
+        st = L.lsnif_serve_stats_get(ctx)
+        L.lsnif_serve_stop(ctx)
+        print(merge_max, {k: st[k] for k in ("completed", "launches", "p50_ms", "p99_ms")})
+        assert st["completed"] == len(reqs) and st["failed"] == 0
+        if merge_max == 1:
+            assert st["launches"] == len(reqs)
+        else:
+            assert st["launches"] < len(reqs)
+        for j, (q, ref) in enumerate(zip(reqs, refs)):
+            assert np.array_equal(bits(q[2]), bits(ref)), j
+    finally:
+        L.lsnif_destroy(ctx)

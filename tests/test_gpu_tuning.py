@@ -31,22 +31,23 @@ def test_single_object_tunings_agree(L):
         for feat, mlp in (("fp16", "fp16"), ("fp32", "fp32")):
             oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
             ref = None
-            for sb, hot, ch in ((5, 40960, 1), (0, 0, 4), (3, 20480, 2), (4, 0, 16), (6, 0, 3)):
-                L.lsnif_set_tuning(ctx, oid, sb, 4, hot, ch)
+            for sb, hot, ch, pe in ((5, 40960, 1, 0), (0, 0, 4, 0), (3, 20480, 2, 1), (4, 0, 16, 0), (6, 0, 3, 1),
+                                    (5, 0, 1, 1), (0, 40960, 1, 1)):
+                L.lsnif_set_tuning(ctx, oid, sb, 4, hot, ch, pe)
                 assert L.lsnif_get_tuning(ctx, oid) == {"sort_bits": sb, "pair_bits": 4, "hot_lds_bytes": hot,
-                                                        "walk_chunks": ch}
+                                                        "walk_chunks": ch, "persistent": pe}
                 out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
                 L.lsnif_query(ctx, oid, rays, out)
                 torch.cuda.synchronize()
                 if ref is None:
                     ref = bits(out)
                 else:
-                    assert np.array_equal(bits(out), ref), (feat, sb, hot, ch)
+                    assert np.array_equal(bits(out), ref), (feat, sb, hot, ch, pe)
             out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
             best = L.lsnif_autotune(ctx, oid, rays, out)
             print(feat, "autotuned", best, flush=True)
             assert best["sort_bits"] in (0, 4, 5, 6) and best["hot_lds_bytes"] in (0, 20480, 40960)
-            assert best["walk_chunks"] in (1, 2, 4, 8)
+            assert best["walk_chunks"] in (1, 2, 4, 8) and best["persistent"] in (0, 1)
             assert L.lsnif_get_tuning(ctx, oid) == best
             L.lsnif_query(ctx, oid, rays, out)
             torch.cuda.synchronize()
@@ -57,6 +58,8 @@ def test_single_object_tunings_agree(L):
                 L.lsnif_set_tuning(ctx, oid, 5, 4, 0, 17)
             with pytest.raises(L.LsnifError):
                 L.lsnif_set_tuning(ctx, oid, 5, 6, 0)
+            with pytest.raises(L.LsnifError):
+                L.lsnif_set_tuning(ctx, oid, 5, 4, 0, 1, 2)
             L.lsnif_release(ctx, oid)
     finally:
         L.lsnif_destroy(ctx)
@@ -76,9 +79,10 @@ def test_pair_tunings_agree(L):
         pi = torch.from_numpy(owner.astype(np.int32)).cuda()
         ref = None
         # pb None: the objects alternate between the finest and a coarse grouping
-        for pb, hot, ch in ((4, 40960, 1), (2, 0, 4), (3, 20480, 16), (5, 0, 1), (1, 0, 2), (None, 0, 1)):
+        for pb, hot, ch, pe in ((4, 40960, 1, 0), (2, 0, 4, 0), (3, 20480, 16, 1), (5, 0, 1, 1), (1, 0, 2, 0),
+                                (None, 0, 1, 0), (4, 0, 1, 1), (None, 40960, 2, 1)):
             for k, i in enumerate(ids):
-                L.lsnif_set_tuning(ctx, i, 5, pb if pb is not None else (5 if k % 2 else 2), hot, ch)
+                L.lsnif_set_tuning(ctx, i, 5, pb if pb is not None else (5 if k % 2 else 2), hot, ch, pe)
             out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
             L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out)
             torch.cuda.synchronize()
@@ -86,7 +90,7 @@ def test_pair_tunings_agree(L):
                 ref = bits(out)
                 assert (ref[:, 0] == 1).sum() > 100
             else:
-                assert np.array_equal(bits(out), ref), (pb, hot, ch)
+                assert np.array_equal(bits(out), ref), (pb, hot, ch, pe)
         out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
         best = L.lsnif_autotune_pairs(ctx, rays, pr, pi, inst, out)
         print("pairs autotuned", best, flush=True)
@@ -96,3 +100,56 @@ def test_pair_tunings_agree(L):
         assert np.array_equal(bits(out), ref)
     finally:
         L.lsnif_destroy(ctx)
+
+
+def test_autotune_cache_round_trip(L, tmp_path):
+    """lsnif_autotune writes its winner to the context's cache file; a second context with
+    the same file starts the same object with the cached parameters, without timing; an
+    entry edited in the file is what the next context applies; a context without the
+    cache keeps the defaults."""
+    import json
+    import torch
+    obj = W.configs.c1_object()
+    rays_np = W.sphere_to_box_rays(np.random.default_rng(21), 200_000, radius=2.0, half_box=1.0)
+    path = str(tmp_path / "tune.json")
+    rays = torch.from_numpy(rays_np).cuda()
+    out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
+    ctx = L.lsnif_create(0, autotune_cache=path)
+    try:
+        oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp16", "fp16"))
+        default = L.lsnif_get_tuning(ctx, oid)
+        won = L.lsnif_autotune(ctx, oid, rays, out)
+    finally:
+        L.lsnif_destroy(ctx)
+    data = json.load(open(path))
+    assert data["lsnif_autotune_cache"] == 1
+    (key, entry), = data["entries"].items()
+    assert key.startswith("gfx950 V=32 L=8 F=2 log2_T=14 H=18 width=64 feat=fp16 mlp=fp16"), key
+    assert entry == won
+    ctx = L.lsnif_create(0, autotune_cache=path)
+    try:
+        oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp16", "fp16"))
+        assert L.lsnif_get_tuning(ctx, oid) == won
+        other = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp32", "fp32"))   # another key: defaults
+        assert L.lsnif_get_tuning(ctx, other) == default
+    finally:
+        L.lsnif_destroy(ctx)
+    edited = {"sort_bits": 2, "pair_bits": 5, "hot_lds_bytes": 20480, "walk_chunks": 3, "persistent": 1}
+    data["entries"][key] = edited
+    json.dump(data, open(path, "w"))
+    ctx = L.lsnif_create(0, autotune_cache=path)
+    plain = L.lsnif_create(0)
+    try:
+        oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp16", "fp16"))
+        assert L.lsnif_get_tuning(ctx, oid) == edited
+        a = torch.empty_like(out)
+        L.lsnif_query(ctx, oid, rays, a)
+        pid = L.lsnif_build(plain, L.ObjectDesc(obj, "fp16", "fp16"))
+        assert L.lsnif_get_tuning(plain, pid) == default
+        b = torch.empty_like(out)
+        L.lsnif_query(plain, pid, rays, b)
+        torch.cuda.synchronize()
+        assert np.array_equal(bits(a), bits(b))     # parameters change speed, never results
+    finally:
+        L.lsnif_destroy(ctx)
+        L.lsnif_destroy(plain)
