@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_FP16_PEAK_TFLOPS = 2500.0
+MFMA_FP32_PEAK_TFLOPS = 157.3
 KERNEL = "k_query_mma<_Float16, _Float16, F=2, WIDTH=64, KBM=2, PAIRS=false, HOT=false>"
 
 
@@ -88,14 +89,35 @@ def time_path(L, ctx, oid, rays, out, steps, warmup):
     return time_calls(L, ctx, lambda s: L.lsnif_query(ctx, oid, rays, out, s), steps, warmup)
 
 
-def points_per_launch(L, ctx, oid, rays, out):
+def point_counts(L, ctx, oid, rays, out, H, chunk=1 << 19):
+    """Boundary points of one launch: (all points, fresh points, candidate rays).
+
+    All points are every ray's 2 x voxels (the unit of the per-point byte count).  A
+    voxel's entry point that equals the previous voxel's exit point bit for bit, on the
+    same face axis, is the same point with the same features; the query kernel reuses
+    them and gathers nothing for it.  Fresh points are the others: the points whose
+    features must be fetched.  Counted from the debug query's voxel axes and points."""
     import torch
     n = rays.shape[0]
-    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
-    L.lsnif_query_debug(ctx, oid, rays, out, {"count": cnt})
-    torch.cuda.synchronize()
-    c = cnt.cpu().numpy()
-    return int(np.maximum(c, 0).sum()), int((c > 0).sum())
+    allp = fresh = cand = 0
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        m = b - a
+        cnt = torch.empty(m, dtype=torch.int32, device="cuda")
+        axis = torch.empty((m, H // 2, 2), dtype=torch.int8, device="cuda")
+        pts = torch.empty((m, H, 3), dtype=torch.float32, device="cuda")
+        L.lsnif_query_debug(ctx, oid, rays[a:b], out[a:b], {"count": cnt, "vox_axis": axis, "points": pts})
+        torch.cuda.synchronize()
+        c = cnt.clamp(min=0)
+        pb = pts.view(torch.int32)
+        same = (pb[:, 2::2] == pb[:, 1:-1:2]).all(-1) & (axis[:, 1:, 0] == axis[:, :-1, 1])
+        j = torch.arange(1, H // 2, device="cuda")
+        dup = same & (2 * j[None, :] < c[:, None])
+        allp += int(c.sum().item())
+        fresh += int(c.sum().item()) - int(dup.sum().item())
+        cand += int((c > 0).sum().item())
+        del cnt, axis, pts
+    return allp, fresh, cand
 
 
 def cpu_baseline(obj, rays_np, sample):
@@ -110,6 +132,16 @@ def cpu_baseline(obj, rays_np, sample):
             "kind": "oracle",
             "sample": f"{len(sub)} of the {len(rays_np)} rays (uniform, seed 2024), "
                       f"float32 walk + float64 encoding/MLP, OpenMP, {dt:.2f} s wall"}
+
+
+def mlp_flops(obj, points, cand):
+    """Algorithmic MLP FLOPs of a launch: the input layer over each ray's own points only
+    (the zero-filled rest of the input vector contributes nothing), the other layers once
+    per candidate ray."""
+    w0 = obj.weights[0]
+    per_point = w0.shape[0] * obj.L * obj.F          # one point's L x F inputs into the first layer
+    rest = sum(w.shape[0] * w.shape[1] for w in obj.weights[1:])
+    return 2.0 * (per_point * points + rest * cand)
 
 
 def bytes_per_point(obj, feat_bytes=2):
@@ -146,23 +178,22 @@ def bench_c4(L, steps, warmup, tune=True):
             wall_g, lat_g, _, _, _ = time_calls(L, ctx, lambda st: L.lsnif_graph_launch(g, st), steps, warmup)
         finally:
             L.lsnif_graph_destroy(g)
-        # algorithmic gather bytes: boundary points per object from the per-ray voxel counts
+        # algorithmic gather bytes: the fresh boundary points of each object's rays
         m = int(counts.max())
-        cnt = torch.empty(m, dtype=torch.int32, device="cuda")
         tmp = torch.empty((m, 6), dtype=torch.float32, device="cuda")
-        alg, pts, cand, off = 0, 0, 0, 0
+        alg, all_b, pts, fresh, cand, flops, off = 0, 0, 0, 0, 0, 0.0, 0
         for k, o in enumerate(objs):
             c = int(counts[k])
-            L.lsnif_query_debug(ctx, ids[k], rays[off:off + c], tmp[:c], {"count": cnt[:c]})
-            cc = cnt[:c]
-            p = int(cc.clamp(min=0).sum().item())
-            alg += p * bytes_per_point(o)
+            p, f, cd = point_counts(L, ctx, ids[k], rays[off:off + c], tmp[:c], o.H)
+            alg += f * bytes_per_point(o)
+            all_b += p * bytes_per_point(o)
             pts += p
-            cand += int((cc > 0).sum().item())
+            fresh += f
+            cand += cd
+            flops += mlp_flops(o, p, cd)
             off += c
     finally:
         L.lsnif_destroy(ctx)
-    macs = sum(w.shape[0] * w.shape[1] for w in objs[0].weights)   # every c4 MLP: 576/k -> 64x3 -> 9
     val = lambda wall: n / (wall / steps) / 1e6
     return {
         "workload": "c4: 64 objects (tori, displaced spheres, box soups; 1k-500k triangles; V 32-256; "
@@ -175,10 +206,13 @@ def bench_c4(L, steps, warmup, tune=True):
                    "prepare_ms": prep_ms, "walk_ms": walk_ms, "kernel_ms": kern_ms},
         "graph": {"value": val(wall_g), "unit": "Mpairs/s", "ms_per_step": wall_g * 1e3 / steps,
                   "p50_ms": float(np.percentile(lat_g, 50)), "p99_ms": float(np.percentile(lat_g, 99))},
-        "roofline": {"bound": "hbm", "alg_bytes_per_launch": alg, "points_per_launch": pts,
+        "roofline": {"bound": "hbm", "alg_bytes_per_launch": alg, "fresh_points_per_launch": fresh,
                      "achieved": alg / (kern_ms * 1e-3) / 1e9 if kern_ms else None, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": alg / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if kern_ms else None,
-                     "candidate_pairs": cand, "mlp_macs_per_pair": macs},
+                     "points_per_launch": pts, "all_points_bytes_per_launch": all_b,
+                     "frac_all_points": all_b / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if kern_ms else None,
+                     "candidate_pairs": cand, "mlp_flops_per_launch": flops,
+                     "mfma_frac": flops / (kern_ms * 1e-3) / 1e12 / MFMA_FP16_PEAK_TFLOPS if kern_ms else None},
     }
 
 
@@ -346,6 +380,94 @@ def bench_small(L, reps=200):
     return res
 
 
+def bench_c1(L, reps=200):
+    """c1: the plain FP32 path on the icosphere object (8 levels, 2^14 entries, 288-64-64-64-9
+    MLP) and its 4,096 rays; latency-bound (16 blocks of 256 rays cannot fill 256 compute
+    units), so p50/p99 per launch over `reps` launches and Mrays/s, with the oracle on the
+    same 4,096 rays."""
+    import torch
+    import oracle
+    import workloads as W
+    c = W.configs.c1()
+    obj, rays_np = c["objects"][0], c["rays"]
+    n = len(rays_np)
+    rays = torch.from_numpy(rays_np).cuda()
+    out = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+    ctx = L.lsnif_create(0)
+    try:
+        oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp32", "fp32"))
+        wall, lat, _, _, kern_ms = time_path(L, ctx, oid, rays, out, reps, 10)
+    finally:
+        L.lsnif_destroy(ctx)
+    oracle.query(obj, rays_np[:256])
+    t0 = time.perf_counter()
+    for _ in range(5):
+        oracle.query(obj, rays_np)
+    dt = (time.perf_counter() - t0) / 5
+    return {"workload": "c1: icosphere (1,280 triangles), V=32, 8 levels x 2^14 entries x 2 fp32 features, "
+                        "MLP 288-64-64-64-9 fp32, 4,096 rays", "path": "fp32 features, fp32 vector-ALU MLP",
+            "rays": n, "launches": reps, "value": n * reps / wall / 1e6, "unit": "Mrays/s",
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "kernel_ms": kern_ms, "roofline": "not meaningful: 16 workgroups on 256 compute units (latency-bound)",
+            "cpu_baseline": {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(),
+                             "kind": "oracle", "sample": "all 4,096 rays, mean of 5 runs"}}
+
+
+def bench_c3(L, steps, warmup):
+    """c3: c2's object queried with 4,194,304 incoherent diffuse bounce rays in every MLP x
+    feature precision (FP32 / BF16 / FP16 / FP8-e4m3 MLP with FP32 accumulation, FP16 / BF16
+    features, plus FP32 / FP32).  Per combination: Mrays/s, p50/p99 per launch, the query
+    kernel's gather roofline (fresh points x bytes per point over its mean time).  The
+    oracle is timed once on a sample (its arithmetic is float64 whatever the GPU's types)."""
+    import torch
+    import oracle
+    import workloads as W
+    print("[bench] generating the c3 workload", file=sys.stderr, flush=True)
+    obj = W.configs.c2_object()
+    rays_np = W.configs.c3_rays()
+    n = len(rays_np)
+    scales = (oracle.act_amax(obj, rays_np[:65536]) / 448.0).astype(np.float32)
+    rays = torch.from_numpy(rays_np).cuda()
+    out = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+    res = {"workload": "c3: c2's object, 4,194,304 cosine-weighted diffuse bounce rays from its surface",
+           "rays": n, "launches": steps, "fp8_act_scale": [float(x) for x in scales], "combos": {}}
+    ctx = L.lsnif_create(0)
+    try:
+        combos = [("fp32", "fp32")] + [(f, m) for m in ("fp32", "bf16", "fp16", "fp8") for f in ("fp16", "bf16")]
+        pts = None
+        for feat, mlp in combos:
+            oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp, fp8_act_scale=scales if mlp == "fp8" else None))
+            tuning = L.lsnif_autotune(ctx, oid, rays, out)
+            iso = dict(tuning, walk_chunks=1)
+            print(f"[bench] c3 {feat}/{mlp} ({tuning})", file=sys.stderr, flush=True)
+            wall, lat, _, _, _ = time_path(L, ctx, oid, rays, out, steps, warmup)
+            L.lsnif_set_tuning(ctx, oid, *iso.values())
+            _, _, _, _, kern_ms = time_path(L, ctx, oid, rays, out, max(steps // 4, 5), warmup)
+            if pts is None:
+                pts = point_counts(L, ctx, oid, rays, out, obj.H)
+            L.lsnif_release(ctx, oid)
+            bpp = bytes_per_point(obj, 4 if feat == "fp32" else 2)
+            gbs = pts[1] * bpp / (kern_ms * 1e-3) / 1e9
+            res["combos"][f"mlp={mlp} feat={feat}"] = {
+                "value": n * steps / wall / 1e6, "unit": "Mrays/s", "tuning": tuning,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "kernel_ms": kern_ms,
+                "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": gbs / HBM_PEAK_GBS, "alg_bytes_per_launch": pts[1] * bpp}}
+        res["points_per_launch"], res["fresh_points_per_launch"], res["candidate_rays"] = pts
+    finally:
+        L.lsnif_destroy(ctx)
+    sub = W.configs.subsample(rays_np, 1 << 19, seed=2024)
+    oracle.query(obj, sub[:1024])
+    t0 = time.perf_counter()
+    oracle.query(obj, sub)
+    dt = time.perf_counter() - t0
+    res["cpu_baseline"] = {"value": len(sub) / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(),
+                           "kind": "oracle", "sample": f"{len(sub)} of the {n} rays (uniform, seed 2024), "
+                                                       f"float32 walk + float64 encoding/MLP, {dt:.2f} s wall"}
+    return res
+
+
 def bench_p1(L, steps, warmup, tune):
     """The paper's default object shape (width-128 leaky-ReLU MLP, albedo head, F = 3, two
     face-aligned levels) and its low-quality variant (width 64, H = 10), FP16 features and
@@ -476,10 +598,39 @@ def bench_t1(L, steps, warmup, data, cpu=True, quality_steps=400):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
             flops = train_flops_per_ray(obj) * n
+            # the same steps again with the library's phase events: layer products and scatter
+            L.lsnif_profile_enable(ctx, True)
+            for _ in range(steps):
+                L.lsnif_train_step(tr, rays, tgt, loss)
+            prod_ms, scat_ms, k = L.lsnif_train_profile_read(tr)
+            L.lsnif_profile_enable(ctx, False)
+            prod_ms, scat_ms = prod_ms / k, scat_ms / k
+            cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+            tmp = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+            L.lsnif_query_debug(ctx, oid, rays, tmp, {"count": cnt})
+            torch.cuda.synchronize()
+            points = int(cnt.clamp(min=0).sum().item())
+            corners = sum(4 if int(R) % obj.V == 0 else 8 for R in obj.R)
+            scat_bytes = points * obj.F * 4 * (obj.L + corners)   # read d loss/d x, add to every corner
             res.update({"value": n / ms / 1e3, "unit": "Mrays/s trained", "ms_per_step": ms,
                         "steps": steps, "warmup": warmup, "gflop_per_step": flops / 1e9,
                         "layer_tflops": flops / ms / 1e9, "loss_step1": loss_first,
-                        "loss_last": float(loss.item()), "adam_steps": steps + warmup + 1})
+                        "loss_last": float(loss.item()), "adam_steps": 2 * steps + warmup + 1,
+                        "roofline": {
+                            "products": {"bound": "mfma", "achieved": flops / prod_ms / 1e9,
+                                         "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                         "frac": flops / prod_ms / 1e9 / MFMA_FP32_PEAK_TFLOPS,
+                                         "ms_per_step": prod_ms, "flop_per_step": flops,
+                                         "what": "forward and backward layer products (fp32 matrix cores), "
+                                                 "with the weight-gradient partial sums"},
+                            "scatter": {"bound": "hbm", "achieved": scat_bytes / scat_ms / 1e6,
+                                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                        "frac": scat_bytes / scat_ms / 1e6 / HBM_PEAK_GBS,
+                                        "ms_per_step": scat_ms, "bytes_per_step": scat_bytes,
+                                        "points_per_step": points,
+                                        "what": "k_train_enc<true>: per boundary point, read its L x F encoding "
+                                                "gradients and add F floats to each of its corners "
+                                                "(4 on face-aligned levels, 8 elsewhere)"}}})
             if quality_steps:
                 print("[bench] t1: training on to score held-out rays", file=sys.stderr, flush=True)
                 res["trained"] = t1_quality(L, ctx, oid, tr, obj, [(rays_np, tg)] + list(more), test, quality_steps)
@@ -551,8 +702,9 @@ def bench_c2(L, args):
                                            max(args.steps // 4, 5), args.warmup)
             L.lsnif_set_tuning(ctx, oid, *tuning.values())
             del sums
-        pts, cand = points_per_launch(L, ctx, oid, rays, out)
-        paths[name] = {"wall": wall, "lat": lat, "points": pts, "cand": cand, "sort_ms": sort_ms, "ub_ms": ub_ms,
+        pts, fresh, cand = point_counts(L, ctx, oid, rays, out, obj.H)
+        paths[name] = {"wall": wall, "lat": lat, "points": pts, "fresh": fresh, "cand": cand, "sort_ms": sort_ms,
+                       "ub_ms": ub_ms,
                        "walk_ms": walk_ms, "kern_ms": kern_ms, "feat_bytes": 2 if feat == "fp16" else 4,
                        "tuning": tuning, "tuning_isolated": iso}
         L.lsnif_release(ctx, oid)
@@ -562,10 +714,10 @@ def bench_c2(L, args):
     ms_per_step = head["wall"] * 1e3 / args.steps
     mean_ms = float(head["kern_ms"])      # query kernel alone, HIP events on its stream
     bpp = bytes_per_point(obj, head["feat_bytes"])
-    alg_bytes = head["points"] * bpp
+    alg_bytes = head["fresh"] * bpp                # fresh points only: the bytes that must move
+    all_bytes = head["points"] * bpp               # every boundary point, repeats included
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
-    macs = sum(w.shape[0] * w.shape[1] for w in obj.weights)
-    flops = 2.0 * macs * head["cand"]
+    flops = mlp_flops(obj, head["points"], head["cand"])
     rec = {
         "metric": "Mrays/s LSNIF queries (FP16 MFMA vs FP32 plain) + p50/p99 batch latency",
         "value": n / (ms_per_step * 1e-3) / 1e6,
@@ -586,12 +738,15 @@ def bench_c2(L, args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("c2-fp16"),
                      "kernel": KERNEL if "fp16" in paths else "k_query_f32",
-                     "alg_bytes_per_launch": alg_bytes, "points_per_launch": head["points"],
+                     "alg_bytes_per_launch": alg_bytes, "fresh_points_per_launch": head["fresh"],
                      "bytes_per_point": bpp, "mean_kernel_ms": mean_ms,
+                     "points_per_launch": head["points"], "all_points_bytes_per_launch": all_bytes,
+                     "frac_all_points": all_bytes / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "mean_sort_ms": float(head["sort_ms"]), "mean_walk_ms": float(head["walk_ms"]),
                      "tuning": head["tuning_isolated"],
                      "ub_gather_ms": head["ub_ms"],
                      "ub_gather_gbs": alg_bytes / (head["ub_ms"] * 1e-3) / 1e9 if head["ub_ms"] else None,
+                     "mlp_flops_per_launch": flops,
                      "frac_of_ub_gather": head["ub_ms"] / mean_ms if head["ub_ms"] else None,
                      "mfma_tflops": flops / (mean_ms * 1e-3) / 1e12,
                      "mfma_frac": flops / (mean_ms * 1e-3) / 1e12 / MFMA_FP16_PEAK_TFLOPS},
@@ -615,10 +770,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--only", choices=["fp16", "fp32"], default=None,
                     help="time one path only (for profiling)")
-    ap.add_argument("--legs", default="c2,c4,c5,p1,small,t1",
+    ap.add_argument("--legs", default="c2,c4,c5,p1,small,t1,c1,c3",
                     help="comma list: c2 (headline), c4 (batched objects), c5 (serving), "
                          "p1 (the paper's default object shape), small (latency of small batches), "
-                         "t1 (training steps)")
+                         "t1 (training steps), c1 (latency of the small FP32 config), "
+                         "c3 (precision sweep on incoherent rays)")
     ap.add_argument("--c5-requests", type=int, default=2000)
     ap.add_argument("--t1-quality-steps", type=int, default=400,
                     help="t1: further training steps before scoring held-out rays (0: skip the scoring)")
@@ -660,6 +816,10 @@ def main():
         rec["serving_c5"] = bench_c5(L, args.c5_requests)
     if "small" in legs:
         rec["small_batches"] = bench_small(L)
+    if "c1" in legs:
+        rec["latency_c1"] = bench_c1(L)
+    if "c3" in legs:
+        rec["precision_c3"] = bench_c3(L, max(args.steps // 10, 10), min(args.warmup, 3))
     if "p1" in legs:
         rec["paper_default_p1"] = bench_p1(L, args.steps, min(args.warmup, 3), not args.no_tune)
     if "t1" in legs:

@@ -129,13 +129,19 @@ def compare_hits(g, o, tatb, enc_or, out_or, obj, u, t_rel, n_ang, vis_min):
 def to_object_f32(m, rays):
     """World rays mapped into an instance's object space the way the oracle's pair query
     maps them: x = A x + b and d = A d, each row as ((m0 x + m1 y) + m2 z) + m3 in float32
-    (numpy float32 products and sums round once each, with no fused multiply-add)."""
+    (numpy float32 products and sums round once each, with no fused multiply-add).  An
+    invalid world ray (a NaN anywhere, an infinite origin or direction, a zero direction,
+    tmin > tmax) stays invalid: its mapped origin is NaN."""
     m = np.asarray(m, np.float32).reshape(3, 4)
     r = np.ascontiguousarray(rays, np.float32)
     out = r.copy()
-    for a in range(3):
-        out[:, a] = ((m[a, 0] * r[:, 0] + m[a, 1] * r[:, 1]) + m[a, 2] * r[:, 2]) + m[a, 3]
-        out[:, 3 + a] = (m[a, 0] * r[:, 3] + m[a, 1] * r[:, 4]) + m[a, 2] * r[:, 5]
+    with np.errstate(invalid="ignore", over="ignore"):
+        for a in range(3):
+            out[:, a] = ((m[a, 0] * r[:, 0] + m[a, 1] * r[:, 1]) + m[a, 2] * r[:, 2]) + m[a, 3]
+            out[:, 3 + a] = (m[a, 0] * r[:, 3] + m[a, 1] * r[:, 4]) + m[a, 2] * r[:, 5]
+    valid = (~np.any(np.isnan(r), 1) & np.all(np.isfinite(r[:, :6]), 1) & np.any(r[:, 3:6] != 0, 1)
+             & ~(r[:, 6] > r[:, 7]))
+    out[~valid, 0] = np.nan
     return out
 
 
@@ -147,9 +153,8 @@ def pair_reference(oracle, objs, insts, rays, pr, pi, u):
     Each pair is answered by ``oracle.query`` on the ray mapped into its instance's
     object space (``to_object_f32``); the nearest hit over those answers is checked
     against ``oracle.query_pairs`` bit for bit, so the pairs are exactly the ones the
-    oracle's own pair query saw.  Rays must be valid (finite, d != 0)."""
+    oracle's own pair query saw."""
     rays = np.ascontiguousarray(rays, np.float32)
-    assert np.all(np.isfinite(rays[:, :6])) and np.all(np.any(rays[:, 3:6] != 0, 1))
     pr = np.asarray(pr, np.int64)
     pi = np.asarray(pi, np.int64)
     n, npairs = len(rays), len(pr)
