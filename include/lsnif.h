@@ -325,7 +325,8 @@ lsnif_status lsnif_bounce(lsnif_ctx *ctx, const lsnif_ray *d_rays, const lsnif_h
  *  sort_bits      single-object queries of at least 8192 rays are first sorted
  *                 by direction octant and by the cell of the voxel grid where
  *                 the ray's segment starts, 2^sort_bits cells per axis
- *                 (0 = no sort, 1..6); rays that meet the grid close together
+ *                 (0 = no sort, 1..6), or at 7 by the cell alone (128 cells
+ *                 per axis, no octant); rays that meet the grid close together
  *                 then share 256-ray tiles (the work decomposition of Sec. 4:
  *                 dispatch sorted rays rather than scattered ones).
  *  pair_bits      the same grouping, 2^pair_bits cells per axis (1..5), for the
@@ -349,7 +350,7 @@ lsnif_status lsnif_bounce(lsnif_ctx *ctx, const lsnif_ray *d_rays, const lsnif_h
  *                 pairs) at a time; 0 launches one workgroup per tile, dealt to
  *                 the XCDs in runs of 8.  Width-128 and FP32-MLP objects always
  *                 take one workgroup per tile.
- * lsnif_autotune times each candidate (sort_bits 0, 4, 5, 6 x hot_lds_bytes 0,
+ * lsnif_autotune times each candidate (sort_bits 0, 4, 5, 6, 7 x hot_lds_bytes 0,
  * 20480, 40960, then walk_chunks 1, 2, 4, 8, then persistent 0 and 1, each for
  * the best so far) on the
  * caller's batch, a warm-up and three timed queries each on a private stream,

@@ -1,7 +1,8 @@
 // Coherence order of a ray batch: a one-pass counting sort of the rays by a
 // coarse key -- direction octant, then the Morton code of the cell (2^b per
 // axis, b <= 6 chosen per object) of the voxel grid where the ray's segment
-// [ta, tb] starts.  Rays that meet the
+// [ta, tb] starts; at b = 7 (128^3 cells) the cell alone, without the
+// octant.  Rays that meet the
 // grid close together and head the same way then share waves, so their
 // walks and their hash-grid gathers touch the same cache lines.  Order within
 // a key is whatever the atomics give; every ray's result is independent of
@@ -15,10 +16,10 @@
 
 namespace lsnif {
 
-// Bits 0..5 of x spread to bits 0, 3, 6, ..., 15 (one axis of a 3-D Morton code).
-__device__ __forceinline__ uint32_t spread6(uint32_t x)
+// Bits 0..6 of x spread to bits 0, 3, 6, ..., 18 (one axis of a 3-D Morton code).
+__device__ __forceinline__ uint32_t spread7(uint32_t x)
 {
-    x &= 63u;
+    x &= 127u;
     x = (x | (x << 8)) & 0x0000f00fu;
     x = (x | (x << 4)) & 0x000c30c3u;
     x = (x | (x << 2)) & 0x00249249u;
@@ -40,8 +41,10 @@ __device__ __forceinline__ uint32_t coherence_key(const Geom &g, float4 r0, floa
         x = x < 0.0f ? 0.0f : (x > cells - 1.0f ? cells - 1.0f : x);
         cell[a] = (uint32_t)x;
     }
+    const uint32_t morton = spread7(cell[0]) | (spread7(cell[1]) << 1) | (spread7(cell[2]) << 2);
+    if (g.sort_bits >= 7u) return morton;
     const uint32_t oct = (w.d[0] < 0.0f ? 1u : 0u) | (w.d[1] < 0.0f ? 2u : 0u) | (w.d[2] < 0.0f ? 4u : 0u);
-    return (oct << (3u * g.sort_bits)) | spread6(cell[0]) | (spread6(cell[1]) << 1) | (spread6(cell[2]) << 2);
+    return (oct << (3u * g.sort_bits)) | morton;
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill(uint32_t *p, uint32_t n, uint32_t v)

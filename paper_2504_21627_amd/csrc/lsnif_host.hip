@@ -286,7 +286,8 @@ void lsnif_destroy(lsnif_ctx *ctx)
     (void)hipFree(ctx->bws);
     (void)hipFree(ctx->sws);
     for (auto &v : ctx->pending)
-        for (hipEvent_t e : v) (void)hipEventDestroy(e);
+        for (hipEvent_t e : v)
+            if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
     for (hipEvent_t e : ctx->order_events) (void)hipEventDestroy(e);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
@@ -774,15 +775,15 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
     A.queue = reinterpret_cast<unsigned long long *>(wl + list_ws_bytes(n, ob.geom.H >> 1));
     A.persistent = ob.persistent && !dbg && !gather_sums ? 1u : 0u;
     const int kbm = ob.mlp.kb_point;
-    const uint32_t k = dbg ? 1u : (chunks > 0 ? (uint32_t)chunks : ob.walk_chunks);
-    lsnif_status st = walk_then_query(ctx, A, false, ob.geom.recheck != 0, grid, k, s, ev[2],
-                                      [&](const QueryArgs &a, uint32_t g) -> hipError_t {
+    auto query = [&](const QueryArgs &a, uint32_t g) -> hipError_t {
         if (gather_sums) return launch_gather_only(a, ob.feat_dtype, ob.F, gather_sums, g, s);
         if (ob.mlp_dtype == LSNIF_FP32) return launch_f32(a, ob.feat_dtype, ob.F, false, g, s);
         if (ob.mlp_dtype == LSNIF_FP16) return launch_mma_f16(a, ob.feat_dtype, ob.F, kbm, false, g, s);
         if (ob.mlp_dtype == LSNIF_BF16) return launch_mma_bf16(a, ob.feat_dtype, ob.F, kbm, false, g, s);
         return launch_mma_fp8(a, ob.feat_dtype, ob.F, kbm, false, g, s);
-    });
+    };
+    const uint32_t k = dbg ? 1u : (chunks > 0 ? (uint32_t)chunks : ob.walk_chunks);
+    lsnif_status st = walk_then_query(ctx, A, false, ob.geom.recheck != 0, grid, k, s, ev[2], query);
     if (st) return st;
     if (ev[3]) {
         HIP_TRY(hipEventRecord(ev[3], s));

@@ -3,11 +3,15 @@
 #include <hip/hip_runtime.h>
 
 namespace lsnif {
-constexpr uint32_t kSortBins = (1u << 21) + 1;   // capacity: 8 octants x 64^3 cells, plus one bin for rays that miss
+constexpr uint32_t kSortBins = (1u << 21) + 1;   // capacity: 8 octants x 64^3 (or 128^3) cells, plus one bin for misses
 constexpr uint32_t kSortScanBlocks = (kSortBins + 1023) / 1024;   // partial sums of the two-pass scan
-// Bins of a coherence sort with 2^bits cells per axis: 8 octants x cells^3, then one for
-// misses; and the partial sums its two-pass scan keeps (one per 1024 bins).
-__host__ __device__ inline uint32_t sort_bins(uint32_t bits) { return (8u << (3u * bits)) + 1u; }
+// Bins of a coherence sort with 2^bits cells per axis: 8 octants x cells^3 (bits <= 6) or
+// cells^3 alone (bits 7), then one for misses; and the partial sums its two-pass scan keeps
+// (one per 1024 bins).
+__host__ __device__ inline uint32_t sort_bins(uint32_t bits)
+{
+    return bits >= 7u ? (1u << 21) + 1u : (8u << (3u * bits)) + 1u;
+}
 __host__ __device__ inline uint32_t sort_scan_blocks(uint32_t bits) { return (sort_bins(bits) + 1023u) / 1024u; }
 struct Geom;
 struct QueryArgs;

@@ -20,7 +20,7 @@ namespace lsnif {
 lsnif_status check_tuning(const lsnif_tuning *t)
 {
     if (!t) return fail(LSNIF_E_INVALID, "tuning is NULL");
-    if (t->sort_bits < 0 || t->sort_bits > 6) return fail(LSNIF_E_INVALID, "sort_bits must be 0..6");
+    if (t->sort_bits < 0 || t->sort_bits > 7) return fail(LSNIF_E_INVALID, "sort_bits must be 0..7");
     if (t->pair_bits < 1 || t->pair_bits > 5) return fail(LSNIF_E_INVALID, "pair_bits must be 1..5");
     if (t->hot_lds_bytes < 0 || t->hot_lds_bytes > (int32_t)kHotLdsBudget)
         return fail(LSNIF_E_INVALID, "hot_lds_bytes must be 0..%u", kHotLdsBudget);
@@ -136,7 +136,7 @@ lsnif_status lsnif_autotune(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray 
     if (n == 0) return fail(LSNIF_E_INVALID, "nothing to time (n = 0)");
     Object &ob = ctx->objects[object_id];
     DeviceGuard guard(ctx->device);
-    if ((st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n, 6, ob.geom.H >> 1)))) return st;   // the finest candidate
+    if ((st = grow_workspace(ctx->ws, ctx->ws_bytes, query_ws_bytes(n, 7, ob.geom.H >> 1)))) return st;   // the most bins
     HIP_TRY(hipDeviceSynchronize());
     const lsnif_tuning start = current(ob);
     lsnif_tuning win = start;
@@ -155,7 +155,7 @@ lsnif_status lsnif_autotune(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray 
             }
             return LSNIF_OK;
         };
-        for (int sb : {0, 4, 5, 6})
+        for (int sb : {0, 4, 5, 6, 7})
             for (int32_t hot : kHotCandidates)
                 if (lsnif_status e = run(lsnif_tuning{sb, start.pair_bits, hot, start.walk_chunks, start.persistent}))
                     return e;

@@ -32,7 +32,7 @@ def test_single_object_tunings_agree(L):
             oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp))
             ref = None
             for sb, hot, ch, pe in ((5, 40960, 1, 0), (0, 0, 4, 0), (3, 20480, 2, 1), (4, 0, 16, 0), (6, 0, 3, 1),
-                                    (5, 0, 1, 1), (0, 40960, 1, 1)):
+                                    (5, 0, 1, 1), (0, 40960, 1, 1), (7, 0, 1, 0), (7, 20480, 2, 1)):
                 L.lsnif_set_tuning(ctx, oid, sb, 4, hot, ch, pe)
                 assert L.lsnif_get_tuning(ctx, oid) == {"sort_bits": sb, "pair_bits": 4, "hot_lds_bytes": hot,
                                                         "walk_chunks": ch, "persistent": pe}
@@ -46,14 +46,14 @@ def test_single_object_tunings_agree(L):
             out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
             best = L.lsnif_autotune(ctx, oid, rays, out)
             print(feat, "autotuned", best, flush=True)
-            assert best["sort_bits"] in (0, 4, 5, 6) and best["hot_lds_bytes"] in (0, 20480, 40960)
+            assert best["sort_bits"] in (0, 4, 5, 6, 7) and best["hot_lds_bytes"] in (0, 20480, 40960)
             assert best["walk_chunks"] in (1, 2, 4, 8) and best["persistent"] in (0, 1)
             assert L.lsnif_get_tuning(ctx, oid) == best
             L.lsnif_query(ctx, oid, rays, out)
             torch.cuda.synchronize()
             assert np.array_equal(bits(out), ref)
             with pytest.raises(L.LsnifError):
-                L.lsnif_set_tuning(ctx, oid, 7, 4, 0)
+                L.lsnif_set_tuning(ctx, oid, 8, 4, 0)
             with pytest.raises(L.LsnifError):
                 L.lsnif_set_tuning(ctx, oid, 5, 4, 0, 17)
             with pytest.raises(L.LsnifError):
