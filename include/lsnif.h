@@ -432,7 +432,8 @@ typedef struct {
     uint32_t max_queue;     /* waiting requests beyond which submit returns LSNIF_E_BUSY; 0 = 65536 */
     uint64_t dry_run_ns_per_ray; /* > 0: touch no device; a request "completes" this many ns per
                                     ray after admission and writes nothing (tests of the
-                                    admission logic on hosts without a GPU; no merging) */
+                                    admission logic on hosts without a GPU; merged launches
+                                    take the time of all their rays) */
     uint32_t merge_rays;    /* largest request (rays) that may be merged; 0 = 262144 */
     uint32_t merge_max;     /* requests per merged launch, 1..32 (1: no merging); 0 = 32 */
 } lsnif_serve_cfg;

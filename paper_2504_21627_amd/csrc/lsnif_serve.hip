@@ -98,6 +98,7 @@ struct Req {
     hipEvent_t done_ev = nullptr;
     int stream = 0;
     std::vector<uint64_t> members;      // a merged launch's first request: the others it answers
+    uint64_t launch_rays = 0;           // rays of the whole launch (dry runs: its duration)
 };
 
 constexpr uint32_t kMergeRays = 1u << 18;     // default largest request that may be merged
@@ -321,6 +322,12 @@ private:
     lsnif_status group_sizing(const lsnif_request &r, uint64_t rays, uint64_t pairs, size_t &need)
     {
         if (rays > 0xffffffffull || pairs > 0xffffffffull) return fail(LSNIF_E_INVALID, "merged launch too large");
+        if (dry_) {   // the default resolution and grouping, the longest lists
+            need = merge_stage_bytes(rays, pairs) +
+                   (r.kind == LSNIF_REQ_PAIRS ? pairs_ws_bytes((uint32_t)rays, (uint32_t)pairs, r.n_inst + 1, kMaxList, 4)
+                                              : query_ws_bytes((uint32_t)rays, 5, kMaxList));
+            return LSNIF_OK;
+        }
         if (r.kind == LSNIF_REQ_PAIRS) {
             PairsSetup ps;
             const lsnif_status st = pairs_setup(ctx_, ps);
@@ -340,6 +347,7 @@ private:
     // (mu_ and ctx->mu held).
     lsnif_status launch_group(Req &q, uint64_t rays, uint64_t pairs)
     {
+        if (dry_) return LSNIF_OK;
         hipStream_t s = streams_[q.stream];
         char *w = static_cast<char *>(base_) + q.off;
         MergeArgs M{};
@@ -494,7 +502,7 @@ private:
                 // the requests right behind it that can share its launch
                 std::vector<uint64_t> grp{t};
                 uint64_t g_rays = q.r.n_rays, g_pairs = q.r.n_pairs;
-                if (!dry_ && mergeable(q.r)) {
+                if (mergeable(q.r)) {
                     for (size_t i = 1; i < queue_.size() && grp.size() < cfg_.merge_max; ++i) {
                         const Req &o = reqs_[queue_[i]];
                         if (!mergeable(o.r) || !same_target(q.r, o.r) || g_rays + o.r.n_rays > kMergeTotal) break;
@@ -509,6 +517,8 @@ private:
                     zst = group_sizing(q.r, g_rays, g_pairs, need);
                     if (zst || need > arena_.size()) {   // alone, then
                         grp.resize(1);
+                        g_rays = q.r.n_rays;
+                        g_pairs = q.r.n_pairs;
                         zst = LSNIF_OK;
                     }
                 }
@@ -530,6 +540,7 @@ private:
                 q.need = need;
                 const auto now_admit = Clock::now();
                 q.members.assign(grp.begin() + 1, grp.end());
+                q.launch_rays = g_rays;
                 for (uint64_t m : grp) {
                     Req &x = reqs_[m];
                     x.t_admit = now_admit;
@@ -551,7 +562,7 @@ private:
                 bool done = false;
                 int32_t state = LSNIF_REQ_DONE;
                 if (dry_ || q.r.n_rays == 0 || !q.done_ev) {
-                    const auto due = q.t_admit + std::chrono::nanoseconds(cfg_.dry_run_ns_per_ray * q.r.n_rays);
+                    const auto due = q.t_admit + std::chrono::nanoseconds(cfg_.dry_run_ns_per_ray * q.launch_rays);
                     done = dry_ ? now >= due : true;
                 } else {
                     const hipError_t e = hipEventQuery(q.done_ev);
