@@ -46,13 +46,24 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload):
-    """HBM traffic per launch from the committed rocprofv3 counter summary, if it is current."""
+def tuning_key(t):
+    """A tuning as the comma list that `--tuning` takes."""
+    return ",".join(str(int(t[k])) for k in ("sort_bits", "pair_bits", "hot_lds_bytes", "walk_chunks", "persistent"))
+
+
+def kernel_label(tuning):
+    """The timed query kernel: the persistent grid is a kernel of its own."""
+    return KERNEL.replace("k_query_mma<", "k_query_mma_persist<") if tuning.get("persistent") else KERNEL
+
+
+def stored_traffic(workload, tuning):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it was taken with
+    the same tuning at the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f).get(workload)
+        rec = json.load(f).get(workload, {}).get(tuning_key(tuning))
     if not rec or rec.get("src_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
@@ -736,8 +747,9 @@ def bench_c2(L, args):
                    "rays": n, "path": "fp16 features, fp16 MFMA MLP, fp32 accumulation"
                    if "fp16" in paths else "fp32 features, fp32 vector-ALU MLP"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("c2-fp16"),
-                     "kernel": KERNEL if "fp16" in paths else "k_query_f32",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": stored_traffic("c2-fp16", head["tuning_isolated"]) if "fp16" in paths else None,
+                     "kernel": kernel_label(head["tuning_isolated"]) if "fp16" in paths else "k_query_f32",
                      "alg_bytes_per_launch": alg_bytes, "fresh_points_per_launch": head["fresh"],
                      "bytes_per_point": bpp, "mean_kernel_ms": mean_ms,
                      "points_per_launch": head["points"], "all_points_bytes_per_launch": all_bytes,
