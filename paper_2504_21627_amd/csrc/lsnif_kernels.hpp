@@ -1020,6 +1020,12 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
 #pragma unroll
         for (int kb = 0; kb < KBM; ++kb) {
             if (kb >= KB) break;
+            // this K block's layer-1 weight fragments, requested ahead of the gathers so that
+            // their latency overlaps the gathers' rather than following them
+            uint32_t wd[MB][DW];
+            const uint32_t *Wk = Wv + mm.woff[0] + ((size_t)((h * KB + kb) * MB) * 64 + lane) * DW;
+#pragma unroll
+            for (int m = 0; m < MB; ++m) load_frag<DW>(Wk + (size_t)m * 64 * DW, wd[m]);
             uint32_t lo[DW], hi[DW];
             if (fresh) {
                 float e[16];
@@ -1062,12 +1068,9 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
 #pragma unroll
             for (int q = 0; q < DW; ++q) swap32(lo[q], hi[q]);
             const vec_t b0 = as_vec<vec_t, DW>(lo), b1 = as_vec<vec_t, DW>(hi);
-            const uint32_t *Wk = Wv + mm.woff[0] + ((size_t)((h * KB + kb) * MB) * 64 + lane) * DW;
 #pragma unroll
             for (int m = 0; m < MB; ++m) {
-                uint32_t wd[DW];
-                load_frag<DW>(Wk + (size_t)m * 64 * DW, wd);
-                const vec_t a = as_vec<vec_t, DW>(wd);
+                const vec_t a = as_vec<vec_t, DW>(wd[m]);
                 acc[m][0] = MmaT<TM>::mma(a, b0, acc[m][0]);
                 acc[m][1] = MmaT<TM>::mma(a, b1, acc[m][1]);
             }
