@@ -1090,6 +1090,21 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
             // activations -> B operands: 16-block s of output block m holds the
             // outputs lying in accumulator registers 8s .. 8s+7
             const float dqi = mm.dq[k - 1], qsi = mm.qs[k];
+            const int MO = head ? 1 : MB;
+            const uint32_t *Wk = Wv + mm.woff[k] + (size_t)lane * DW;
+            // width 64: the whole layer's weight fragments requested before the activations are
+            // converted, so that their latency overlaps that work
+            constexpr int PF = MB == 2 ? MB : 1;   // output blocks prefetched
+            uint32_t wpf[PF][MB][2][DW];
+#pragma unroll
+            for (int mo = 0; mo < PF; ++mo)
+                if (mo < MO)
+#pragma unroll
+                    for (int m = 0; m < MB; ++m)
+#pragma unroll
+                        for (int s = 0; s < 2; ++s)
+                            load_frag<DW>(Wk + (size_t)((mo * MB + m) * 2 + s) * 64 * DW, wpf[mo][m][s]);
+            asm volatile("" ::: "memory");   // keep the requests ahead of the conversion
             uint32_t xb[MB][2][2][DW];
 #pragma unroll
             for (int m = 0; m < MB; ++m)
@@ -1105,8 +1120,6 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
                         }
                         pack8<TM>(v, qsi, xb[m][nb][s]);
                     }
-            const int MO = head ? 1 : MB;
-            const uint32_t *Wk = Wv + mm.woff[k] + (size_t)lane * DW;
 #pragma unroll
             for (int m = 0; m < MB; ++m)
 #pragma unroll
@@ -1121,7 +1134,12 @@ __device__ __forceinline__ void query_mma_body(const QueryArgs &A, const Geom &g
 #pragma unroll
                         for (int s = 0; s < 2; ++s) {
                             uint32_t wd[DW];
-                            load_frag<DW>(Wk + (size_t)((mo * MB + m) * 2 + s) * 64 * DW, wd);
+                            if (mo < PF) {
+#pragma unroll
+                                for (int q = 0; q < DW; ++q) wd[q] = wpf[mo < PF ? mo : 0][m][s][q];
+                            } else {
+                                load_frag<DW>(Wk + (size_t)((mo * MB + m) * 2 + s) * 64 * DW, wd);
+                            }
                             const vec_t a = as_vec<vec_t, DW>(wd);
                             acc[mo][0] = MmaT<TM>::mma(a, as_vec<vec_t, DW>(xb[m][0][s]), acc[mo][0]);
                             acc[mo][1] = MmaT<TM>::mma(a, as_vec<vec_t, DW>(xb[m][1][s]), acc[mo][1]);
