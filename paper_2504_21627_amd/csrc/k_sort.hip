@@ -130,14 +130,28 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t *hist, uint32_t 
     }
 }
 
+// kScatterPer rays per thread (rays blockIdx kBlock kScatterPer + j kBlock +
+// threadIdx), their counter atomics all in flight before the first position is
+// used (c2: 109 -> 78 us).
+constexpr uint32_t kScatterPer = 4;
+
 __global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint32_t *keys, uint32_t n, uint32_t *cursor,
                                                          uint32_t *order)
 {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    const bool live = i < n;
-    const uint32_t k = live ? keys[i] : 0u;
-    const uint32_t pos = wave_aggregated_add(cursor, k, live);
-    if (live) order[pos] = i;
+    const uint32_t i0 = blockIdx.x * kBlock * kScatterPer + threadIdx.x;
+    AggAdd a[kScatterPer];
+#pragma unroll
+    for (uint32_t j = 0; j < kScatterPer; ++j) {
+        const uint32_t i = i0 + j * kBlock;
+        const bool live = i < n;
+        a[j] = wave_aggregated_issue(cursor, live ? keys[i] : 0u, live);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kScatterPer; ++j) {
+        const uint32_t i = i0 + j * kBlock;
+        const uint32_t pos = wave_aggregated_rank(a[j]);
+        if (i < n) order[pos] = i;
+    }
 }
 
 hipError_t launch_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *part, hipStream_t s)
@@ -191,12 +205,13 @@ hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, 
     // the workspace holds this resolution's bins, then one partial sum per 1024 bins
     const uint32_t nbins = sort_bins(g.sort_bits), nblocks = sort_scan_blocks(g.sort_bits);
     const dim3 gb((nbins + kBlock - 1) / kBlock), gr((n + kBlock - 1) / kBlock);
+    const dim3 gj((n + kBlock * kScatterPer - 1) / (kBlock * kScatterPer));
     uint32_t *part = hist + nbins;
     hipLaunchKernelGGL(k_fill, gb, dim3(kBlock), 0, s, hist, nbins, 0u);
     hipLaunchKernelGGL(k_sort_keys, gr, dim3(kBlock), 0, s, g, rays, n, keys, hist);
     hipLaunchKernelGGL(k_scan_partial, dim3(nblocks), dim3(kBlock), 0, s, hist, nbins, part);
     hipLaunchKernelGGL(k_scan_final, dim3(nblocks), dim3(kBlock), 0, s, hist, nbins, part);
-    hipLaunchKernelGGL(k_sort_scatter, gr, dim3(kBlock), 0, s, keys, n, hist, order);
+    hipLaunchKernelGGL(k_sort_scatter, gj, dim3(kBlock), 0, s, keys, n, hist, order);
     return hipGetLastError();
 }
 

@@ -375,7 +375,16 @@ __device__ __forceinline__ float act_f(float x, int act, float slope)
 // of scattered keys gains nothing from grouping: after kAggMax groups the
 // remaining lanes add for themselves.
 constexpr int kAggMax = 6;
-__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t *ctr, uint32_t key, bool active)
+// The two halves of wave_aggregated_add, so that a thread can have the atomics
+// of several keys in flight before it waits for any: issue groups the lanes and
+// sends each group's atomic, rank turns the returned counter into the lane's
+// value.
+struct AggAdd {
+    uint32_t old, leader;
+    uint64_t mine;
+};
+
+__device__ __forceinline__ AggAdd wave_aggregated_issue(uint32_t *ctr, uint32_t key, bool active)
 {
     const uint32_t lane = threadIdx.x & 63u;
     uint64_t todo = __ballot(active);
@@ -399,9 +408,20 @@ __device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t *ctr, uint32_t 
     }
     uint32_t old = 0;
     if (n) old = atomicAdd(&ctr[key], n);
-    const uint32_t base = __shfl(old, leader, 64);
+    return AggAdd{old, leader, mine};
+}
+
+__device__ __forceinline__ uint32_t wave_aggregated_rank(const AggAdd &a)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t base = __shfl(a.old, a.leader, 64);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    return base + (uint32_t)__builtin_popcountll(mine & below);
+    return base + (uint32_t)__builtin_popcountll(a.mine & below);
+}
+
+__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t *ctr, uint32_t key, bool active)
+{
+    return wave_aggregated_rank(wave_aggregated_issue(ctr, key, active));
 }
 
 // Largest non-negative value of the wave folded into *dst (float bits of
