@@ -416,10 +416,12 @@ def bench_c1(L, reps=200):
         oracle.query(obj, rays_np)
     dt = (time.perf_counter() - t0) / 5
     return {"workload": "c1: icosphere (1,280 triangles), V=32, 8 levels x 2^14 entries x 2 fp32 features, "
-                        "MLP 288-64-64-64-9 fp32, 4,096 rays", "path": "fp32 features, fp32 vector-ALU MLP",
+                        "MLP 288-64-64-64-9 fp32, 4,096 rays",
+            "path": "fp32 features, fp32 vector-ALU MLP, one wave per ray (k_query_lat)",
             "rays": n, "launches": reps, "value": n * reps / wall / 1e6, "unit": "Mrays/s",
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "kernel_ms": kern_ms, "roofline": "not meaningful: 16 workgroups on 256 compute units (latency-bound)",
+            "kernel_ms": kern_ms,
+            "roofline": "not meaningful: 4,096 waves of a few microseconds each (latency-bound)",
             "cpu_baseline": {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(),
                              "kind": "oracle", "sample": "all 4,096 rays, mean of 5 runs"}}
 

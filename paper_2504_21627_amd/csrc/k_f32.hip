@@ -86,6 +86,14 @@ static void go(const QueryArgs &A, bool pairs, uint32_t grid, hipStream_t s)
     else hipLaunchKernelGGL((k_query_f32<TF, F, 64, false, false>), dim3(grid), dim3(kBlock), lds, s, A);
 }
 
+hipError_t launch_lat(const QueryArgs &A, int F, uint32_t grid, hipStream_t s)
+{
+    const dim3 blocks(grid * (kBlock / kLatWaves));   // one wave per slot of the grid's tiles
+    if (F == 2) hipLaunchKernelGGL(k_query_lat<2>, blocks, dim3(64 * kLatWaves), 0, s, A);
+    else hipLaunchKernelGGL(k_query_lat<3>, blocks, dim3(64 * kLatWaves), 0, s, A);
+    return hipGetLastError();
+}
+
 hipError_t launch_f32(const QueryArgs &A, int feat_dtype, int F, bool pairs, uint32_t grid, hipStream_t s)
 {
     if (feat_dtype == LSNIF_FP32) {

@@ -68,6 +68,8 @@ void destroy_server(lsnif_ctx *ctx);   // stops a running serving loop
 
 // Batches below this size are processed in the order given (no coherence sort).
 constexpr uint32_t kSortMin = 8192;
+// FP32 batches of at most this many rays run one wave per ray (k_query_lat).
+constexpr uint32_t kSmallBatchRays = 8192;
 
 // Workspace bytes of one query of n rays, and of one pair query; cap is the
 // longest voxel list (H / 2, the largest over the objects for pairs).

@@ -1233,6 +1233,153 @@ __global__ __launch_bounds__(kBlock) void k_query_mma_persist(QueryArgs A)
     }
 }
 
+// ------------------------------------------------------------- small batches
+//
+// One wave per ray, for batches too small to fill the chip with one ray per
+// lane (FP32 features and MLP, width 64, at most 16 levels): a point's
+// 8-corner gathers of up to 8 levels are spread over the lanes (lane 8q + c:
+// corner c of level 8 round + q), a butterfly sum over each level's 8 lanes
+// interpolates, and lane j then owns output j of every layer, taking the
+// layer's inputs one at a time from the lanes that hold them.  Cells, slots,
+// corner weights and every layer's summation order are those of the
+// ray-per-lane FP32 kernel; the 8-corner sums are pairwise instead of in
+// corner order.  The walk kernel's lists are read from the workspace; the
+// debug outputs (counts, intervals, encodings, raw outputs, calibration
+// maxima) are those of the ray-per-lane kernel.
+constexpr int kLatWaves = 4;     // rays (one wave each) per workgroup
+constexpr int kLatMaxLF = 48;    // features per point: at most 16 levels of at most 3
+
+template <int F>
+__device__ __forceinline__ void lat_level(const Geom &g, const float *__restrict__ tab, int l, uint32_t c,
+                                          const float p[3], float v[F])
+{
+    const bool in = l < g.L;
+    const int lc = in ? l : g.L - 1;
+    uint32_t i[3];
+    float wt[3];
+    level_cell_mm(g, lc, p, i, wt);
+    const uint32_t x = i[0] + (c & 1u), y = (i[1] + ((c >> 1) & 1u)) * g.my[lc], z = (i[2] + (c >> 2)) * g.mz[lc];
+    const uint32_t s = ((x + y + z) & g.dmask[lc]) | ((x ^ y ^ z) & g.hmask[lc]);
+    const float wx = (c & 1u) ? wt[0] : 1.0f - wt[0];
+    const float wy = ((c >> 1) & 1u) ? wt[1] : 1.0f - wt[1];
+    const float wz = (c >> 2) ? wt[2] : 1.0f - wt[2];
+    const float wc = wx * (wy * wz);
+    const float *e = tab + (((size_t)lc << g.log2_T) + s) * F;
+#pragma unroll
+    for (int f = 0; f < F; ++f) v[f] = in ? wc * e[f] : 0.0f;
+#pragma unroll
+    for (int m = 1; m < 8; m <<= 1)
+#pragma unroll
+        for (int f = 0; f < F; ++f) v[f] += __shfl_xor(v[f], m, 64);
+}
+
+template <int F>
+__global__ __launch_bounds__(64 * kLatWaves) void k_query_lat(QueryArgs A)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t slot = A.tile0 * kBlock + blockIdx.x * kLatWaves + (threadIdx.x >> 6);
+    if (slot >= A.n) return;   // the whole wave
+    const Geom &g = A.g;
+    const Mlp &mm = A.m;
+    const float *__restrict__ tab = reinterpret_cast<const float *>(A.tables);
+    const float *__restrict__ W = reinterpret_cast<const float *>(mm.W);
+    uint32_t r, pair;
+    bool live;
+    VRay w;
+    slot_ray<false>(A, g, slot, r, pair, live, w);
+    const int count = __builtin_amdgcn_readfirstlane(live ? 2 * (int)A.nvox[slot] : 0);
+    const int LF = g.L * F;
+    const uint32_t q = lane >> 3, c = lane & 7u;
+    float acc = 0.0f;
+    float fv[2][F];   // this lane's level features (rounds 0 and 1), kept for a repeated point
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+        for (int f = 0; f < F; ++f) fv[k][f] = 0.0f;
+    uint32_t pp[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu};
+    int pface = -1;
+    float amax = 0.0f;   // largest |input| of the current layer (calibration)
+    for (int h = 0; h < count; ++h) {
+        // this point's layer-1 weights (output `lane` of each input), requested ahead of the gathers
+        float wk[kLatMaxLF];
+        const float *W1 = W + mm.off[0] + (size_t)h * LF * 64 + lane;
+#pragma unroll
+        for (int k = 0; k < kLatMaxLF; ++k) wk[k] = W1[(size_t)(k < LF ? k : 0) * 64];   // k >= LF: unused
+        float p[3];
+        const int face = boundary_point(w, A.lists[(size_t)(h >> 1) * A.n + slot], h & 1, p);
+        const bool dup = (h & 1) == 0 && face == pface && __float_as_uint(p[0]) == pp[0] &&
+                         __float_as_uint(p[1]) == pp[1] && __float_as_uint(p[2]) == pp[2];
+        if (!dup) {
+            lat_level<F>(g, tab, (int)q, c, p, fv[0]);
+            if (g.L > 8) lat_level<F>(g, tab, 8 + (int)q, c, p, fv[1]);
+        }
+        if (A.dbg.act_amax) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int f = 0; f < F; ++f) amax = fmax2(amax, __builtin_fabsf(fv[k][f]));
+        }
+        if (A.dbg.enc && live && c == 0u) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int l = 8 * k + (int)q;
+                if (l < g.L)
+#pragma unroll
+                    for (int f = 0; f < F; ++f) A.dbg.enc[((size_t)r * g.H + h) * LF + l * F + f] = fv[k][f];
+            }
+        }
+        // input k = l F + f lives in lane 8 (l mod 8), round l / 8
+#pragma unroll
+        for (int k = 0; k < kLatMaxLF; ++k) {
+            if (k < LF) {
+                const int l = k / F, f = k % F;
+                const float x = __builtin_bit_cast(
+                    float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, fv[l >> 3][f]), 8 * (l & 7)));
+                acc = __builtin_fmaf(wk[k], x, acc);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) pp[b] = __float_as_uint(p[b]);
+        pface = face;
+    }
+    // hidden layers, then the head (lanes below kMaxOut)
+    float o = 0.0f;
+    if (A.dbg.act_amax) fold_max(A.dbg.act_amax + 0, amax);
+    if (count > 0) {
+        for (int k = 1; k <= mm.n_hidden; ++k) {
+            const bool head = k == mm.n_hidden;
+            const float x = act_f(acc, mm.act, mm.slope);
+            if (A.dbg.act_amax) fold_max(A.dbg.act_amax + k, __builtin_fabsf(x));
+            const float *Wk = W + mm.off[k] + (head ? (lane < (uint32_t)kMaxOut ? lane : 0u) : lane);
+            const int stride = head ? kMaxOut : 64;
+            float nxt = 0.0f;
+#pragma unroll 16
+            for (int i = 0; i < 64; ++i) {
+                const float xi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), i));
+                nxt = __builtin_fmaf(Wk[(size_t)i * stride], xi, nxt);
+            }
+            if (head) o = lane < (uint32_t)kMaxOut ? nxt : 0.0f;
+            else acc = nxt;
+        }
+    }
+    float oo[kMaxOut];
+#pragma unroll
+    for (int k = 0; k < kMaxOut; ++k)
+        oo[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, o), k));
+    if (!live || lane != 0u) return;
+    if (A.dbg.count) A.dbg.count[r] = w.valid ? count : -1;
+    if (A.dbg.tatb) {
+        A.dbg.tatb[2 * r] = w.ta;
+        A.dbg.tatb[2 * r + 1] = w.tb;
+    }
+    if (A.dbg.out) {
+#pragma unroll
+        for (int k = 0; k < kMaxOut; ++k)
+            if (k < mm.out_dim) A.dbg.out[(size_t)r * mm.out_dim + k] = count > 0 ? oo[k] : 0.0f;
+    }
+    decode_store<false>(A, mm, r, pair, w, count, oo);
+}
+
 // ------------------------------------------------------------- gather ceiling
 //
 // The query kernel's gathers alone, for measurement: the same prologue (voxel

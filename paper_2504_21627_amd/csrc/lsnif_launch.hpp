@@ -18,6 +18,9 @@ struct QueryArgs;
 struct DebugArgs;
 // Query kernels: `grid` blocks of 256 lanes; `pairs` selects the instanced-pair variant.
 hipError_t launch_f32(const QueryArgs &A, int feat_dtype, int F, bool pairs, uint32_t grid, hipStream_t s);
+// One wave per ray (FP32 features and MLP, width 64, F <= 3, at most 16 levels), for `grid`
+// tiles' slots starting at tile A.tile0.
+hipError_t launch_lat(const QueryArgs &A, int F, uint32_t grid, hipStream_t s);
 hipError_t launch_mma_f16(const QueryArgs &A, int feat_dtype, int F, int kbm, bool pairs, uint32_t grid,
                           hipStream_t s);
 hipError_t launch_mma_bf16(const QueryArgs &A, int feat_dtype, int F, int kbm, bool pairs, uint32_t grid,

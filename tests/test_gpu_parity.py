@@ -94,6 +94,50 @@ def test_c1_fp32_parity(L, ctx, c1, feat, mlp):
         L.lsnif_release(ctx, oid)
 
 
+def test_small_batch_wave_per_ray(L, ctx, c1):
+    """FP32 batches of at most 8,192 rays run one wave per ray.  c1's 4,096 rays: voxel
+    counts exact, raw outputs and hits against the oracle at the c1 bar; then the same
+    rays three times over (12,288 rays, the ray-per-lane kernel) give the same hits up to
+    the order of the 8-corner sums, and 1 and 7 rays (a partly filled workgroup)."""
+    import torch
+    obj, rays = c1["objects"][0], c1["rays"]
+    n = len(rays)
+    _say(f"small batch: {n} rays, one wave each")
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp32", "fp32"))
+    try:
+        t = torch.from_numpy(np.ascontiguousarray(rays, np.float32)).cuda()
+        out = torch.empty((n, 6), dtype=torch.float32, device="cuda")
+        bufs = {"count": torch.empty(n, dtype=torch.int32, device="cuda"),
+                "tatb": torch.empty((n, 2), dtype=torch.float32, device="cuda"),
+                "out": torch.empty((n, obj.out_dim), dtype=torch.float32, device="cuda")}
+        L.lsnif_query_debug(ctx, oid, t, out, bufs)
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in bufs.items()}
+        h = out.cpu().numpy()
+        g.update(hit=h[:, 0].view(np.uint32).copy(), t=h[:, 1].copy(), normal=h[:, 2:5].copy(),
+                 material=h[:, 5].view(np.int32).copy())
+        o = oracle.query(obj, rays, debug=True)
+        assert np.array_equal(g["count"], o["count"])
+        cand = o["count"] > 0
+        zerr = np.abs(g["out"][cand] - o["out"][cand]).max() / np.abs(o["out"][cand]).max()
+        assert zerr < 1e-5, zerr
+        st = compare_hits(g, o, o["tatb"], o["enc"], o["out"], obj, U["fp32"], 1e-5, 1e-4, 0.9999)
+        _say(str(st))
+        assert st["ok"], st
+        big = gpu_query(L, ctx, oid, np.concatenate([rays] * 3))
+        for k in range(3):
+            s = slice(k * n, (k + 1) * n)
+            both = (big["hit"][s] == 1) & (g["hit"] == 1)
+            assert (big["hit"][s] == g["hit"]).mean() >= 0.9999
+            assert np.all(np.abs(big["t"][s][both] - g["t"][both]) <= 1e-5 * np.abs(g["t"][both]) + 1e-6)
+        for m in (1, 7):
+            few = gpu_query(L, ctx, oid, rays[:m])
+            assert np.array_equal(few["hit"], g["hit"][:m])
+            assert np.array_equal(few["t"].view(np.uint32), g["t"][:m].view(np.uint32))
+    finally:
+        L.lsnif_release(ctx, oid)
+
+
 @pytest.mark.parametrize("feat,mlp", [("fp16", "fp16"), ("bf16", "bf16"), ("fp32", "fp16")])
 def test_c1_mma_parity(L, ctx, c1, feat, mlp):
     obj, rays = c1["objects"][0], c1["rays"]
