@@ -1241,11 +1241,10 @@ __global__ __launch_bounds__(kBlock) void k_query_mma_persist(QueryArgs A)
 // corner c of level 8 round + q), a butterfly sum over each level's 8 lanes
 // interpolates, and lane j then owns output j of every layer, taking the
 // layer's inputs one at a time from the lanes that hold them.  Cells, slots,
-// corner weights and every layer's summation order are those of the
-// ray-per-lane FP32 kernel; the 8-corner sums are pairwise instead of in
-// corner order.  The walk kernel's lists are read from the workspace; the
-// debug outputs (counts, intervals, encodings, raw outputs, calibration
-// maxima) are those of the ray-per-lane kernel.
+// corner weights and every sum's order are those of the ray-per-lane FP32
+// kernel, so a ray's answer and debug outputs are the same bits whichever of
+// the two kernels its batch runs on.  The walk kernel's lists are read from
+// the workspace.
 constexpr int kLatWaves = 4;     // rays (one wave each) per workgroup
 constexpr int kLatMaxLF = 48;    // features per point: at most 16 levels of at most 3
 
@@ -1265,12 +1264,24 @@ __device__ __forceinline__ void lat_level(const Geom &g, const float *__restrict
     const float wz = (c >> 2) ? wt[2] : 1.0f - wt[2];
     const float wc = wx * (wy * wz);
     const float *e = tab + (((size_t)lc << g.log2_T) + s) * F;
+    float ec[F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) v[f] = in ? wc * e[f] : 0.0f;
+    for (int f = 0; f < F; ++f) ec[f] = e[f];
+    // every lane of the level sums the 8 corners in corner order, as one fused
+    // multiply-add chain: the ray-per-lane kernel's sum, bit for bit
+    const int g0 = (int)((threadIdx.x & 63u) & ~7u);
 #pragma unroll
-    for (int m = 1; m < 8; m <<= 1)
+    for (int f = 0; f < F; ++f) v[f] = 0.0f;
 #pragma unroll
-        for (int f = 0; f < F; ++f) v[f] += __shfl_xor(v[f], m, 64);
+    for (int k = 0; k < 8; ++k) {
+        const float wk = __shfl(wc, g0 + k, 64);
+#pragma unroll
+        for (int f = 0; f < F; ++f) v[f] = __builtin_fmaf(wk, __shfl(ec[f], g0 + k, 64), v[f]);
+    }
+    if (!in) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) v[f] = 0.0f;
+    }
 }
 
 template <int F>
