@@ -8,4 +8,9 @@ hipError_t launch_mma_f16(const QueryArgs &A, int feat_dtype, int F, int kbm, bo
     return launch_mma<_Float16>(A, feat_dtype, F, kbm, pairs, grid, s);
 }
 
+hipError_t launch_mma_small_f16(const QueryArgs &A, int feat_dtype, int kbm, uint32_t grid, hipStream_t s)
+{
+    return launch_mma_small<_Float16>(A, feat_dtype, kbm, grid, s);
+}
+
 }  // namespace lsnif

@@ -8,4 +8,9 @@ hipError_t launch_mma_fp8(const QueryArgs &A, int feat_dtype, int F, int kbm, bo
     return launch_mma<fp8e4m3>(A, feat_dtype, F, kbm, pairs, grid, s);
 }
 
+hipError_t launch_mma_small_fp8(const QueryArgs &A, int feat_dtype, int kbm, uint32_t grid, hipStream_t s)
+{
+    return launch_mma_small<fp8e4m3>(A, feat_dtype, kbm, grid, s);
+}
+
 }  // namespace lsnif

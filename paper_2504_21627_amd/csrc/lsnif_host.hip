@@ -775,13 +775,20 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
     A.queue = reinterpret_cast<unsigned long long *>(wl + list_ws_bytes(n, ob.geom.H >> 1));
     A.persistent = ob.persistent && !dbg && !gather_sums ? 1u : 0u;
     const int kbm = ob.mlp.kb_point;
-    // Batches too small to fill the chip with one ray per lane run one wave per ray (FP32
-    // objects of width 64 with at most 16 levels), whichever debug buffers are asked for.
-    const bool small = !gather_sums && n <= kSmallBatchRays && ob.mlp_dtype == LSNIF_FP32 &&
-                       ob.feat_dtype == LSNIF_FP32 && ob.width == 64 && ob.F <= 3 && ob.geom.L <= 16;
+    // Batches too small to fill the chip with one ray per lane run one wave per ray (width 64,
+    // at most 16 levels; FP32 MLP with FP32 features and F <= 3, or a matrix-core MLP with
+    // F = 2), whichever debug buffers are asked for: the answers are the same bits.
+    const bool small = !gather_sums && n <= kSmallBatchRays && ob.width == 64 && ob.geom.L <= 16 &&
+                       (ob.mlp_dtype == LSNIF_FP32 ? ob.feat_dtype == LSNIF_FP32 && ob.F <= 3
+                                                   : ob.F == 2 && ob.mlp.kb_point <= 2);
     auto query = [&](const QueryArgs &a, uint32_t g) -> hipError_t {
         if (gather_sums) return launch_gather_only(a, ob.feat_dtype, ob.F, gather_sums, g, s);
-        if (small) return launch_lat(a, ob.F, g, s);
+        if (small) {
+            if (ob.mlp_dtype == LSNIF_FP32) return launch_lat(a, ob.F, g, s);
+            if (ob.mlp_dtype == LSNIF_FP16) return launch_mma_small_f16(a, ob.feat_dtype, kbm, g, s);
+            if (ob.mlp_dtype == LSNIF_BF16) return launch_mma_small_bf16(a, ob.feat_dtype, kbm, g, s);
+            return launch_mma_small_fp8(a, ob.feat_dtype, kbm, g, s);
+        }
         if (ob.mlp_dtype == LSNIF_FP32) return launch_f32(a, ob.feat_dtype, ob.F, false, g, s);
         if (ob.mlp_dtype == LSNIF_FP16) return launch_mma_f16(a, ob.feat_dtype, ob.F, kbm, false, g, s);
         if (ob.mlp_dtype == LSNIF_BF16) return launch_mma_bf16(a, ob.feat_dtype, ob.F, kbm, false, g, s);

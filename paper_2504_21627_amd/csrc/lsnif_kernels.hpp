@@ -1248,8 +1248,8 @@ __global__ __launch_bounds__(kBlock) void k_query_mma_persist(QueryArgs A)
 constexpr int kLatWaves = 4;     // rays (one wave each) per workgroup
 constexpr int kLatMaxLF = 48;    // features per point: at most 16 levels of at most 3
 
-template <int F>
-__device__ __forceinline__ void lat_level(const Geom &g, const float *__restrict__ tab, int l, uint32_t c,
+template <typename TF, int F>
+__device__ __forceinline__ void lat_level(const Geom &g, const TF *__restrict__ tab, int l, uint32_t c,
                                           const float p[3], float v[F])
 {
     const bool in = l < g.L;
@@ -1263,25 +1263,45 @@ __device__ __forceinline__ void lat_level(const Geom &g, const float *__restrict
     const float wy = ((c >> 1) & 1u) ? wt[1] : 1.0f - wt[1];
     const float wz = (c >> 2) ? wt[2] : 1.0f - wt[2];
     const float wc = wx * (wy * wz);
-    const float *e = tab + (((size_t)lc << g.log2_T) + s) * F;
-    float ec[F];
-#pragma unroll
-    for (int f = 0; f < F; ++f) ec[f] = e[f];
+    Entry<TF, F> en;
+    en.load(reinterpret_cast<const char *>(tab + ((size_t)lc << g.log2_T) * F), s * (uint32_t)(F * sizeof(TF)));
     // every lane of the level sums the 8 corners in corner order, as one fused
-    // multiply-add chain: the ray-per-lane kernel's sum, bit for bit
+    // multiply-add chain on the raw entries: the ray-per-lane kernel's sum, bit for bit
     const int g0 = (int)((threadIdx.x & 63u) & ~7u);
 #pragma unroll
     for (int f = 0; f < F; ++f) v[f] = 0.0f;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const float wk = __shfl(wc, g0 + k, 64);
+        Entry<TF, F> ek;
 #pragma unroll
-        for (int f = 0; f < F; ++f) v[f] = __builtin_fmaf(wk, __shfl(ec[f], g0 + k, 64), v[f]);
+        for (int d = 0; d < Entry<TF, F>::W; ++d) ek.d[d] = (uint32_t)__shfl((int)en.d[d], g0 + k, 64);
+#pragma unroll
+        for (int f = 0; f < F; ++f) v[f] = __builtin_fmaf(wk, ek.get(f), v[f]);
     }
     if (!in) {
 #pragma unroll
         for (int f = 0; f < F; ++f) v[f] = 0.0f;
     }
+}
+
+// The lane's corner of lat_level without the sum: corner c of level l (levels at
+// or beyond L read level L - 1), its weight and its entry.
+template <typename TF, int F>
+__device__ __forceinline__ void lat_corner(const Geom &g, const TF *__restrict__ tab, int l, uint32_t c,
+                                           const float p[3], float &wc, Entry<TF, F> &en)
+{
+    const int lc = l < g.L ? l : g.L - 1;
+    uint32_t i[3];
+    float wt[3];
+    level_cell_mm(g, lc, p, i, wt);
+    const uint32_t x = i[0] + (c & 1u), y = (i[1] + ((c >> 1) & 1u)) * g.my[lc], z = (i[2] + (c >> 2)) * g.mz[lc];
+    const uint32_t s = ((x + y + z) & g.dmask[lc]) | ((x ^ y ^ z) & g.hmask[lc]);
+    const float wx = (c & 1u) ? wt[0] : 1.0f - wt[0];
+    const float wy = ((c >> 1) & 1u) ? wt[1] : 1.0f - wt[1];
+    const float wz = (c >> 2) ? wt[2] : 1.0f - wt[2];
+    wc = wx * (wy * wz);
+    en.load(reinterpret_cast<const char *>(tab + ((size_t)lc << g.log2_T) * F), s * (uint32_t)(F * sizeof(TF)));
 }
 
 template <int F>
@@ -1321,8 +1341,8 @@ __global__ __launch_bounds__(64 * kLatWaves) void k_query_lat(QueryArgs A)
         const bool dup = (h & 1) == 0 && face == pface && __float_as_uint(p[0]) == pp[0] &&
                          __float_as_uint(p[1]) == pp[1] && __float_as_uint(p[2]) == pp[2];
         if (!dup) {
-            lat_level<F>(g, tab, (int)q, c, p, fv[0]);
-            if (g.L > 8) lat_level<F>(g, tab, 8 + (int)q, c, p, fv[1]);
+            lat_level<float, F>(g, tab, (int)q, c, p, fv[0]);
+            if (g.L > 8) lat_level<float, F>(g, tab, 8 + (int)q, c, p, fv[1]);
         }
         if (A.dbg.act_amax) {
 #pragma unroll
@@ -1389,6 +1409,196 @@ __global__ __launch_bounds__(64 * kLatWaves) void k_query_lat(QueryArgs A)
             if (k < mm.out_dim) A.dbg.out[(size_t)r * mm.out_dim + k] = count > 0 ? oo[k] : 0.0f;
     }
     decode_store<false>(A, mm, r, pair, w, count, oo);
+}
+
+// The matrix-core form of the one-wave-per-ray kernel (two features per level,
+// width 64, at most two K blocks per point).  The wave's lanes interpolate the
+// ray's point as above; every lane then packs the point's 16 K slots of a K
+// block, and the B operand puts slots 0..7 in lanes 0..31 and 8..15 in lanes
+// 32..63, so each of the 32 columns is this ray.  A column of a matrix-core
+// product does not depend on the other columns, so every column, and the
+// answer, has the bits the ray gets in k_query_mma.
+template <typename TF, typename TM, int KBM>
+__global__ __launch_bounds__(64 * kLatWaves) void k_query_mma_lat(QueryArgs A)
+{
+    typedef typename MmaT<TM>::vec vec_t;
+    constexpr int F = 2, MB = 2, DW = MmaT<TM>::DW;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t slot = A.tile0 * kBlock + blockIdx.x * kLatWaves + (threadIdx.x >> 6);
+    if (slot >= A.n) return;   // the whole wave
+    const Geom &g = A.g;
+    const Mlp &mm = A.m;
+    const TF *__restrict__ tab = reinterpret_cast<const TF *>(A.tables);
+    const uint32_t *__restrict__ Wv = reinterpret_cast<const uint32_t *>(mm.W);
+    uint32_t r, pair;
+    bool live;
+    VRay w;
+    slot_ray<false>(A, g, slot, r, pair, live, w);
+    const int count = __builtin_amdgcn_readfirstlane(live ? 2 * (int)A.nvox[slot] : 0);
+    const int KB = mm.kb_point;
+    const uint32_t q = lane >> 3, c = lane & 7u;
+    f16_t acc[MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[m][e] = 0.0f;
+    uint32_t prev[KBM][DW];
+#pragma unroll
+    for (int kb = 0; kb < KBM; ++kb)
+#pragma unroll
+        for (int d = 0; d < DW; ++d) prev[kb][d] = 0u;
+    uint32_t pp[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu};
+    int pface = -1;
+    for (int h = 0; h < count; ++h) {
+        // the point's layer-1 weight fragments, requested ahead of the gathers
+        uint32_t wd[KBM][MB][DW];
+#pragma unroll
+        for (int kb = 0; kb < KBM; ++kb)
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+                load_frag<DW>(Wv + mm.woff[0] + ((size_t)(((h * KB + (kb < KB ? kb : 0)) * MB + m) * 64) + lane) * DW,
+                              wd[kb][m]);
+        float p[3];
+        const int face = boundary_point(w, A.lists[(size_t)(h >> 1) * A.n + slot], h & 1, p);
+        const bool dup = (h & 1) == 0 && face == pface && __float_as_uint(p[0]) == pp[0] &&
+                         __float_as_uint(p[1]) == pp[1] && __float_as_uint(p[2]) == pp[2];
+        // this lane's corner: c of level 8 kb + q, for the two K blocks
+        float wcr[2] = {0.0f, 0.0f};
+        Entry<TF, F> enr[2];
+        if (!dup) {
+            lat_corner<TF, F>(g, tab, (int)q, c, p, wcr[0], enr[0]);
+            if (g.L > 8) lat_corner<TF, F>(g, tab, 8 + (int)q, c, p, wcr[1], enr[1]);
+        }
+        const uint32_t hf = lane >> 5;
+#pragma unroll
+        for (int kb = 0; kb < KBM; ++kb) {
+            if (kb >= KB) break;
+            uint32_t bk[DW];
+            if (!dup) {
+                // Lanes 0..31 form the B operand's K slots 0..7 (levels 8 kb .. 8 kb + 3), lanes
+                // 32..63 slots 8..15 (levels 8 kb + 4 .. 8 kb + 7): each lane sums those 4 levels'
+                // corners itself, in corner order, and packs them, as a lane of k_query_mma
+                // does for its own ray (the same expressions, so the same roundings).
+                float e[8];
+#pragma unroll
+                for (int li = 0; li < 4; ++li) {
+                    const int j = 4 * (int)hf + li;   // level 8 kb + j: corners in lanes 8 j ..
+                    float v[F];
+#pragma unroll
+                    for (int f = 0; f < F; ++f) v[f] = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const float wk = __shfl(wcr[kb], 8 * j + k, 64);
+                        Entry<TF, F> ek;
+#pragma unroll
+                        for (int d = 0; d < Entry<TF, F>::W; ++d)
+                            ek.d[d] = (uint32_t)__shfl((int)enr[kb].d[d], 8 * j + k, 64);
+#pragma unroll
+                        for (int f = 0; f < F; ++f) v[f] = __builtin_fmaf(wk, ek.get(f), v[f]);
+                    }
+                    if (8 * kb + j >= g.L) {
+#pragma unroll
+                        for (int f = 0; f < F; ++f) v[f] = 0.0f;
+                    }
+#pragma unroll
+                    for (int f = 0; f < F; ++f) e[2 * li + f] = v[f];
+                }
+                pack8<TM>(e, mm.qs[0], bk);
+            } else {
+#pragma unroll
+                for (int d = 0; d < DW; ++d) bk[d] = prev[kb][d];
+            }
+            if (A.dbg.enc && live && (lane & 31u) == 0u) {
+                // lane 0 writes K slots 0..7, lane 32 slots 8..15 (a repeated point: the previous one's)
+                const int LF = g.L * F;
+                for (int k = 0; k < 8; ++k) {
+                    const int l = kb * 8 + 4 * (int)hf + k / 2, f = k % 2;
+                    if (l < g.L) {
+                        const float v = unpack8<TM>(bk, k);
+                        A.dbg.enc[(size_t)r * g.H * LF + h * LF + l * F + f] = MmaT<TM>::scaled ? v / mm.qs[0] : v;
+                    }
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < DW; ++d) prev[kb][d] = bk[d];
+            const vec_t b0 = as_vec<vec_t, DW>(bk);
+#pragma unroll
+            for (int m = 0; m < MB; ++m) acc[m] = MmaT<TM>::mma(as_vec<vec_t, DW>(wd[kb][m]), b0, acc[m]);
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) pp[b] = __float_as_uint(p[b]);
+        pface = face;
+    }
+    // hidden layers 2..n_hidden, then the head, as k_query_mma with one column block
+    float o[kMaxOut];
+#pragma unroll
+    for (int k = 0; k < kMaxOut; ++k) o[k] = 0.0f;
+    if (count > 0) {
+        for (int k = 1; k <= mm.n_hidden; ++k) {
+            const bool head = k == mm.n_hidden;
+            const float dqi = mm.dq[k - 1], qsi = mm.qs[k];
+            uint32_t xb[MB][2][DW];
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    float v[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float y = MmaT<TM>::scaled ? acc[m][8 * s2 + e] * dqi : acc[m][8 * s2 + e];
+                        v[e] = act_f(y, mm.act, mm.slope);
+                    }
+                    pack8<TM>(v, qsi, xb[m][s2]);
+                }
+            const int MO = head ? 1 : MB;
+            const uint32_t *Wk = Wv + mm.woff[k] + (size_t)lane * DW;
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[m][e] = 0.0f;
+#pragma unroll
+            for (int mo = 0; mo < MB; ++mo) {
+                if (mo < MO) {
+#pragma unroll
+                    for (int m = 0; m < MB; ++m)
+#pragma unroll
+                        for (int s2 = 0; s2 < 2; ++s2) {
+                            uint32_t wd2[DW];
+                            load_frag<DW>(Wk + (size_t)((mo * MB + m) * 2 + s2) * 64 * DW, wd2);
+                            acc[mo] = MmaT<TM>::mma(as_vec<vec_t, DW>(wd2), as_vec<vec_t, DW>(xb[m][s2]), acc[mo]);
+                        }
+                }
+            }
+        }
+        // rows 8q + r of the head lie in lanes 0..31, rows 8q + 4 + r in lanes 32..63
+        uint32_t x[8], y[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            x[e] = __float_as_uint(acc[0][e]);
+            y[e] = x[e];
+            swap32(x[e], y[e]);
+        }
+        const float dqo = MmaT<TM>::scaled ? mm.dq[mm.n_hidden] : 1.0f;
+#pragma unroll
+        for (int q2 = 0; q2 < 2; ++q2)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                o[8 * q2 + rr] = __uint_as_float(x[4 * q2 + rr]) * dqo;
+                o[8 * q2 + 4 + rr] = __uint_as_float(y[4 * q2 + rr]) * dqo;
+            }
+    }
+    if (!live || lane != 0u) return;
+    if (A.dbg.count) A.dbg.count[r] = w.valid ? count : -1;
+    if (A.dbg.tatb) {
+        A.dbg.tatb[2 * r] = w.ta;
+        A.dbg.tatb[2 * r + 1] = w.tb;
+    }
+    if (A.dbg.out) {
+#pragma unroll
+        for (int k = 0; k < kMaxOut; ++k)
+            if (k < mm.out_dim) A.dbg.out[(size_t)r * mm.out_dim + k] = count > 0 ? o[k] : 0.0f;
+    }
+    decode_store<false>(A, mm, r, pair, w, count, o);
 }
 
 // ------------------------------------------------------------- gather ceiling

@@ -21,6 +21,10 @@ hipError_t launch_f32(const QueryArgs &A, int feat_dtype, int F, bool pairs, uin
 // One wave per ray (FP32 features and MLP, width 64, F <= 3, at most 16 levels), for `grid`
 // tiles' slots starting at tile A.tile0.
 hipError_t launch_lat(const QueryArgs &A, int F, uint32_t grid, hipStream_t s);
+// The same with the MLP on the matrix cores (two features per level, at most two K blocks).
+hipError_t launch_mma_small_f16(const QueryArgs &A, int feat_dtype, int kbm, uint32_t grid, hipStream_t s);
+hipError_t launch_mma_small_bf16(const QueryArgs &A, int feat_dtype, int kbm, uint32_t grid, hipStream_t s);
+hipError_t launch_mma_small_fp8(const QueryArgs &A, int feat_dtype, int kbm, uint32_t grid, hipStream_t s);
 hipError_t launch_mma_f16(const QueryArgs &A, int feat_dtype, int F, int kbm, bool pairs, uint32_t grid,
                           hipStream_t s);
 hipError_t launch_mma_bf16(const QueryArgs &A, int feat_dtype, int F, int kbm, bool pairs, uint32_t grid,

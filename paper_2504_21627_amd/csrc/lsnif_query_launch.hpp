@@ -56,6 +56,25 @@ inline void mma_by_kb(const QueryArgs &A, int kbm, bool pairs, uint32_t grid, hi
     else mma_go<TF, TM, F, 8>(A, pairs, grid, s);
 }
 
+// One wave per ray (two features per level, width 64, at most two K blocks per point) over
+// `grid` tiles' slots starting at tile A.tile0.
+template <typename TF, typename TM>
+inline void mma_small_go(const QueryArgs &A, int kbm, uint32_t grid, hipStream_t s)
+{
+    const dim3 blocks(grid * (kBlock / kLatWaves)), threads(64 * kLatWaves);
+    if (kbm <= 1) hipLaunchKernelGGL((k_query_mma_lat<TF, TM, 1>), blocks, threads, 0, s, A);
+    else hipLaunchKernelGGL((k_query_mma_lat<TF, TM, 2>), blocks, threads, 0, s, A);
+}
+
+template <typename TM>
+inline hipError_t launch_mma_small(const QueryArgs &A, int feat_dtype, int kbm, uint32_t grid, hipStream_t s)
+{
+    if (feat_dtype == LSNIF_FP32) mma_small_go<float, TM>(A, kbm, grid, s);
+    else if (feat_dtype == LSNIF_FP16) mma_small_go<_Float16, TM>(A, kbm, grid, s);
+    else mma_small_go<__bf16, TM>(A, kbm, grid, s);
+    return hipGetLastError();
+}
+
 template <typename TM>
 inline hipError_t launch_mma(const QueryArgs &A, int feat_dtype, int F, int kbm, bool pairs, uint32_t grid,
                              hipStream_t s)

@@ -137,6 +137,38 @@ def test_small_batch_wave_per_ray(L, ctx, c1):
         L.lsnif_release(ctx, oid)
 
 
+@pytest.mark.parametrize("feat,mlp", [("fp16", "fp16"), ("bf16", "bf16"), ("fp32", "bf16"), ("fp16", "fp8")])
+def test_small_batch_matrix_core(L, ctx, c2_small, feat, mlp):
+    """Matrix-core objects' batches of at most 8,192 rays run one wave per ray, each of the
+    32 columns of every product holding that ray: on c2's object (16 levels, two K blocks)
+    4,096 rays give the raw outputs and hits that the same rays get three times over
+    (12,288 rays, k_query_mma), bit for bit, with the per-layer FP8 scales fixed."""
+    import torch
+    obj = c2_small["objects"][0]
+    rays = c2_small["rays"][:4096]
+    n = len(rays)
+    _say(f"small batch, {feat}/{mlp}: {n} rays against {3 * n}")
+    scale = [1.0 / 64.0] * (obj.n_hidden + 1) if mlp == "fp8" else None
+    oid = L.lsnif_build(ctx, L.ObjectDesc(obj, feat, mlp, fp8_act_scale=scale))
+    try:
+        def run(r):
+            m = len(r)
+            t = torch.from_numpy(np.ascontiguousarray(r, np.float32)).cuda()
+            out = torch.empty((m, 6), dtype=torch.float32, device="cuda")
+            raw = torch.empty((m, obj.out_dim), dtype=torch.float32, device="cuda")
+            L.lsnif_query_debug(ctx, oid, t, out, {"out": raw})
+            torch.cuda.synchronize()
+            return out.cpu().numpy(), raw.cpu().numpy()
+        small_out, small_raw = run(rays)
+        big_out, big_raw = run(np.concatenate([rays] * 3))
+        for k in range(3):
+            assert np.array_equal(big_out[k * n:(k + 1) * n].view(np.uint32), small_out.view(np.uint32)), k
+            assert np.array_equal(big_raw[k * n:(k + 1) * n].view(np.uint32), small_raw.view(np.uint32)), k
+        assert (small_out[:, 0].view(np.uint32) == 1).sum() > 100   # hits to compare
+    finally:
+        L.lsnif_release(ctx, oid)
+
+
 @pytest.mark.parametrize("feat,mlp", [("fp16", "fp16"), ("bf16", "bf16"), ("fp32", "fp16")])
 def test_c1_mma_parity(L, ctx, c1, feat, mlp):
     obj, rays = c1["objects"][0], c1["rays"]
