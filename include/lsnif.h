@@ -204,7 +204,11 @@ lsnif_status lsnif_object_bytes(lsnif_ctx *ctx, uint32_t object_id, uint64_t *by
  * (order them, or use graphs or the serving loop, which own their
  * workspaces).  Calls on one stream are ordered by the stream. */
 
-/* Query n rays (object space) against one object: out[i] answers rays[i]. */
+/* Query n rays (object space) against one object: out[i] answers rays[i].
+ * Batches of at most 8,192 rays of a width-64 object with at most 16 levels
+ * (FP32 features and MLP with F <= 3, or a matrix-core MLP with F = 2) run
+ * one wave per ray instead of one ray per lane (lower latency); a ray's answer
+ * is the same bits either way. */
 lsnif_status lsnif_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_rays,
                          uint32_t n, lsnif_hit *d_out, void *stream);
 
