@@ -333,7 +333,8 @@ lsnif_status lsnif_bounce(lsnif_ctx *ctx, const lsnif_ray *d_rays, const lsnif_h
  *                 per axis, no octant); rays that meet the grid close together
  *                 then share 256-ray tiles (the work decomposition of Sec. 4:
  *                 dispatch sorted rays rather than scattered ones).
- *  pair_bits      the same grouping, 2^pair_bits cells per axis (1..5), for the
+ *  pair_bits      the same grouping, 2^pair_bits cells per axis (1..5), or at 6
+ *                 by the cell alone (64 cells per axis, no octant), for the
  *                 object's pairs in pair queries, within the object's tiles.
  *  hot_lds_bytes  LDS per workgroup for the object's coarsest levels (0..40960):
  *                 those levels, all of whose used entries fit, are copied into
@@ -359,7 +360,7 @@ lsnif_status lsnif_bounce(lsnif_ctx *ctx, const lsnif_ray *d_rays, const lsnif_h
  * the best so far) on the
  * caller's batch, a warm-up and three timed queries each on a private stream,
  * keeps the fastest for the object and returns it.  lsnif_autotune_pairs does
- * the same for a pair query (pair_bits 2, 3, 4, 5 x hot_lds_bytes, then
+ * the same for a pair query (pair_bits 2, 3, 4, 5, 6 x hot_lds_bytes, then
  * walk_chunks, then persistent), applying one choice to every object of the context.  Both
  * overwrite d_out, synchronise the device and, like lsnif_set_tuning, make the
  * context's captured graphs stale.

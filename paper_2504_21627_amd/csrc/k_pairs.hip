@@ -39,11 +39,12 @@ __global__ __launch_bounds__(kBlock) void k_pairs_fill(PairPlan P)
     if (i < P.n_tiles) P.tile_obj[i] = -1;
 }
 
-// The low 5 bits of x spread to every third bit (one axis of a Morton code).
-__device__ __forceinline__ uint32_t spread5(uint32_t x)
+// The low 6 bits of x spread to every third bit (one axis of a Morton code).
+__device__ __forceinline__ uint32_t spread6(uint32_t x)
 {
-    x &= 31u;
-    return (x & 1u) | ((x & 2u) << 2) | ((x & 4u) << 4) | ((x & 8u) << 6) | ((x & 16u) << 8);
+    x &= 63u;
+    return (x & 1u) | ((x & 2u) << 2) | ((x & 4u) << 4) | ((x & 8u) << 6) | ((x & 16u) << 8) |
+           ((x & 32u) << 10);
 }
 
 __global__ __launch_bounds__(kBlock) void k_pairs_keys(PairPlan P)
@@ -72,8 +73,9 @@ __global__ __launch_bounds__(kBlock) void k_pairs_keys(PairPlan P)
                     }
                     const uint32_t oct = (w.d[0] < 0.0f ? 1u : 0u) | (w.d[1] < 0.0f ? 2u : 0u) |
                                          (w.d[2] < 0.0f ? 4u : 0u);
-                    bin = o * P.bins +
-                          ((oct << (3u * P.bits)) | spread5(c[0]) | (spread5(c[1]) << 1) | (spread5(c[2]) << 2));
+                    const uint32_t cell = spread6(c[0]) | (spread6(c[1]) << 1) | (spread6(c[2]) << 2);
+                    // the octant above the object's own cell bits, none at 64 cells per axis
+                    bin = o * P.bins + (g.pair_bits >= 6u ? cell : (oct << (3u * g.pair_bits)) | cell);
                 }
             }
         }

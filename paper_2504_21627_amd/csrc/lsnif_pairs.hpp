@@ -4,11 +4,15 @@
 
 namespace lsnif {
 
-// Counters per object of the pair grouping at 2^bits cells per axis: 8 octants x cells^3,
-// at least 4096 (the per-object scan works in chunks of 2048).  A query uses the finest
-// pair_bits of its objects (coarser objects use a subset of their bins).
-constexpr uint32_t kMaxPairBits = 5;
-__host__ __device__ inline uint32_t pair_bins(uint32_t bits) { return 8u << (3u * (bits < 3u ? 3u : bits)); }
+// Counters per object of the pair grouping at 2^bits cells per axis: 8 octants x cells^3 up
+// to 5 bits, cells^3 alone (no octant) at 6, at least 4096 (the per-object scan works in
+// chunks of 2048).  A query uses the finest pair_bits of its objects (coarser objects use a
+// subset of their bins).
+constexpr uint32_t kMaxPairBits = 6;
+__host__ __device__ inline uint32_t pair_bins(uint32_t bits)
+{
+    return bits >= 6u ? 1u << 18 : 8u << (3u * (bits < 3u ? 3u : bits));
+}
 
 struct PairPlan {
     const float4 *rays;

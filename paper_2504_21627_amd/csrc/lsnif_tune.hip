@@ -21,7 +21,7 @@ lsnif_status check_tuning(const lsnif_tuning *t)
 {
     if (!t) return fail(LSNIF_E_INVALID, "tuning is NULL");
     if (t->sort_bits < 0 || t->sort_bits > 7) return fail(LSNIF_E_INVALID, "sort_bits must be 0..7");
-    if (t->pair_bits < 1 || t->pair_bits > 5) return fail(LSNIF_E_INVALID, "pair_bits must be 1..5");
+    if (t->pair_bits < 1 || t->pair_bits > 6) return fail(LSNIF_E_INVALID, "pair_bits must be 1..6");
     if (t->hot_lds_bytes < 0 || t->hot_lds_bytes > (int32_t)kHotLdsBudget)
         return fail(LSNIF_E_INVALID, "hot_lds_bytes must be 0..%u", kHotLdsBudget);
     if (t->walk_chunks < 1 || t->walk_chunks > 16) return fail(LSNIF_E_INVALID, "walk_chunks must be 1..16");
@@ -224,7 +224,7 @@ lsnif_status lsnif_autotune_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint3
             }
             return LSNIF_OK;
         };
-        for (int pb : {2, 3, 4, 5})
+        for (int pb : {2, 3, 4, 5, 6})
             for (int32_t hot : kHotCandidates)
                 if (lsnif_status e = run(lsnif_tuning{0, pb, hot, (int32_t)start_chunks, start_persist})) return e;
         const lsnif_tuning best = win;

@@ -57,7 +57,7 @@ def test_single_object_tunings_agree(L):
             with pytest.raises(L.LsnifError):
                 L.lsnif_set_tuning(ctx, oid, 5, 4, 0, 17)
             with pytest.raises(L.LsnifError):
-                L.lsnif_set_tuning(ctx, oid, 5, 6, 0)
+                L.lsnif_set_tuning(ctx, oid, 5, 7, 0)
             with pytest.raises(L.LsnifError):
                 L.lsnif_set_tuning(ctx, oid, 5, 4, 0, 1, 2)
             L.lsnif_release(ctx, oid)
@@ -78,11 +78,12 @@ def test_pair_tunings_agree(L):
         pr = torch.arange(len(rays_np), dtype=torch.int32, device="cuda")
         pi = torch.from_numpy(owner.astype(np.int32)).cuda()
         ref = None
-        # pb None: the objects alternate between the finest and a coarse grouping
+        # a pair (fine, coarse): the objects alternate between two groupings
         for pb, hot, ch, pe in ((4, 40960, 1, 0), (2, 0, 4, 0), (3, 20480, 16, 1), (5, 0, 1, 1), (1, 0, 2, 0),
-                                (None, 0, 1, 0), (4, 0, 1, 1), (None, 40960, 2, 1)):
+                                ((5, 2), 0, 1, 0), (4, 0, 1, 1), ((5, 2), 40960, 2, 1), (6, 0, 1, 0),
+                                ((6, 3), 20480, 1, 1), ((6, 5), 0, 2, 0)):
             for k, i in enumerate(ids):
-                L.lsnif_set_tuning(ctx, i, 5, pb if pb is not None else (5 if k % 2 else 2), hot, ch, pe)
+                L.lsnif_set_tuning(ctx, i, 5, pb if isinstance(pb, int) else pb[k % 2 == 0], hot, ch, pe)
             out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
             L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out)
             torch.cuda.synchronize()
@@ -94,7 +95,7 @@ def test_pair_tunings_agree(L):
         out = torch.empty((len(rays_np), 6), dtype=torch.float32, device="cuda")
         best = L.lsnif_autotune_pairs(ctx, rays, pr, pi, inst, out)
         print("pairs autotuned", best, flush=True)
-        assert best["pair_bits"] in (2, 3, 4, 5) and best["walk_chunks"] in (1, 2, 4, 8)
+        assert best["pair_bits"] in (2, 3, 4, 5, 6) and best["walk_chunks"] in (1, 2, 4, 8)
         L.lsnif_query_pairs(ctx, rays, pr, pi, inst, out)
         torch.cuda.synchronize()
         assert np.array_equal(bits(out), ref)
