@@ -270,6 +270,10 @@ def bench_c5(L, n_requests, seed=7):
         pr, pi = pr_d[:n_pairs].cpu().numpy(), pi_d[:n_pairs].cpu().numpy()
         # the whole pool as one scene query (broad phase + pair query)
         out_d = torch.empty((len(rays), 6), dtype=torch.float32, device="cuda")
+        # the pair tuning of every object, timed on the pool's pairs; the scene query, the
+        # wavefront loop and the serving loop all run with it
+        print("[bench] autotuning the c5 pair query", file=sys.stderr, flush=True)
+        tuning = L.lsnif_autotune_pairs(ctx, rays_d, pr_d[:n_pairs], pi_d[:n_pairs], inst_d, out_d)
         sc_ms = []
         for _ in range(6):
             torch.cuda.synchronize()
@@ -348,7 +352,7 @@ def bench_c5(L, n_requests, seed=7):
         "workload": "c5: c4's 64 objects as 8x8 instances, 1024x1024 primary pool + 3M secondary "
                     f"(diffuse, shadow) rays, {len(windows)} requests of 256-2M rays, depth 1-4, "
                     "fp16, 4 GiB in-flight budget, 8 slots, 4 streams",
-        "requests": len(windows), "rays": total, "pairs_per_ray": len(pr) / len(rays),
+        "requests": len(windows), "rays": total, "pairs_per_ray": len(pr) / len(rays), "tuning": tuning,
         "broad_phase": {"where": "device (lsnif_broad_phase)", "pool_rays": len(rays), "pairs": int(n_pairs),
                         "ms": float(np.median(bp_ms[1:])),
                         "mrays_s": len(rays) / float(np.median(bp_ms[1:])) / 1e3},

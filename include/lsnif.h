@@ -288,7 +288,10 @@ lsnif_status lsnif_query_pairs(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t
  * read the count; the writing pass is enqueued after it and returns without
  * waiting.  If the count exceeds cap, nothing is written and LSNIF_E_NOMEM is
  * returned with *n_pairs set.  n_rays x n_inst must be below 2^32 (else
- * LSNIF_E_INVALID).  Uses a workspace of the context (4 bytes per ray). */
+ * LSNIF_E_INVALID).  Uses a workspace of the context: 4 bytes per ray, and
+ * with at most 256 instances 4 more per ray and 32 instances, where the
+ * counting pass keeps the instances each ray meets so that the writing pass
+ * does not test them again. */
 lsnif_status lsnif_broad_phase(lsnif_ctx *ctx, const lsnif_ray *d_rays, uint32_t n_rays,
                                const lsnif_instance *d_inst, uint32_t n_inst, uint32_t *d_pair_ray,
                                uint32_t *d_pair_inst, uint32_t cap, uint32_t *n_pairs, void *stream);

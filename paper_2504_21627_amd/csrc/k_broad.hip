@@ -9,7 +9,9 @@
 // One lane per ray walks every instance in order (the instance and its
 // object's constants are wave-uniform, read through the scalar path); a
 // counting pass, an exclusive scan of the counts and a writing pass list the
-// pairs by ray, then instance.
+// pairs by ray, then instance.  For up to 256 instances the counting pass
+// keeps each ray's hit instances as a bit mask, and the writing pass reads
+// the masks rather than repeating the tests.
 #include "lsnif_kernels.hpp"
 #include "lsnif_launch.hpp"
 
@@ -27,28 +29,49 @@ __global__ __launch_bounds__(kBlock) void k_broad(BroadArgs B)
         rb = B.rays[2 * r + 1];
     }
     uint32_t n = 0, at = WRITE && live ? B.offsets[r] : 0u;
+    if (WRITE && B.mask_words) {
+        if (!live) return;
+        for (uint32_t k = 0; k < B.mask_words; ++k) {
+            uint32_t m = B.masks[(size_t)k * B.n_rays + r];
+            while (m) {
+                B.pair_ray[at] = r;
+                B.pair_inst[at] = 32u * k + (uint32_t)__builtin_ctz(m);
+                ++at;
+                m &= m - 1u;
+            }
+        }
+        return;
+    }
     typedef const __attribute__((address_space(4))) lsnif_instance cinst;
+    uint32_t bits = 0;
     for (uint32_t i = 0; i < B.n_inst; ++i) {
         const uint32_t o = ((cinst *)B.inst)[i].object_id;
-        if (o >= B.n_objs) continue;   // no such object: no pair
-        const cObjDev &O = ((const cObjDev *)B.objs)[o];
-        if (!O.live) continue;
-        lsnif_instance I;
-        I.object_id = o;
+        bool hit = false;
+        if (o < B.n_objs && ((const cObjDev *)B.objs)[o].live) {   // else no such object: no pair
+            const cObjDev &O = ((const cObjDev *)B.objs)[o];
+            lsnif_instance I;
+            I.object_id = o;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) I.world_to_object[k] = ((cinst *)B.inst)[i].world_to_object[k];
-        float4 a = ra, b = rb;
-        to_object_space(I, a, b);
-        VRay w;
-        setup_ray(O.g, a, b, w);
-        if (live && w.cand && w.ta <= w.tmax) {
+            for (int k = 0; k < 12; ++k) I.world_to_object[k] = ((cinst *)B.inst)[i].world_to_object[k];
+            float4 a = ra, b = rb;
+            to_object_space(I, a, b);
+            VRay w;
+            setup_ray(O.g, a, b, w);
+            hit = live && w.cand && w.ta <= w.tmax;
+        }
+        if (hit) {
             if constexpr (WRITE) {
                 B.pair_ray[at] = r;
                 B.pair_inst[at] = i;
                 ++at;
             } else {
                 ++n;
+                bits |= 1u << (i & 31u);
             }
+        }
+        if (!WRITE && B.mask_words && ((i & 31u) == 31u || i + 1 == B.n_inst)) {   // i is wave-uniform
+            if (live) B.masks[(size_t)(i >> 5) * B.n_rays + r] = bits;
+            bits = 0;
         }
     }
     if (!WRITE && live) B.offsets[r] = n;

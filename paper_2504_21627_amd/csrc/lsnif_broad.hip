@@ -35,7 +35,10 @@ lsnif_status count_pairs(lsnif_ctx *ctx, uint32_t n_objs, const lsnif_ray *d_ray
                          uint32_t &total)
 {
     const size_t n1 = (size_t)n_rays + 1, parts = (n1 + 1023) / 1024;
-    lsnif_status st = grow_workspace(ctx->bws, ctx->bws_bytes, al256(n1 * 4) + al256(parts * 4));
+    const uint32_t words = (n_inst + 31) / 32;
+    const uint32_t mask_words = words <= kBroadMaskWords ? words : 0u;
+    lsnif_status st = grow_workspace(ctx->bws, ctx->bws_bytes,
+                                     al256(n1 * 4) + al256(parts * 4) + al256((size_t)mask_words * n_rays * 4));
     if (st) return st;
     B = BroadArgs{};
     B.rays = reinterpret_cast<const float4 *>(d_rays);
@@ -46,6 +49,8 @@ lsnif_status count_pairs(lsnif_ctx *ctx, uint32_t n_objs, const lsnif_ray *d_ray
     B.n_objs = n_objs;
     B.offsets = static_cast<uint32_t *>(ctx->bws);
     uint32_t *part = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->bws) + al256(n1 * 4));
+    B.mask_words = mask_words;
+    B.masks = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->bws) + al256(n1 * 4) + al256(parts * 4));
     HIP_TRY(launch_broad_count(B, s));
     HIP_TRY(launch_exclusive_scan(B.offsets, (uint32_t)n1, part, s));
     HIP_TRY(hipMemcpyAsync(&total, B.offsets + n_rays, sizeof(uint32_t), hipMemcpyDeviceToHost, s));

@@ -1671,7 +1671,13 @@ struct BroadArgs {
     uint32_t n_objs;
     uint32_t *offsets;        // [n_rays + 1]: pairs per ray, then their exclusive scan
     uint32_t *pair_ray, *pair_inst;
+    // With mask_words > 0 the counting pass also records which instances each ray
+    // meets (bit i % 32 of word i / 32, word-major: masks[(i / 32) n_rays + r]) and
+    // the writing pass lists the pairs from those bits instead of testing again.
+    uint32_t *masks;
+    uint32_t mask_words;
 };
+constexpr uint32_t kBroadMaskWords = 8;   // instance masks for launches of at most 256 instances
 
 // ------------------------------------------------------------ merged serving
 // One member of a merged serving launch: its own buffers and where its rays and

@@ -71,6 +71,37 @@ def test_broad_phase_matches_oracle(L, scene):
         L.lsnif_destroy(ctx)
 
 
+@pytest.mark.parametrize("n_inst", [40, 256, 257])
+def test_broad_phase_many_instances(L, scene, n_inst):
+    """Instance bit masks over several words (40, and 256: the most the masks serve) and the
+    repeated tests beyond them (257): the pairs are the oracle's, an instance naming no built
+    object (index 37) giving none."""
+    import torch
+    objs, insts, boxes, rays_np = scene
+    rays_np = rays_np[::3]
+    many = [insts[k % len(insts)] for k in range(n_inst)]
+    want_r, want_i = oracle.broad_phase(objs, many, rays_np)
+    keep = want_i != 37
+    want_r, want_i = want_r[keep], want_i[keep]
+    ctx = L.lsnif_create(0)
+    try:
+        ids, inst, rays = setup(L, ctx, objs, many, rays_np)
+        inst[37, 0] = 999
+        cap = len(want_r) + 100
+        pr = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+        pi = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+        for _ in range(2):   # the second call reuses the workspace and its stale masks
+            n = L.lsnif_broad_phase(ctx, rays, inst, pr, pi)
+            torch.cuda.synchronize()
+            assert n == len(want_r)
+            assert np.array_equal(pr[:n].cpu().numpy().astype(np.uint32), want_r)
+            assert np.array_equal(pi[:n].cpu().numpy().astype(np.uint32), want_i)
+            assert (pr[n:] == -1).all()
+        print(f"{n_inst} instances: {n} pairs", flush=True)
+    finally:
+        L.lsnif_destroy(ctx)
+
+
 def test_scene_query_equals_pairs_query(L, scene):
     """lsnif_query_scene answers every ray as the pair query does given the host's (looser)
     world-box pairs, bit for bit, and agrees with the oracle's pair query."""
