@@ -805,8 +805,8 @@ def main():
                          "against which rocprofv3's FETCH_SIZE/WRITE_SIZE counters are scaled")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); every box here has one GPU "
-              "and this build runs no multi-GPU path.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the library has no multi-GPU "
+              "path.", file=sys.stderr)
         sys.exit(2)
 
     legs = set(args.legs.split(","))
