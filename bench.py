@@ -312,7 +312,7 @@ def bench_c5(L, n_requests, seed=7):
         del out_d, pr_d, pi_d, nxt, hits, bufs
         rs = RequestSet(L, rays, pr, pi, insts, windows)
         torch.cuda.synchronize()
-        cfg = dict(max_inflight=8, hbm_budget=4 << 30, n_streams=4)
+        cfg = dict(max_inflight=8, hbm_budget=4 << 30, n_streams=4, merge_rays=1 << 21)
 
         def run(arrivals):
             L.lsnif_serve_start(ctx, **cfg)
@@ -351,7 +351,7 @@ def bench_c5(L, n_requests, seed=7):
     return {
         "workload": "c5: c4's 64 objects as 8x8 instances, 1024x1024 primary pool + 3M secondary "
                     f"(diffuse, shadow) rays, {len(windows)} requests of 256-2M rays, depth 1-4, "
-                    "fp16, 4 GiB in-flight budget, 8 slots, 4 streams",
+                    "fp16, 4 GiB in-flight budget, 8 slots, 4 streams, requests merged up to 8M rays per launch",
         "requests": len(windows), "rays": total, "pairs_per_ray": len(pr) / len(rays), "tuning": tuning,
         "broad_phase": {"where": "device (lsnif_broad_phase)", "pool_rays": len(rays), "pairs": int(n_pairs),
                         "ms": float(np.median(bp_ms[1:])),

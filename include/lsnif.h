@@ -423,7 +423,7 @@ void lsnif_graph_destroy(lsnif_graph *graph);
  * merged: the request at the head of the queue and the ones right behind it
  * with the same target (the same object_id, or pairs over the same d_inst and
  * n_inst), each of at most merge_rays rays, up to merge_max requests and
- * 2,097,152 rays in all, are admitted as one launch that takes one slot: their
+ * 8,388,608 rays in all, are admitted as one launch that takes one slot: their
  * rays and pairs are staged into one batch in the launch's workspace, one
  * query answers it, and each request's answers are copied to its own d_out;
  * they complete together.  Results are those of the direct calls: a request's

@@ -14,7 +14,7 @@
 // Small requests that wait together are merged: the request at the head of
 // the queue and the ones right behind it that query the same target (the same
 // object, or pairs over the same instance array), each of at most merge_rays
-// rays, up to merge_max of them and 2^21 rays in all, are admitted as one
+// rays, up to merge_max of them and 2^23 rays in all, are admitted as one
 // launch: their rays and pairs are staged into one batch (k_serve.hip), one
 // query answers it, and each request's answers are copied back to its own
 // output.  Every member completes when the launch does.  A ray's answer does
@@ -102,7 +102,7 @@ struct Req {
 };
 
 constexpr uint32_t kMergeRays = 1u << 18;     // default largest request that may be merged
-constexpr uint64_t kMergeTotal = 1ull << 21;  // rays of one merged launch at most
+constexpr uint64_t kMergeTotal = 1ull << 23;  // rays of one merged launch at most
 
 inline size_t al256s(size_t x) { return (x + 255) / 256 * 256; }
 
