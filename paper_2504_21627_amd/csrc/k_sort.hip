@@ -1,12 +1,19 @@
-// Coherence order of a ray batch: a one-pass counting sort of the rays by a
-// coarse key -- direction octant, then the Morton code of the cell (2^b per
-// axis, b <= 6 chosen per object) of the voxel grid where the ray's segment
-// [ta, tb] starts; at b = 7 (128^3 cells) the cell alone, without the
-// octant.  Rays that meet the
-// grid close together and head the same way then share waves, so their
-// walks and their hash-grid gathers touch the same cache lines.  Order within
-// a key is whatever the atomics give; every ray's result is independent of
-// the order the rays are processed in.
+// Coherence order of a ray batch: the rays sorted by a coarse key --
+// direction octant, then the Morton code of the cell (2^b per axis, b <= 6
+// chosen per object) of the voxel grid where the ray's segment [ta, tb]
+// starts; at b = 7 (128^3 cells) the cell alone, without the octant.  Rays
+// that meet the grid close together and head the same way then share waves,
+// so their walks and their hash-grid gathers touch the same cache lines.
+//
+// The sort is a least-significant-digit radix sort with 8-bit digits (three
+// passes for the largest keys).  Each pass counts the digit per block of
+// kRadixTile consecutive rays of its input (the first pass while forming the
+// keys) in LDS, scans the counters digit-major, which gives every (digit,
+// block) its output range, then ranks each block's rays stably (a wave
+// matches equal digits with one ballot per digit bit and keeps running counts
+// per digit in LDS) and writes them there.  No global atomics: the counting
+// sort this replaces spent most of its time in one returning atomic per ray.
+// Every ray's result is independent of the order the rays are processed in.
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -53,17 +60,93 @@ __global__ __launch_bounds__(kBlock) void k_fill(uint32_t *p, uint32_t n, uint32
     if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sort_keys(Geom g, const float4 *rays, uint32_t n, uint32_t *keys,
-                                                      uint32_t *hist)
+constexpr uint32_t kRadixPer = kRadixTile / kBlock;   // rays per thread in a block of the passes
+constexpr uint32_t kRadixMaxPasses = 3;                 // keys of at most 24 bits
+
+// Block b: the keys of rays [kRadixTile b, kRadixTile (b + 1)) (keys != NULL: formed
+// from the rays first) and the count of each value of their digit at `shift`, to
+// hist[digit nblk + b].
+__global__ __launch_bounds__(kBlock) void k_radix_count(Geom g, const float4 *rays, uint32_t n, uint32_t *keys,
+                                                        const uint32_t *sk, uint32_t *hist, uint32_t nblk,
+                                                        uint32_t shift)
 {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    const bool live = i < n;
-    uint32_t k = 0;
-    if (live) {
-        k = coherence_key(g, rays[2 * i], rays[2 * i + 1]);
-        keys[i] = k;
+    __shared__ uint32_t cnt[256];
+    const uint32_t t = threadIdx.x, b = blockIdx.x;
+    cnt[t] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kRadixPer; ++j) {
+        const uint32_t i = b * kRadixTile + j * kBlock + t;
+        if (i < n) {
+            uint32_t k;
+            if (keys) {
+                k = coherence_key(g, rays[2 * i], rays[2 * i + 1]);
+                keys[i] = k;
+            } else {
+                k = sk[i];
+            }
+            atomicAdd(&cnt[(k >> shift) & 255u], 1u);
+        }
     }
-    (void)wave_aggregated_add(hist, k, live);
+    __syncthreads();
+    hist[(size_t)t * nblk + b] = cnt[t];
+}
+
+// One pass: block b moves rays [kRadixTile b, kRadixTile (b + 1)) of (sk, sv) to
+// their places in (dk, dv) by the digit at `shift`, keeping their order within a
+// digit.  off: the exclusive scan of this pass's counters (digit-major), less
+// `base`.  sv NULL: the indices are the positions;
+// dk NULL: the keys are not needed after this pass.  Wave w takes rays
+// 512 w .. 512 w + 511 of the block, 64 at a time, so (wave, step, lane) is
+// the rays' order.
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t *sk, const uint32_t *sv, uint32_t *dk,
+                                                          uint32_t *dv, uint32_t n, const uint32_t *off,
+                                                          uint32_t nblk, uint32_t shift, uint32_t base)
+{
+    __shared__ uint32_t run[kBlock / 64][256];   // per wave: rays of each digit so far, then the wave's start
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6, b = blockIdx.x;
+    for (uint32_t i = t; i < (kBlock / 64) * 256u; i += kBlock) (&run[0][0])[i] = 0u;
+    __syncthreads();
+    const uint64_t below = lane ? (~0ull >> (64u - lane)) : 0ull;
+    uint32_t key[kRadixPer], val[kRadixPer], pos[kRadixPer];
+#pragma unroll
+    for (uint32_t j = 0; j < kRadixPer; ++j) {
+        const uint32_t i = b * kRadixTile + w * (kRadixTile / 4u) + j * 64u + lane;
+        const bool live = i < n;
+        key[j] = live ? sk[i] : 0u;
+        val[j] = live ? (sv ? sv[i] : i) : 0u;
+        const uint32_t d = (key[j] >> shift) & 255u;
+        // lanes holding this lane's digit: one ballot per digit bit
+        uint64_t same = __ballot(live);
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) {
+            const uint64_t ones = __ballot((d >> q) & 1u);
+            same &= ((d >> q) & 1u) ? ones : ~ones;
+        }
+        const uint32_t before = run[w][d];
+        pos[j] = before + (uint32_t)__builtin_popcountll(same & below);
+        if (live && (same & below) == 0ull) run[w][d] = before + (uint32_t)__builtin_popcountll(same);
+    }
+    __syncthreads();
+    {   // thread t = digit t: the start of each wave's rays of that digit
+        uint32_t at = off[(size_t)t * nblk + b] - base;
+#pragma unroll
+        for (uint32_t q = 0; q < kBlock / 64; ++q) {
+            const uint32_t c = run[q][t];
+            run[q][t] = at;
+            at += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kRadixPer; ++j) {
+        const uint32_t i = b * kRadixTile + w * (kRadixTile / 4u) + j * 64u + lane;
+        const uint32_t dst = run[w][(key[j] >> shift) & 255u] + pos[j];
+        if (i < n && dst < n) {
+            if (dk) dk[dst] = key[j];
+            dv[dst] = val[j];
+        }
+    }
 }
 
 // Exclusive scan of the kSortBins counters in two passes: block b first sums
@@ -130,30 +213,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_final(uint32_t *hist, uint32_t 
     }
 }
 
-// kScatterPer rays per thread (rays blockIdx kBlock kScatterPer + j kBlock +
-// threadIdx), their counter atomics all in flight before the first position is
-// used (c2: 109 -> 78 us).
-constexpr uint32_t kScatterPer = 4;
-
-__global__ __launch_bounds__(kBlock) void k_sort_scatter(const uint32_t *keys, uint32_t n, uint32_t *cursor,
-                                                         uint32_t *order)
-{
-    const uint32_t i0 = blockIdx.x * kBlock * kScatterPer + threadIdx.x;
-    AggAdd a[kScatterPer];
-#pragma unroll
-    for (uint32_t j = 0; j < kScatterPer; ++j) {
-        const uint32_t i = i0 + j * kBlock;
-        const bool live = i < n;
-        a[j] = wave_aggregated_issue(cursor, live ? keys[i] : 0u, live);
-    }
-#pragma unroll
-    for (uint32_t j = 0; j < kScatterPer; ++j) {
-        const uint32_t i = i0 + j * kBlock;
-        const uint32_t pos = wave_aggregated_rank(a[j]);
-        if (i < n) order[pos] = i;
-    }
-}
-
 hipError_t launch_exclusive_scan(uint32_t *v, uint32_t n, uint32_t *part, hipStream_t s)
 {
     const uint32_t nblocks = (n + kScanChunk - 1) / kScanChunk;
@@ -199,19 +258,27 @@ uint32_t persistent_blocks(const void *kernel, size_t lds, uint32_t tiles)
     return want < nb ? (want ? want : 8u) : nb;
 }
 
-hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *keys, uint32_t *hist,
-                                 uint32_t *order, hipStream_t s)
+hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *ws, uint32_t **order,
+                                 hipStream_t s)
 {
-    // the workspace holds this resolution's bins, then one partial sum per 1024 bins
-    const uint32_t nbins = sort_bins(g.sort_bits), nblocks = sort_scan_blocks(g.sort_bits);
-    const dim3 gb((nbins + kBlock - 1) / kBlock), gr((n + kBlock - 1) / kBlock);
-    const dim3 gj((n + kBlock * kScatterPer - 1) / (kBlock * kScatterPer));
-    uint32_t *part = hist + nbins;
-    hipLaunchKernelGGL(k_fill, gb, dim3(kBlock), 0, s, hist, nbins, 0u);
-    hipLaunchKernelGGL(k_sort_keys, gr, dim3(kBlock), 0, s, g, rays, n, keys, hist);
-    hipLaunchKernelGGL(k_scan_partial, dim3(nblocks), dim3(kBlock), 0, s, hist, nbins, part);
-    hipLaunchKernelGGL(k_scan_final, dim3(nblocks), dim3(kBlock), 0, s, hist, nbins, part);
-    hipLaunchKernelGGL(k_sort_scatter, gj, dim3(kBlock), 0, s, keys, n, hist, order);
+    static_assert(kRadixTile == 4u * 512u && kBlock == 256u, "a block of the passes is 4 waves of 8 x 64 rays");
+    const uint32_t passes = radix_passes(g.sort_bits), nblk = (n + kRadixTile - 1) / kRadixTile;
+    if (passes > kRadixMaxPasses) return hipErrorInvalidValue;
+    uint32_t *k0 = ws, *v0 = k0 + n, *k1 = v0 + n, *v1 = k1 + n, *hist = v1 + n;
+    const uint32_t counters = 256u * nblk;
+    const uint32_t *sk = k0, *sv = nullptr;
+    for (uint32_t p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_radix_count, dim3(nblk), dim3(kBlock), 0, s, g, rays, n, p ? nullptr : k0, sk, hist,
+                           nblk, 8u * p);
+        const hipError_t e = launch_exclusive_scan(hist, counters, hist + counters, s);
+        if (e != hipSuccess) return e;
+        uint32_t *dk = (p & 1u) ? k0 : k1, *dv = (p & 1u) ? v0 : v1;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kBlock), 0, s, sk, sv, p + 1 < passes ? dk : nullptr,
+                           dv, n, hist, nblk, 8u * p, 0u);
+        sk = dk;
+        sv = dv;
+    }
+    *order = const_cast<uint32_t *>(sv);
     return hipGetLastError();
 }
 

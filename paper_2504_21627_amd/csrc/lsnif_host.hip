@@ -646,11 +646,12 @@ static hipEvent_t take_event(lsnif_ctx *ctx)
 
 static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Coherence-sort arrays (keys, order, bins, scan partials), when the batch is sorted.
+// Coherence-sort arrays (keys and ray indices twice, digit counters, scan partials), when
+// the batch is sorted.
 static size_t sort_ws_bytes(uint32_t n, uint32_t sort_bits)
 {
     if (n < kSortMin || sort_bits == 0) return 0;
-    return al256(((size_t)2 * n + sort_bins(sort_bits) + sort_scan_blocks(sort_bits)) * sizeof(uint32_t));
+    return al256(radix_ws_words(n, sort_bits) * sizeof(uint32_t));
 }
 
 // Voxel counts (one byte) and voxel lists (cap entries) of n_slots slots.
@@ -761,10 +762,8 @@ lsnif_status enqueue_query(lsnif_ctx *ctx, const Object &ob, const lsnif_ray *d_
     }
     const size_t sort_bytes = sort_ws_bytes(n, ob.geom.sort_bits);
     if (sort_bytes) {
-        uint32_t *keys = static_cast<uint32_t *>(ws);
-        uint32_t *order = keys + n;
-        uint32_t *hist = order + n;
-        HIP_TRY(launch_coherence_sort(ob.geom, A.rays, n, keys, hist, order, s));
+        uint32_t *order = nullptr;
+        HIP_TRY(launch_coherence_sort(ob.geom, A.rays, n, static_cast<uint32_t *>(ws), &order, s));
         A.order = order;
     }
     if (ev[1]) HIP_TRY(hipEventRecord(ev[1], s));

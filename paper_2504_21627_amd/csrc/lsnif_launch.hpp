@@ -13,6 +13,23 @@ __host__ __device__ inline uint32_t sort_bins(uint32_t bits)
     return bits >= 7u ? (1u << 21) + 1u : (8u << (3u * bits)) + 1u;
 }
 __host__ __device__ inline uint32_t sort_scan_blocks(uint32_t bits) { return (sort_bins(bits) + 1023u) / 1024u; }
+// The coherence keys are put in order by a least-significant-digit radix sort with 8-bit
+// digits, each block of the passes taking kRadixTile consecutive rays: passes enough
+// for the largest key (sort_bins(bits) - 1), and the 32-bit words of its workspace for n
+// rays -- keys and ray indices twice (the passes alternate between the two copies), then
+// a counter per (digit, block) of a pass and the partial sums of their scan.
+constexpr uint32_t kRadixTile = 2048;
+__host__ __device__ inline uint32_t radix_passes(uint32_t bits)
+{
+    const uint32_t top = sort_bins(bits) - 1u;
+    const uint32_t used = 32u - (uint32_t)__builtin_clz(top | 1u);
+    return (used + 7u) / 8u;
+}
+__host__ __device__ inline size_t radix_ws_words(uint32_t n, uint32_t bits)
+{
+    const size_t counters = (size_t)256u * ((n + kRadixTile - 1u) / kRadixTile);
+    return 4u * (size_t)n + counters + (counters + 1023u) / 1024u;
+}
 struct Geom;
 struct QueryArgs;
 struct DebugArgs;
@@ -62,6 +79,8 @@ hipError_t launch_merge_unpack(const MergeArgs &M, hipStream_t s);
 struct PairPlan;
 hipError_t launch_pairs_prepare(const PairPlan &P, hipStream_t s);
 hipError_t launch_pairs_payload(const PairPlan &P, hipStream_t s);
-hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *keys, uint32_t *hist,
-                                 uint32_t *order, hipStream_t s);
+// Sorts rays 0..n-1 by coherence key in `ws` (radix_ws_words(n, g.sort_bits) words);
+// *order receives the sorted ray indices (inside ws).
+hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *ws, uint32_t **order,
+                                 hipStream_t s);
 }  // namespace lsnif
