@@ -216,16 +216,15 @@ lsnif_status lsnif_query(lsnif_ctx *ctx, uint32_t object_id, const lsnif_ray *d_
  * tight serving loops, harnesses that forbid hipMalloc): lsnif_query with the
  * same kernels and the same results, bit for bit, whose workspace (the
  * coherence sort's keys, ray indices and digit counters; the voxel counts and
- * lists) lives in
- * a fixed device array of LSNIF_NOALLOC_SCRATCH_BYTES that the library holds
- * on every GPU it runs on until the process ends.  The call allocates nothing
+ * lists) lives in a fixed device array of LSNIF_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends.  The call allocates nothing
  * (no hipMalloc or hipFree, no stream or event creation); the caller still
  * passes the rays and the output as for lsnif_query.
  *
  * Limit: the workspace of n rays is about (17.5 + 4 H/2) bytes per ray (the
- * sort's 16.5 and the voxel lists; 53.5 bytes per ray at H = 18, so about
- * 1.25M rays); a batch that
- * needs more returns LSNIF_E_INVALID, naming the limit, and enqueues nothing.
+ * sort's 16.5, the voxel count and lists; 53.5 bytes per ray at H = 18, so
+ * about 1.25M rays); a batch that needs more returns LSNIF_E_INVALID, naming
+ * the limit, and enqueues nothing.
  * Every call on one GPU shares that GPU's array, whatever its context:
  * allocation-free queries that may overlap on the device (different streams,
  * different contexts on the same device, threads) race on it, so order them
