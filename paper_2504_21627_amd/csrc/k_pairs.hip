@@ -2,9 +2,13 @@
 //
 // Before the query kernel, the (ray, instance) pairs are grouped by object
 // and, within an object, by direction octant and the cell (2^b per axis,
-// b <= 5 chosen per object) of the segment start in that object's voxel grid
-// (a counting sort with wave-aggregated atomics).  Each object's run is padded to whole 256-slot tiles, so every
-// workgroup of the query kernel serves one object with one set of weights.
+// b <= 5 chosen per object) of the segment start in that object's voxel grid,
+// or at b = 6 by the cell alone (64 per axis): a key per pair, object-major,
+// put in order by the radix passes of the coherence sort (stable, so pairs
+// of one key keep their given order).  The sorted keys give each object's
+// first position; each object's run is then padded to whole 256-slot tiles,
+// so every workgroup of the query kernel serves one object with one set of
+// weights.
 // Pairs whose ray misses the object's box, or that name a ray, instance or
 // object that does not exist, are dropped here.
 //
@@ -34,7 +38,6 @@ __global__ __launch_bounds__(kBlock) void k_pairs_init(PairPlan P)
 __global__ __launch_bounds__(kBlock) void k_pairs_fill(PairPlan P)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < P.n_objs * P.bins) P.hist[i] = 0u;
     if (i < P.n_slots) P.slot_pair[i] = 0xffffffffu;
     if (i < P.n_tiles) P.tile_obj[i] = -1;
 }
@@ -47,11 +50,19 @@ __device__ __forceinline__ uint32_t spread6(uint32_t x)
            ((x & 32u) << 10);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pairs_keys(PairPlan P)
+// Block b: the keys of pairs [kRadixTile b, kRadixTile (b + 1)) -- object o's keys are
+// o bins + (octant, cell) bin; a dropped pair's is n_objs bins, after every object --
+// and the count of each value of their lowest digit, to hist[digit nblk + b].
+__global__ __launch_bounds__(kBlock) void k_pairs_keys(PairPlan P, uint32_t nblk)
 {
-    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
-    uint32_t bin = 0xffffffffu;
-    if (p < P.n_pairs) {
+    __shared__ uint32_t cnt[256];
+    const uint32_t t = threadIdx.x, b = blockIdx.x;
+    cnt[t] = 0u;
+    __syncthreads();
+    for (uint32_t j = 0; j < kRadixTile / kBlock; ++j) {
+        const uint32_t p = b * kRadixTile + j * kBlock + t;
+        if (p >= P.n_pairs) continue;
+        uint32_t bin = P.n_objs * P.bins;
         const uint32_t r = P.pair_ray[p], i = P.pair_inst[p];
         if (r < P.n_rays && i < P.n_inst) {
             const uint32_t o = P.inst[i].object_id;
@@ -80,56 +91,24 @@ __global__ __launch_bounds__(kBlock) void k_pairs_keys(PairPlan P)
             }
         }
         P.keys[p] = bin;
+        atomicAdd(&cnt[bin & 255u], 1u);
     }
-    (void)wave_aggregated_add(P.hist, bin, bin != 0xffffffffu);
+    __syncthreads();
+    P.hist[(size_t)t * nblk + b] = cnt[t];
 }
 
-// Block o: exclusive scan of object o's P.bins counters in place, total to
-// obj_total[o].  The counters go in chunks of kScanChunk (each thread 8
-// consecutive, two 16-byte loads): per-thread sums, a wave scan with lane
-// shuffles, the four wave totals through LDS, and a carry between chunks.
-constexpr uint32_t kScanPer = 8, kScanChunk = kScanPer * kBlock;
-
-__global__ __launch_bounds__(kBlock) void k_pairs_scan_obj(PairPlan P)
+// Sorted position i (of n): where the objects between its predecessor's and its own
+// start; the last position also closes the objects after its own.  sk: sorted keys.
+__global__ __launch_bounds__(kBlock) void k_pairs_bounds(PairPlan P, const uint32_t *sk)
 {
-    __shared__ uint32_t wsum[kBlock / 64];
-    uint32_t *h = P.hist + (size_t)blockIdx.x * P.bins;
-    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < P.bins; base += kScanChunk) {
-        uint4 *p = reinterpret_cast<uint4 *>(h + base + t * kScanPer);
-        const uint4 a = p[0], b = p[1];
-        const uint32_t v[kScanPer] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-        uint32_t s = 0;
-#pragma unroll
-        for (uint32_t q = 0; q < kScanPer; ++q) s += v[q];
-        uint32_t inc = s;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t u = __shfl_up(inc, o, 64);
-            if (lane >= (uint32_t)o) inc += u;
-        }
-        if (lane == 63) wsum[wv] = inc;
-        __syncthreads();
-        uint32_t run = carry + inc - s, chunk = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < kBlock / 64; ++k) {
-            const uint32_t x = wsum[k];
-            run += k < wv ? x : 0u;
-            chunk += x;
-        }
-        __syncthreads();   // wsum is rewritten by the next chunk
-        uint32_t out[kScanPer];
-#pragma unroll
-        for (uint32_t q = 0; q < kScanPer; ++q) {
-            out[q] = run;
-            run += v[q];
-        }
-        p[0] = make_uint4(out[0], out[1], out[2], out[3]);
-        p[1] = make_uint4(out[4], out[5], out[6], out[7]);
-        carry += chunk;
-    }
-    if (t == 0) P.obj_total[blockIdx.x] = carry;
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= P.n_pairs) return;
+    const uint32_t sh = (uint32_t)__builtin_ctz(P.bins);
+    const uint32_t o = min(sk[i] >> sh, P.n_objs);
+    const uint32_t from = i ? min(sk[i - 1] >> sh, P.n_objs) + 1u : 0u;
+    for (uint32_t q = from; q <= o; ++q) P.obj_start[q] = i;
+    if (i + 1 == P.n_pairs)
+        for (uint32_t q = o + 1; q <= P.n_objs; ++q) P.obj_start[q] = P.n_pairs;
 }
 
 // One block: object runs padded to whole tiles, their offsets, and each tile's object.
@@ -139,7 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs_offsets(PairPlan P)
     if (threadIdx.x == 0) base = 0;
     __syncthreads();
     for (uint32_t o = 0; o < P.n_objs; ++o) {
-        const uint32_t padded = (P.obj_total[o] + kBlock - 1) / kBlock * kBlock;
+        const uint32_t total = P.obj_start[o + 1] - P.obj_start[o];
+        const uint32_t padded = (total + kBlock - 1) / kBlock * kBlock;
         const uint32_t b = base;
         if (threadIdx.x == 0) P.obj_off[o] = b;
         for (uint32_t t = threadIdx.x; t < padded / kBlock; t += kBlock) P.tile_obj[b / kBlock + t] = (int32_t)o;
@@ -149,19 +129,20 @@ __global__ __launch_bounds__(kBlock) void k_pairs_offsets(PairPlan P)
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_pairs_scatter(PairPlan P)
+// Sorted position i: its pair into its object's next slot.  sk, sv: sorted keys and pairs.
+__global__ __launch_bounds__(kBlock) void k_pairs_place(PairPlan P, const uint32_t *sk, const uint32_t *sv)
 {
-    const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
-    const uint32_t bin = p < P.n_pairs ? P.keys[p] : 0xffffffffu;
-    const bool live = bin != 0xffffffffu;
-    const uint32_t within = wave_aggregated_add(P.hist, bin, live);
-    if (live) P.slot_pair[P.obj_off[bin / P.bins] + within] = p;
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= P.obj_start[P.n_objs]) return;   // the dropped pairs sort last
+    const uint32_t o = sk[i] >> (uint32_t)__builtin_ctz(P.bins);
+    const uint32_t slot = P.obj_off[o] + (i - P.obj_start[o]);
+    if (slot < P.n_slots) P.slot_pair[slot] = sv[i];
 }
 
 __global__ __launch_bounds__(kBlock) void k_pairs_payload(PairPlan P)
 {
     const uint32_t p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= P.n_pairs || P.keys[p] == 0xffffffffu) return;
+    if (p >= P.n_pairs || P.keys[p] >= P.n_objs * P.bins) return;   // dropped
     const PairRes res = P.res[p];
     if (!(res.t <= 3.402823466e38f)) return;
     const uint32_t r = P.pair_ray[p], i = P.pair_inst[p];
@@ -187,14 +168,24 @@ __global__ __launch_bounds__(kBlock) void k_pairs_payload(PairPlan P)
 
 hipError_t launch_pairs_prepare(const PairPlan &P, hipStream_t s)
 {
-    const uint32_t nfill = P.n_objs * P.bins > P.n_slots ? P.n_objs * P.bins : P.n_slots;
     hipLaunchKernelGGL(k_pairs_init, dim3((P.n_rays + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P);
-    hipLaunchKernelGGL(k_pairs_fill, dim3((nfill + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL(k_pairs_fill, dim3((P.n_slots + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P);
     if (P.n_pairs == 0) return hipGetLastError();
-    hipLaunchKernelGGL(k_pairs_keys, dim3((P.n_pairs + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P);
-    hipLaunchKernelGGL(k_pairs_scan_obj, dim3(P.n_objs), dim3(kBlock), 0, s, P);
+    const uint32_t nblk = (P.n_pairs + kRadixTile - 1) / kRadixTile, grid = (P.n_pairs + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_pairs_keys, dim3(nblk), dim3(kBlock), 0, s, P, nblk);
+    // passes enough for the dropped pairs' key, n_objs bins
+    const uint32_t top = P.n_objs * P.bins, passes = (32u - (uint32_t)__builtin_clz(top | 1u) + 7u) / 8u;
+    const uint32_t *sk = P.keys, *sv = nullptr;
+    for (uint32_t p = 0; p < passes; ++p) {
+        uint32_t *dk = P.rk[p & 1u], *dv = P.rv[p & 1u];
+        const hipError_t e = launch_radix_pass(sk, sv, dk, dv, P.n_pairs, P.hist, 8u * p, p == 0, s);
+        if (e != hipSuccess) return e;
+        sk = dk;
+        sv = dv;
+    }
+    hipLaunchKernelGGL(k_pairs_bounds, dim3(grid), dim3(kBlock), 0, s, P, sk);
     hipLaunchKernelGGL(k_pairs_offsets, dim3(1), dim3(kBlock), 0, s, P);
-    hipLaunchKernelGGL(k_pairs_scatter, dim3((P.n_pairs + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P);
+    hipLaunchKernelGGL(k_pairs_place, dim3(grid), dim3(kBlock), 0, s, P, sk, sv);
     return hipGetLastError();
 }
 

@@ -60,15 +60,13 @@ __global__ __launch_bounds__(kBlock) void k_fill(uint32_t *p, uint32_t n, uint32
     if (i < n) p[i] = v;
 }
 
-constexpr uint32_t kRadixPer = kRadixTile / kBlock;   // rays per thread in a block of the passes
-constexpr uint32_t kRadixMaxPasses = 3;                 // keys of at most 24 bits
+constexpr uint32_t kRadixPer = kRadixTile / kBlock;   // items per thread in a block of the passes
+constexpr uint32_t kRadixMaxPasses = 3;                 // coherence keys of at most 24 bits
 
-// Block b: the keys of rays [kRadixTile b, kRadixTile (b + 1)) (keys != NULL: formed
-// from the rays first) and the count of each value of their digit at `shift`, to
-// hist[digit nblk + b].
-__global__ __launch_bounds__(kBlock) void k_radix_count(Geom g, const float4 *rays, uint32_t n, uint32_t *keys,
-                                                        const uint32_t *sk, uint32_t *hist, uint32_t nblk,
-                                                        uint32_t shift)
+// Block b: the coherence keys of rays [kRadixTile b, kRadixTile (b + 1)), and the
+// count of each value of their lowest digit, to hist[digit nblk + b].
+__global__ __launch_bounds__(kBlock) void k_radix_keys(Geom g, const float4 *rays, uint32_t n, uint32_t *keys,
+                                                       uint32_t *hist, uint32_t nblk)
 {
     __shared__ uint32_t cnt[256];
     const uint32_t t = threadIdx.x, b = blockIdx.x;
@@ -78,15 +76,28 @@ __global__ __launch_bounds__(kBlock) void k_radix_count(Geom g, const float4 *ra
     for (uint32_t j = 0; j < kRadixPer; ++j) {
         const uint32_t i = b * kRadixTile + j * kBlock + t;
         if (i < n) {
-            uint32_t k;
-            if (keys) {
-                k = coherence_key(g, rays[2 * i], rays[2 * i + 1]);
-                keys[i] = k;
-            } else {
-                k = sk[i];
-            }
-            atomicAdd(&cnt[(k >> shift) & 255u], 1u);
+            const uint32_t k = coherence_key(g, rays[2 * i], rays[2 * i + 1]);
+            keys[i] = k;
+            atomicAdd(&cnt[k & 255u], 1u);
         }
+    }
+    __syncthreads();
+    hist[(size_t)t * nblk + b] = cnt[t];
+}
+
+// Block b: the count of each value of the digit at `shift` among keys
+// [kRadixTile b, kRadixTile (b + 1)), to hist[digit nblk + b].
+__global__ __launch_bounds__(kBlock) void k_radix_count(const uint32_t *sk, uint32_t n, uint32_t *hist,
+                                                        uint32_t nblk, uint32_t shift)
+{
+    __shared__ uint32_t cnt[256];
+    const uint32_t t = threadIdx.x, b = blockIdx.x;
+    cnt[t] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kRadixPer; ++j) {
+        const uint32_t i = b * kRadixTile + j * kBlock + t;
+        if (i < n) atomicAdd(&cnt[(sk[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
     hist[(size_t)t * nblk + b] = cnt[t];
@@ -258,23 +269,31 @@ uint32_t persistent_blocks(const void *kernel, size_t lds, uint32_t tiles)
     return want < nb ? (want ? want : 8u) : nb;
 }
 
+hipError_t launch_radix_pass(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, uint32_t *dv, uint32_t n,
+                             uint32_t *hist, uint32_t shift, bool counted, hipStream_t s)
+{
+    static_assert(kRadixTile == 4u * 512u && kBlock == 256u, "a block of the passes is 4 waves of 8 x 64 items");
+    const uint32_t nblk = (n + kRadixTile - 1) / kRadixTile, counters = 256u * nblk;
+    if (!nblk) return hipSuccess;
+    if (!counted) hipLaunchKernelGGL(k_radix_count, dim3(nblk), dim3(kBlock), 0, s, sk, n, hist, nblk, shift);
+    const hipError_t e = launch_exclusive_scan(hist, counters, hist + counters, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kBlock), 0, s, sk, sv, dk, dv, n, hist, nblk, shift, 0u);
+    return hipGetLastError();
+}
+
 hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *ws, uint32_t **order,
                                  hipStream_t s)
 {
-    static_assert(kRadixTile == 4u * 512u && kBlock == 256u, "a block of the passes is 4 waves of 8 x 64 rays");
     const uint32_t passes = radix_passes(g.sort_bits), nblk = (n + kRadixTile - 1) / kRadixTile;
     if (passes > kRadixMaxPasses) return hipErrorInvalidValue;
     uint32_t *k0 = ws, *v0 = k0 + n, *k1 = v0 + n, *v1 = k1 + n, *hist = v1 + n;
-    const uint32_t counters = 256u * nblk;
+    hipLaunchKernelGGL(k_radix_keys, dim3(nblk), dim3(kBlock), 0, s, g, rays, n, k0, hist, nblk);
     const uint32_t *sk = k0, *sv = nullptr;
     for (uint32_t p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_radix_count, dim3(nblk), dim3(kBlock), 0, s, g, rays, n, p ? nullptr : k0, sk, hist,
-                           nblk, 8u * p);
-        const hipError_t e = launch_exclusive_scan(hist, counters, hist + counters, s);
-        if (e != hipSuccess) return e;
         uint32_t *dk = (p & 1u) ? k0 : k1, *dv = (p & 1u) ? v0 : v1;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kBlock), 0, s, sk, sv, p + 1 < passes ? dk : nullptr,
-                           dv, n, hist, nblk, 8u * p, 0u);
+        const hipError_t e = launch_radix_pass(sk, sv, p + 1 < passes ? dk : nullptr, dv, n, hist, 8u * p, p == 0, s);
+        if (e != hipSuccess) return e;
         sk = dk;
         sv = dv;
     }

@@ -651,7 +651,7 @@ static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 static size_t sort_ws_bytes(uint32_t n, uint32_t sort_bits)
 {
     if (n < kSortMin || sort_bits == 0) return 0;
-    return al256(radix_ws_words(n, sort_bits) * sizeof(uint32_t));
+    return al256(radix_ws_words(n) * sizeof(uint32_t));
 }
 
 // Voxel counts (one byte) and voxel lists (cap entries) of n_slots slots.
@@ -670,10 +670,12 @@ size_t query_ws_bytes(uint32_t n, uint32_t sort_bits, uint32_t cap)
 
 size_t pairs_ws_bytes(uint32_t n_rays, uint32_t n_pairs, uint32_t n_objs, uint32_t cap, uint32_t pair_bits)
 {
+    (void)pair_bits;   // the radix passes' workspace does not depend on the grouping
     const size_t n_slots = (size_t)(n_pairs + kBlock - 1) / kBlock * kBlock + (size_t)kBlock * n_objs;
     return al256((size_t)n_rays * 8) + al256((size_t)n_pairs * sizeof(PairRes)) + al256((size_t)n_pairs * 4) +
-           al256(n_slots * 4) + al256(n_slots / kBlock * 4) + al256((size_t)n_objs * pair_bins(pair_bits) * 4) +
-           2 * al256((size_t)n_objs * 4) + list_ws_bytes(n_slots, cap) + kQueueBytes;
+           al256(n_slots * 4) + al256(n_slots / kBlock * 4) + 4 * al256((size_t)n_pairs * 4) +
+           al256(radix_hist_words(n_pairs) * 4) + al256((size_t)(n_objs + 1) * 4) + al256((size_t)n_objs * 4) +
+           list_ws_bytes(n_slots, cap) + kQueueBytes;
 }
 
 // The walk kernel, then the query kernel, over `ntiles` tiles.  With k > 1 tile
@@ -856,7 +858,7 @@ lsnif_status pairs_setup(lsnif_ctx *ctx, PairsSetup &ps)
     }
     lsnif_status st = upload_table(ctx, ps.n_objs);
     if (st) return st;
-    if ((uint64_t)ps.n_objs * pair_bins(ps.pair_bits) >= 0xffffffffull)   // pair keys are 32-bit, ~0 means dropped
+    if ((uint64_t)ps.n_objs * pair_bins(ps.pair_bits) >= 0xffffffffull)   // 32-bit pair keys; n_objs bins: dropped
         return fail(LSNIF_E_INVALID, "object ids up to %u need pair_bits below %u", ps.n_objs - 1, ps.pair_bits);
     return LSNIF_OK;
 }
@@ -896,12 +898,18 @@ lsnif_status enqueue_pairs(lsnif_ctx *ctx, const PairsSetup &ps, const lsnif_ray
     w += al256((size_t)n_slots * 4);
     P.tile_obj = reinterpret_cast<int32_t *>(w);
     w += al256((size_t)n_tiles * 4);
+    for (int q = 0; q < 2; ++q) {
+        P.rk[q] = reinterpret_cast<uint32_t *>(w);
+        w += al256((size_t)n_pairs * 4);
+        P.rv[q] = reinterpret_cast<uint32_t *>(w);
+        w += al256((size_t)n_pairs * 4);
+    }
     P.hist = reinterpret_cast<uint32_t *>(w);
+    w += al256(radix_hist_words(n_pairs) * 4);
     P.bits = ps.pair_bits;
     P.bins = pair_bins(ps.pair_bits);
-    w += al256((size_t)n_objs * P.bins * 4);
-    P.obj_total = reinterpret_cast<uint32_t *>(w);
-    w += al256((size_t)n_objs * 4);
+    P.obj_start = reinterpret_cast<uint32_t *>(w);
+    w += al256((size_t)(n_objs + 1) * 4);
     P.obj_off = reinterpret_cast<uint32_t *>(w);
     w += al256((size_t)n_objs * 4);
     uint8_t *nvox = reinterpret_cast<uint8_t *>(w);

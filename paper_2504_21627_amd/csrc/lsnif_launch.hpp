@@ -25,11 +25,13 @@ __host__ __device__ inline uint32_t radix_passes(uint32_t bits)
     const uint32_t used = 32u - (uint32_t)__builtin_clz(top | 1u);
     return (used + 7u) / 8u;
 }
-__host__ __device__ inline size_t radix_ws_words(uint32_t n, uint32_t bits)
+// Digit counters of a pass over n items, then the partial sums of their scan.
+__host__ __device__ inline size_t radix_hist_words(uint32_t n)
 {
     const size_t counters = (size_t)256u * ((n + kRadixTile - 1u) / kRadixTile);
-    return 4u * (size_t)n + counters + (counters + 1023u) / 1024u;
+    return counters + (counters + 1023u) / 1024u;
 }
+__host__ __device__ inline size_t radix_ws_words(uint32_t n) { return 4u * (size_t)n + radix_hist_words(n); }
 struct Geom;
 struct QueryArgs;
 struct DebugArgs;
@@ -79,7 +81,13 @@ hipError_t launch_merge_unpack(const MergeArgs &M, hipStream_t s);
 struct PairPlan;
 hipError_t launch_pairs_prepare(const PairPlan &P, hipStream_t s);
 hipError_t launch_pairs_payload(const PairPlan &P, hipStream_t s);
-// Sorts rays 0..n-1 by coherence key in `ws` (radix_ws_words(n, g.sort_bits) words);
+// One pass of the radix sort (8-bit digit at `shift`, stable) over n items of (sk, sv)
+// into (dk, dv): sv NULL means the values are the positions 0..n-1, dk NULL that the
+// keys are not kept.  hist holds 256 counters per kRadixTile items and then the
+// partial sums of their scan; counted: they already hold this pass's per-block counts.
+hipError_t launch_radix_pass(const uint32_t *sk, const uint32_t *sv, uint32_t *dk, uint32_t *dv, uint32_t n,
+                             uint32_t *hist, uint32_t shift, bool counted, hipStream_t s);
+// Sorts rays 0..n-1 by coherence key in `ws` (radix_ws_words(n) words);
 // *order receives the sorted ray indices (inside ws).
 hipError_t launch_coherence_sort(const Geom &g, const float4 *rays, uint32_t n, uint32_t *ws, uint32_t **order,
                                  hipStream_t s);

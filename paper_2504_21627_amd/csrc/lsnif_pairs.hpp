@@ -27,12 +27,14 @@ struct PairPlan {
     // workspace
     unsigned long long *minkey;      // [n_rays]
     PairRes *res;                    // [n_pairs]
-    uint32_t *keys;                  // [n_pairs] bin of each pair, or 0xffffffff if dropped
+    uint32_t *keys;                  // [n_pairs] key of each pair: object bins + bin, n_objs bins if dropped
     uint32_t *slot_pair;             // [n_slots]
     int32_t *tile_obj;               // [n_tiles]
-    uint32_t *hist;                  // [n_objs * bins]
-    uint32_t bins, bits;             // pair_bins(bits) counters per object; bits = the finest pair_bits
-    uint32_t *obj_total, *obj_off;   // [n_objs]
+    uint32_t *rk[2], *rv[2];         // [n_pairs] each: the radix passes' keys and pair indices
+    uint32_t *hist;                  // radix_hist_words(n_pairs): digit counters, then their scan partials
+    uint32_t bins, bits;             // pair_bins(bits) keys per object; bits = the finest pair_bits
+    uint32_t *obj_start;             // [n_objs + 1] first sorted position of each object; [n_objs]: live pairs
+    uint32_t *obj_off;               // [n_objs] first slot of each object's tiles
     uint32_t n_slots, n_tiles;       // n_tiles * 256 == n_slots
 };
 
