@@ -160,9 +160,9 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t *sk, co
     }
 }
 
-// Exclusive scan of the kSortBins counters in two passes: block b first sums
-// counters [1024 b, 1024 b + 1024), then rescans them with the sum of the
-// blocks before it as the carry-in.
+// Exclusive scan of n counters in two passes: block b first sums counters
+// [1024 b, 1024 b + 1024), then rescans them with the sum of the blocks before
+// it as the carry-in.
 constexpr uint32_t kScanChunk = 1024;
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *tmp, uint32_t &total)

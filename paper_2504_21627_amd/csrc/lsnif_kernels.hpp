@@ -365,65 +365,6 @@ __device__ __forceinline__ float act_f(float x, int act, float slope)
     return x > 0.0f ? x : (act == LSNIF_LEAKY_RELU ? x * slope : 0.0f);
 }
 
-// Lanes of a wave that share a key are served by one atomic on that key's
-// counter (issued by the lowest such lane); returns the counter's old value
-// plus this lane's rank among the lanes with its key, so equal keys of one
-// wave never contend for the same address.  The groups are found first (a
-// uniform loop over the distinct keys, the key broadcast by readlane), then
-// every group's leader issues its atomic in one instruction, so the atomics
-// of one wave are in flight together rather than one after another.  A wave
-// of scattered keys gains nothing from grouping: after kAggMax groups the
-// remaining lanes add for themselves.
-constexpr int kAggMax = 6;
-// The two halves of wave_aggregated_add, so that a thread can have the atomics
-// of several keys in flight before it waits for any: issue groups the lanes and
-// sends each group's atomic, rank turns the returned counter into the lane's
-// value.
-struct AggAdd {
-    uint32_t old, leader;
-    uint64_t mine;
-};
-
-__device__ __forceinline__ AggAdd wave_aggregated_issue(uint32_t *ctr, uint32_t key, bool active)
-{
-    const uint32_t lane = threadIdx.x & 63u;
-    uint64_t todo = __ballot(active);
-    uint32_t leader = lane, n = 0;
-    uint64_t mine = 0;
-    for (int it = 0; it < kAggMax && todo; ++it) {
-        const uint32_t l = (uint32_t)__builtin_ctzll(todo);
-        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, (int)l);
-        const uint64_t same = __ballot(active && key == k);
-        if (active && key == k) {
-            leader = l;
-            mine = same;
-        }
-        if (lane == l) n = (uint32_t)__builtin_popcountll(same);
-        todo &= ~same;
-    }
-    if ((todo >> lane) & 1ull) {   // not grouped: a group of its own
-        n = 1;
-        leader = lane;
-        mine = 1ull << lane;
-    }
-    uint32_t old = 0;
-    if (n) old = atomicAdd(&ctr[key], n);
-    return AggAdd{old, leader, mine};
-}
-
-__device__ __forceinline__ uint32_t wave_aggregated_rank(const AggAdd &a)
-{
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t base = __shfl(a.old, a.leader, 64);
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    return base + (uint32_t)__builtin_popcountll(a.mine & below);
-}
-
-__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t *ctr, uint32_t key, bool active)
-{
-    return wave_aggregated_rank(wave_aggregated_issue(ctr, key, active));
-}
-
 // Largest non-negative value of the wave folded into *dst (float bits of
 // non-negative numbers order like unsigned integers).
 __device__ __forceinline__ void fold_max(float *dst, float v)

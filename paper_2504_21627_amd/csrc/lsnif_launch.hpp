@@ -3,16 +3,12 @@
 #include <hip/hip_runtime.h>
 
 namespace lsnif {
-constexpr uint32_t kSortBins = (1u << 21) + 1;   // capacity: 8 octants x 64^3 (or 128^3) cells, plus one bin for misses
-constexpr uint32_t kSortScanBlocks = (kSortBins + 1023) / 1024;   // partial sums of the two-pass scan
-// Bins of a coherence sort with 2^bits cells per axis: 8 octants x cells^3 (bits <= 6) or
-// cells^3 alone (bits 7), then one for misses; and the partial sums its two-pass scan keeps
-// (one per 1024 bins).
+// Keys of a coherence sort with 2^bits cells per axis: 8 octants x cells^3 (bits <= 6) or
+// cells^3 alone (bits 7), then one for misses.
 __host__ __device__ inline uint32_t sort_bins(uint32_t bits)
 {
     return bits >= 7u ? (1u << 21) + 1u : (8u << (3u * bits)) + 1u;
 }
-__host__ __device__ inline uint32_t sort_scan_blocks(uint32_t bits) { return (sort_bins(bits) + 1023u) / 1024u; }
 // The coherence keys are put in order by a least-significant-digit radix sort with 8-bit
 // digits, each block of the passes taking kRadixTile consecutive rays: passes enough
 // for the largest key (sort_bins(bits) - 1), and the 32-bit words of its workspace for n
