@@ -412,6 +412,12 @@ def bench_c1(L, reps=200):
     try:
         oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp32", "fp32"))
         wall, lat, _, _, kern_ms = time_path(L, ctx, oid, rays, out, reps, 10)
+        # the same query captured once and replayed: the launches leave the host as one graph
+        g = L.lsnif_graph_query(ctx, oid, rays, out)
+        try:
+            wall_g, lat_g, _, _, _ = time_calls(L, ctx, lambda st: L.lsnif_graph_launch(g, st), reps, 10)
+        finally:
+            L.lsnif_graph_destroy(g)
     finally:
         L.lsnif_destroy(ctx)
     oracle.query(obj, rays_np[:256])
@@ -425,6 +431,8 @@ def bench_c1(L, reps=200):
             "rays": n, "launches": reps, "value": n * reps / wall / 1e6, "unit": "Mrays/s",
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "kernel_ms": kern_ms,
+            "graph": {"value": n * reps / wall_g / 1e6, "unit": "Mrays/s", "p50_ms": float(np.percentile(lat_g, 50)),
+                      "p99_ms": float(np.percentile(lat_g, 99))},
             "roofline": "not meaningful: 4,096 waves of a few microseconds each (latency-bound)",
             "cpu_baseline": {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(),
                              "kind": "oracle", "sample": "all 4,096 rays, mean of 5 runs"}}
