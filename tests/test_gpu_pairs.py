@@ -140,6 +140,35 @@ def test_c4_full_size_sampled(L):
     assert st["ok"], st
 
 
+def test_pairs_objects_without_pairs(L):
+    """Objects with no pairs between objects with pairs, and dropped pairs, in shuffled
+    order: the sorted keys' object bounds leave the empty objects no tiles and every other
+    object its own, so the answers are the oracle's."""
+    rng = np.random.default_rng(23)
+    objs = [W.configs.c1_object(s) for s in range(4)]
+    insts = [(o, m) for o, m in random_instances(rng, 8, 4, spread=1.0) if o in (0, 3)]
+    rays = W.sphere_to_box_rays(np.random.default_rng(29), 2500, radius=3.5, half_box=1.5)
+    n = len(rays)
+    pr = np.repeat(np.arange(n), len(insts)).astype(np.uint32)
+    pi = np.tile(np.arange(len(insts)), n).astype(np.uint32)
+    perm = rng.permutation(len(pr))
+    pr, pi = pr[perm], pi[perm]
+    bad = np.array([len(insts) + 3] * 50, np.uint32)     # instances that do not exist: dropped
+    pr_all = np.concatenate([pr, rng.integers(0, n, 50).astype(np.uint32)])
+    pi_all = np.concatenate([pi, bad])
+    ctx = L.lsnif_create(0)
+    try:
+        ids = [L.lsnif_build(ctx, L.ObjectDesc(o, "fp16", "fp16")) for o in objs]
+        g = run_pairs(L, ctx, ids, insts, rays, pr_all, pi_all)
+    finally:
+        L.lsnif_destroy(ctx)
+    u, t_rel, n_ang, vis = BARS["fp16"]
+    st = compare_pairs(g, pair_reference(oracle, objs, insts, rays, pr, pi, u), t_rel, n_ang, vis)
+    print(f"pairs with empty objects: {st}", flush=True)
+    assert st["hits_compared"] > 100
+    assert st["ok"], st
+
+
 def test_pairs_edge_cases(L):
     """No pairs, pairs naming missing rays/instances/objects, and mixed kernel classes."""
     import torch

@@ -65,6 +65,34 @@ def test_single_object_tunings_agree(L):
         L.lsnif_destroy(ctx)
 
 
+@pytest.mark.parametrize("n", [8192, 8193, 10241, 65535])
+def test_radix_sorted_batches_ragged(L, n):
+    """Batches just above the sort threshold and across partial 2,048-ray blocks of the
+    radix passes (one, two and three passes: sort_bits 1, 4, 7) answer every ray as the
+    unsorted batch does, bit for bit."""
+    import torch
+    obj = W.configs.c2_object()
+    rays_np = W.configs.subsample(W.configs.c2_rays(), n, seed=19)
+    ctx = L.lsnif_create(0)
+    try:
+        rays = torch.from_numpy(rays_np).cuda()
+        oid = L.lsnif_build(ctx, L.ObjectDesc(obj, "fp16", "fp16"))
+        ref = None
+        for sb in (0, 1, 4, 7):
+            L.lsnif_set_tuning(ctx, oid, sb, 4, 0)
+            out = torch.full((n, 6), float("nan"), dtype=torch.float32, device="cuda")
+            L.lsnif_query(ctx, oid, rays, out)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = bits(out)
+                assert (ref[:, 0] == 1).sum() > n // 10
+            else:
+                assert np.array_equal(bits(out), ref), (n, sb)
+        print(f"{n} rays: sorted in 1, 2 and 3 passes as unsorted", flush=True)
+    finally:
+        L.lsnif_destroy(ctx)
+
+
 def test_pair_tunings_agree(L):
     import torch
     d = W.configs.c4(n_objects=6, total=6 * 200000, scale=0.1)
