@@ -11,8 +11,9 @@
 // keys) in LDS, scans the counters digit-major, which gives every (digit,
 // block) its output range, then ranks each block's rays stably (a wave
 // matches equal digits with one ballot per digit bit and keeps running counts
-// per digit in LDS) and writes them there.  No global atomics: the counting
-// sort this replaces spent most of its time in one returning atomic per ray.
+// per digit in LDS) and writes them there.  No global atomics: a counting
+// sort's histogram and scatter take one device-wide atomic per ray, and those
+// atomics, not the bytes moved, set its pace.
 // Every ray's result is independent of the order the rays are processed in.
 #include <map>
 #include <mutex>
